@@ -1,0 +1,160 @@
+"""Benchmark: nDGP multigrid solve at 512^3 on one MI355X.
+
+One step = CIC density of 256^3 Zel'dovich-displaced particles on the 512^3
+mesh (L = 512 Mpc/h) followed by the nDGP (H0 r_c = 1, a = 1) FAS V(1,1)
+solve from phi = 0 to a mean-projected residual <= 1e-8, all in FP64.
+Particles are resident on the GPU before the timed region.
+
+Prints one JSON line: value = finest-level cell updates per second over the
+whole step (n^3 * (nu_pre + nu_post) * cycles / step time), the dominant
+kernel's roofline (finest colour pass, timed with HIP events on the stream
+the solver launches on) and the FP64 CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N_MESH, N_PART, BOX, SEED = 512, 256, 512.0, 6
+H0RC, A, OMEGA_M, TOL = 1.0, 1.0, 0.3089, 1e-8
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes of one finest colour pass per mesh cell (FP64): read both
+# colour halves (8 B), the colour's delta (4 B), write the colour (4 B)
+PASS_BYTES_PER_CELL = 16
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pass_dgp_512_traffic.json")
+KERNEL_SOURCES = ["paper_2110_00566_amd/csrc/mg_device.h", "paper_2110_00566_amd/csrc/mg_kernels.h"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per pass launch from the committed rocprofv3 counter runs,
+    if they were taken on the current kernel source."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(pos_np):
+    """FP64 oracle on the host: CIC + 3 V(1,1) cycles at 512^3 (bounded sample)."""
+    import oracle
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    _, delta = oracle.cic_density(pos_np, N_MESH)
+    r = oracle.solve(oracle.dgp_model(A, OMEGA_M, H0RC), delta, tol=0.0, max_cycles=3)
+    dt = time.perf_counter() - t0
+    updates = N_MESH ** 3 * 2 * r.cycles
+    return {"value": updates / dt, "unit": "cell-updates/s",
+            "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+            "kind": "oracle",
+            "sample": "CIC of the 256^3 particles + 3 FAS V(1,1) cycles at 512^3 (tol=0), "
+                      "%.1f s" % dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the solver runs on a single MI355X "
+              "(multi-GPU sharding is not built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import inputs
+    import paper_2110_00566_amd as mg
+
+    dev = torch.device("cuda:0")
+    pos_np = inputs.za_particles(N_PART, N_MESH, SEED)
+    pos = torch.from_numpy(pos_np).to(dev)
+    L = mg.lib()
+    ws_pm = torch.empty(L.mg_pm_workspace_bytes(N_MESH), dtype=torch.uint8, device=dev)
+    ws = mg.workspace(N_MESH, mg.MODEL_DGP, False, dev)
+    delta = torch.empty((N_MESH,) * 3, dtype=torch.float64, device=dev)
+    phi = torch.empty_like(delta)
+    par = mg.dgp_params(A, OMEGA_M, H0RC)
+    opts = mg.make_opts(N_MESH, tol=TOL, max_cycles=60, profile=True)
+    import ctypes as C
+
+    def step():
+        stream = mg._stream()
+        mg._raise(L.mg_cic_delta(N_MESH, N_PART, mg._ptr(pos), mg._ptr(delta), mg._ptr(ws_pm),
+                                 ws_pm.numel(), stream))
+        phi.zero_()
+        st = mg.Stats()
+        mg._raise(L.mg_solve_dgp(C.byref(opts), C.byref(par), mg._ptr(delta), mg._ptr(phi),
+                                 mg._ptr(ws), ws.numel(), stream, C.byref(st)))
+        return st
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        stats.append(step())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+
+    cycles = [s.cycles for s in stats]
+    assert all(s.status == 0 and s.eps <= TOL for s in stats), [s.status for s in stats]
+    updates = sum(N_MESH ** 3 * 2 * c for c in cycles)
+    ms_step = 1e3 * dt / args.steps
+    solve_ms = 1e3 * float(np.mean([s.seconds for s in stats]))
+    pass_ms = float(np.mean([s.pass_ms_avg for s in stats]))
+    achieved = PASS_BYTES_PER_CELL * N_MESH ** 3 / (pass_ms * 1e-3) / 1e9
+    traffic = measured_traffic()
+    out = {
+        "metric": "cell-updates/s and time-to-residual 1e-8 per V-cycle at 512^3; % HBM peak",
+        "value": updates / dt,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "nDGP FAS V(1,1) solve, 512^3 mesh, CIC of 256^3 Zel'dovich "
+                               "particles, L=512 Mpc/h, H0rc=1, a=1, phi0=0, tol=1e-8",
+                   "n_mesh": N_MESH, "n_part": N_PART, "box_mpch": BOX, "h0rc": H0RC,
+                   "tol": TOL, "precision": "fp64"},
+        "cycles": int(round(float(np.mean(cycles)))),
+        "time_to_tol_ms": solve_ms,
+        "ms_per_vcycle": solve_ms / float(np.mean(cycles)),
+        "roofline": {"bound": "hbm", "kernel": "k_pass<OP_DGP> (finest colour pass)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "pass_ms_avg": pass_ms,
+                     "algorithmic_bytes_per_launch": PASS_BYTES_PER_CELL * N_MESH ** 3},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(pos_np)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,191 @@
+/*
+ * mgglam.h -- C ABI of the MI355X (gfx950) multigrid solver for the scalar
+ * fields of derivative-coupling modified gravity, after Hernandez-Aguayo et
+ * al., "Fast full N-body simulations of generic modified gravity: derivative
+ * coupling models" (arXiv:2110.00566).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Code units of Sec. 3.1.1: the finest mesh has cell size h = 1 and n
+ *    cells per side; n is a power of two, 8 <= n <= 2048.
+ *  - Mesh arrays are DEVICE pointers to contiguous C-order arrays
+ *    a[z][y][x] (x fastest) of n^3 elements, periodic in every axis.
+ *    Particle arrays are DEVICE pointers to [n_part^3][3] FP32 (x, y, z).
+ *  - The caller owns every array and the workspace; the library never
+ *    allocates, frees or keeps them.  Work is enqueued on the caller's
+ *    stream.  Solver calls return after that stream has reached the end of
+ *    the solve (the stopping test reads one residual per V-cycle).
+ *  - Arguments are validated before the first GPU call; invalid ones give
+ *    MG_ERR_ARG and mg_last_error() says which.  Positive status codes mean
+ *    the outputs are valid (see the stats); negative codes leave outputs
+ *    unspecified.
+ *  - Calls that share a workspace must not overlap in time.
+ */
+#ifndef MGGLAM_H
+#define MGGLAM_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MG_OK = 0,
+    MG_NOT_CONVERGED = 1,   /* cycle cap reached; phi valid, stats.eps > tol */
+    MG_WARN_CLAMPED = 2,    /* converged, but a negative nDGP discriminant was clamped */
+    MG_ERR_ARG = -1,
+    MG_ERR_HIP = -2,
+    MG_ERR_NONFINITE = -3,  /* residual became NaN/Inf (e.g. NaN in delta) */
+    MG_ERR_DIVERGED = -4,   /* residual grew 1e3x above its minimum */
+    MG_ERR_WORKSPACE = -5   /* workspace pointer null or smaller than required */
+} mg_status;
+
+typedef enum { MG_FP64 = 0, MG_MIXED = 1 } mg_precision;
+typedef enum { MG_MODEL_DGP = 0, MG_MODEL_KMOUFLAGE = 1, MG_MODEL_POISSON = 2 } mg_model;
+
+/* Solver options.  Sec. 3.2.1: FAS V-cycle with nonlinear red-black
+ * Gauss-Seidel smoothing, 8-cell mean restriction, 27/9/3/1 prolongation,
+ * coarsest level 4^3. */
+typedef struct {
+    int n;            /* cells per side of the finest mesh (power of two, 8..2048) */
+    int max_cycles;   /* cap on V-cycles (0..100000); default 50 */
+    double tol;       /* stop when the RMS of the mean-projected finest residual
+                         is <= tol (code units); 0 runs exactly max_cycles */
+    int nu_pre;       /* smoothing sweeps before restriction (one sweep = colour 0
+                         pass then colour 1 pass); default 1 */
+    int nu_post;      /* sweeps after the coarse-grid correction; default 1 */
+    int nu_coarse;    /* sweeps on the 4^3 level; default 32 */
+    int precision;    /* mg_precision; only MG_FP64 in this version */
+    int cycle;        /* 0 = V-cycle (the only schedule in this version) */
+    int profile;      /* 1: time every finest-level colour pass with HIP events
+                         on the caller's stream (stats.pass_ms_avg) */
+} mg_opts;
+
+#define MG_HIST 64
+typedef struct {
+    int cycles;                 /* V-cycles run */
+    int status;                 /* same as the return value */
+    double eps0;                /* residual of the initial guess */
+    double eps;                 /* residual of the returned field */
+    double eps_hist[MG_HIST];   /* residual after the pre-smoothing of cycle c */
+    double lambda;              /* Lagrange multiplier: L(phi) + lambda = 0 */
+    long long cell_updates;     /* n^3 * (nu_pre + nu_post) * cycles */
+    long long n_clamped;        /* clamped discriminants (nDGP) */
+    double seconds;             /* host wall clock of the call */
+    double pass_ms_avg;         /* mean finest colour-pass duration (profile=1) */
+    int pass_count;             /* number of timed finest colour passes */
+} mg_stats;
+
+/* nDGP background (eq:beta_dgp with the LCDM expansion eq:H_lcdm, flat,
+ * Omega_L = 1 - Omega_m); h0rc = H0 r_c / c = R_c. */
+typedef struct { double a, omega_m, h0rc; } mg_dgp_params;
+
+/* Kmouflage, K(X) = -1 + X + K0 X^n, A = exp(beta phi) (eq:kmf_model_K_function);
+ * c~ = (n / box_mpch) * 2997.92458; gamma = n_k K0 (1/(2 a^2 lambda^2))^(n_k-1);
+ * background part of Sigma_1 uses (phibar'/H0)^2 = dphibar_dtau_over_h0^2. */
+typedef struct {
+    int n_k;
+    double k0, beta, lambda, a, omega_m, box_mpch, phibar, dphibar_dtau_over_h0;
+} mg_kmo_params;
+
+/* Linear Poisson model lap(phi) = s * delta (used for the Newtonian
+ * potential, eq:GR_poisson_codeunit with s = 1.5 Omega_m / a). */
+typedef struct { double s; } mg_poisson_params;
+
+/* Bytes of device workspace needed by a solve on an n^3 mesh.  model is an
+ * mg_model; adjoint != 0 sizes mg_solve_adjoint.  Returns 0 for invalid n. */
+size_t mg_workspace_bytes(int n, int precision, int model, int adjoint);
+
+/* Solve the nDGP scalar-field equation eq:dgp_eom_code in the form of
+ * eq:DGP, i.e. L(phi) = lap(phi) - (3/4)[-alpha + sign(alpha) sqrt(alpha^2 +
+ * 8 Sigma / 3)] = 0 with Sigma from the discrete operator of Sec. 3.2.3.
+ * delta: FP64 density contrast (n^3).  phi: in = initial guess, out = the
+ * zero-mean solution.  The periodic discrete problem is solved in bordered
+ * form L(phi) + lambda = 0 (lambda in stats). */
+mg_status mg_solve_dgp(const mg_opts *opts, const mg_dgp_params *par, const double *delta,
+                       double *phi, void *ws, size_t ws_bytes, hipStream_t stream,
+                       mg_stats *stats);
+
+/* Solve the Kmouflage equation in the split form eq:kmf_eqn_codeunit_final:
+ * c~ lap(phi) = (3 beta A Omega_m delta / a + Sigma_2) / Sigma_1.
+ * Same argument conventions as mg_solve_dgp. */
+mg_status mg_solve_kmouflage(const mg_opts *opts, const mg_kmo_params *par,
+                             const double *delta, double *phi, void *ws, size_t ws_bytes,
+                             hipStream_t stream, mg_stats *stats);
+
+/* Solve the linear periodic Poisson equation lap(phi) = s (delta - mean
+ * delta) with the same multigrid (zero-mean phi).  Equals the FFT solution
+ * with the discrete Green's function of the 7-point Laplacian. */
+mg_status mg_solve_poisson(const mg_opts *opts, const mg_poisson_params *par,
+                           const double *delta, double *phi, void *ws, size_t ws_bytes,
+                           hipStream_t stream, mg_stats *stats);
+
+/* Gradient of loss = sum(phi * w) with respect to delta, phi being the
+ * converged zero-mean solution of model (mg_model) with parameters params
+ * (mg_dgp_params* or mg_kmo_params*).  Solves the bordered adjoint
+ * J^T mu + nu 1 = w, sum(mu) = 0 (J = dL/dphi at phi) by multigrid with the
+ * coarse-level linearisation points recomputed by restriction, then
+ * grad_delta = -(dL/ddelta) mu.  opts->tol applies to the RMS of the adjoint
+ * residual.  mu: in = warm start (zeros if unknown), out = adjoint field. */
+mg_status mg_solve_adjoint(const mg_opts *opts, int model, const void *params,
+                           const double *delta, const double *phi, const double *w,
+                           double *grad_delta, double *mu, void *ws, size_t ws_bytes,
+                           hipStream_t stream, mg_stats *stats);
+
+/* One nDGP particle-mesh step (Sec. 3.1): CIC density from the particles,
+ * Newtonian potential (eq:GR_poisson_codeunit), scalar field (warm start from
+ * phi), total potential Phi_N + phi/2 (eq:poisson_nDGP), 3-point force
+ * interpolated with CIC, kick dp/da = -(H0/adot) grad Phi at a, drift
+ * dx/da = (H0/adot) p / a^2 at a + da/2.  pos in [0, n_mesh) is wrapped. */
+typedef struct {
+    int n_mesh, n_part;
+    double omega_m, h0rc, a, da;
+    mg_opts mg;   /* options of both field solves; mg.n must equal n_mesh */
+} mg_pm_params;
+size_t mg_pm_workspace_bytes(int n_mesh);
+mg_status mg_pm_step(const mg_pm_params *par, float *pos, float *mom, double *phi,
+                     double *phi_newton, double *delta_out, void *ws, size_t ws_bytes,
+                     hipStream_t stream, mg_stats *stats);
+
+/* CIC density contrast of n_part^3 unit-mass particles on an n_mesh^3
+ * mesh (cell i has centre i + 1/2): delta = rho / rho_bar - 1.  Deterministic:
+ * weights accumulate as 64-bit fixed point (2^-32 per unit mass).  ws needs
+ * mg_pm_workspace_bytes(n_mesh) bytes. */
+mg_status mg_cic_delta(int n_mesh, int n_part, const float *pos, double *delta, void *ws,
+                       size_t ws_bytes, hipStream_t stream);
+
+/* ---- single operations of the solve, for parity tests ------------------
+ * Natural-layout device arrays of n^3 FP64; level spacing h; model/params
+ * as in mg_solve_adjoint; f: device array or NULL for the scalar fs.
+ * ws needs mg_op_workspace_bytes(n). */
+size_t mg_op_workspace_bytes(int n);
+/* out = L_h(phi) - f */
+mg_status mg_op_residual(int model, const void *params, int n, double h, const double *phi,
+                         const double *delta, const double *f, double fs, double *out,
+                         void *ws, size_t ws_bytes, hipStream_t stream);
+/* one colour pass (colour 0: (i+j+k) even) from phi_in to phi_out */
+mg_status mg_op_colour_pass(int model, const void *params, int n, double h, int colour,
+                            const double *phi_in, const double *delta, const double *f,
+                            double fs, double *phi_out, void *ws, size_t ws_bytes,
+                            hipStream_t stream);
+/* coarse = 8-cell mean of fine (n = fine cells per side) */
+mg_status mg_op_restrict(int n, const double *fine, double *coarse, void *ws, size_t ws_bytes,
+                         hipStream_t stream);
+/* fine += P(uc - rc) (n = fine cells per side) */
+mg_status mg_op_prolong_add(int n, double *fine, const double *uc, const double *rc, void *ws,
+                            size_t ws_bytes, hipStream_t stream);
+/* out = J^T v, J = dL/dphi at (phi, delta) */
+mg_status mg_op_jt_apply(int model, const void *params, int n, double h, const double *phi,
+                         const double *delta, const double *v, double *out, void *ws,
+                         size_t ws_bytes, hipStream_t stream);
+
+const char *mg_status_string(mg_status s);
+/* Detail of the last error on the calling thread ("" if none). */
+const char *mg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGGLAM_H */

@@ -1,0 +1,354 @@
+"""MI355X (gfx950) multigrid solver for derivative-coupling modified gravity.
+
+A thin ctypes binding over ``libmgglam.so`` (C ABI in ``include/mgglam.h``).
+Every step of the solve runs in the library's HIP kernels; this module only
+marshals arguments.  PyTorch provides device memory (CUDA/HIP tensors) and
+the current stream.  The library must be built (``python -m
+paper_2110_00566_amd.build``); importing works without it, but every call
+raises if it is missing.
+
+Main entry points (tensors are float64, C order [z][y][x], on the GPU):
+
+* ``solve_dgp(delta, phi0=None, a=1, omega_m=0.3089, h0rc=1, ...)``
+* ``solve_kmouflage(delta, phi0=None, n_k=3, k0=1, beta=0.1, ...)``
+* ``solve_poisson(delta, s, phi0=None, ...)``
+* ``solve_adjoint(model, params, delta, phi, w, mu0=None, ...)``
+* ``DGPSolve.apply(delta, h0rc, a, omega_m, tol)`` -- autograd wrapper
+* ``cic_delta(pos, n_mesh)`` and ``pm_step(pos, mom, phi, ...)``
+* ``op_*`` single operations of the solve (for parity tests).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmgglam.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "mgglam.h")
+
+MG_OK, MG_NOT_CONVERGED, MG_WARN_CLAMPED = 0, 1, 2
+MG_ERR_ARG, MG_ERR_HIP, MG_ERR_NONFINITE, MG_ERR_DIVERGED, MG_ERR_WORKSPACE = -1, -2, -3, -4, -5
+MODEL_DGP, MODEL_KMOUFLAGE, MODEL_POISSON = 0, 1, 2
+OMEGA_M = 0.3089
+HIST = 64
+
+
+class MGError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(msg)
+        self.status = status
+
+
+class Opts(C.Structure):
+    _fields_ = [("n", C.c_int), ("max_cycles", C.c_int), ("tol", C.c_double),
+                ("nu_pre", C.c_int), ("nu_post", C.c_int), ("nu_coarse", C.c_int),
+                ("precision", C.c_int), ("cycle", C.c_int), ("profile", C.c_int)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("cycles", C.c_int), ("status", C.c_int), ("eps0", C.c_double),
+                ("eps", C.c_double), ("eps_hist", C.c_double * HIST), ("lambda_", C.c_double),
+                ("cell_updates", C.c_longlong), ("n_clamped", C.c_longlong),
+                ("seconds", C.c_double), ("pass_ms_avg", C.c_double), ("pass_count", C.c_int)]
+
+    def as_dict(self):
+        k = min(self.cycles, HIST)
+        return dict(cycles=self.cycles, status=self.status, eps0=self.eps0, eps=self.eps,
+                    eps_hist=list(self.eps_hist[:k]), lam=self.lambda_,
+                    cell_updates=self.cell_updates, n_clamped=self.n_clamped,
+                    seconds=self.seconds, pass_ms_avg=self.pass_ms_avg,
+                    pass_count=self.pass_count)
+
+
+class DgpParams(C.Structure):
+    _fields_ = [("a", C.c_double), ("omega_m", C.c_double), ("h0rc", C.c_double)]
+
+
+class KmoParams(C.Structure):
+    _fields_ = [("n_k", C.c_int), ("k0", C.c_double), ("beta", C.c_double),
+                ("lambda_", C.c_double), ("a", C.c_double), ("omega_m", C.c_double),
+                ("box_mpch", C.c_double), ("phibar", C.c_double),
+                ("dphibar_dtau_over_h0", C.c_double)]
+
+
+class PoissonParams(C.Structure):
+    _fields_ = [("s", C.c_double)]
+
+
+class PmParams(C.Structure):
+    _fields_ = [("n_mesh", C.c_int), ("n_part", C.c_int), ("omega_m", C.c_double),
+                ("h0rc", C.c_double), ("a", C.c_double), ("da", C.c_double), ("mg", Opts)]
+
+
+_lib = None
+_P = C.c_void_p
+
+
+def lib():
+    """Load libmgglam.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libmgglam.so is not built: run python -m paper_2110_00566_amd.build")
+        L = C.CDLL(LIB_PATH)
+        st = C.c_int
+        L.mg_workspace_bytes.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
+        L.mg_workspace_bytes.restype = C.c_size_t
+        L.mg_pm_workspace_bytes.argtypes = [C.c_int]
+        L.mg_pm_workspace_bytes.restype = C.c_size_t
+        L.mg_op_workspace_bytes.argtypes = [C.c_int]
+        L.mg_op_workspace_bytes.restype = C.c_size_t
+        for name, par in (("mg_solve_dgp", DgpParams), ("mg_solve_kmouflage", KmoParams),
+                          ("mg_solve_poisson", PoissonParams)):
+            f = getattr(L, name)
+            f.argtypes = [C.POINTER(Opts), C.POINTER(par), _P, _P, _P, C.c_size_t, _P,
+                          C.POINTER(Stats)]
+            f.restype = st
+        L.mg_solve_adjoint.argtypes = [C.POINTER(Opts), C.c_int, _P, _P, _P, _P, _P, _P, _P,
+                                       C.c_size_t, _P, C.POINTER(Stats)]
+        L.mg_solve_adjoint.restype = st
+        L.mg_pm_step.argtypes = [C.POINTER(PmParams), _P, _P, _P, _P, _P, _P, C.c_size_t, _P,
+                                 C.POINTER(Stats)]
+        L.mg_pm_step.restype = st
+        L.mg_cic_delta.argtypes = [C.c_int, C.c_int, _P, _P, _P, C.c_size_t, _P]
+        L.mg_cic_delta.restype = st
+        L.mg_op_residual.argtypes = [C.c_int, _P, C.c_int, C.c_double, _P, _P, _P, C.c_double,
+                                     _P, _P, C.c_size_t, _P]
+        L.mg_op_residual.restype = st
+        L.mg_op_colour_pass.argtypes = [C.c_int, _P, C.c_int, C.c_double, C.c_int, _P, _P, _P,
+                                        C.c_double, _P, _P, C.c_size_t, _P]
+        L.mg_op_colour_pass.restype = st
+        L.mg_op_restrict.argtypes = [C.c_int, _P, _P, _P, C.c_size_t, _P]
+        L.mg_op_restrict.restype = st
+        L.mg_op_prolong_add.argtypes = [C.c_int, _P, _P, _P, _P, C.c_size_t, _P]
+        L.mg_op_prolong_add.restype = st
+        L.mg_op_jt_apply.argtypes = [C.c_int, _P, C.c_int, C.c_double, _P, _P, _P, _P, _P,
+                                     C.c_size_t, _P]
+        L.mg_op_jt_apply.restype = st
+        L.mg_status_string.argtypes = [C.c_int]
+        L.mg_status_string.restype = C.c_char_p
+        L.mg_last_error.argtypes = []
+        L.mg_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/mgglam.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mg_[a-z_0-9]+)\s*\(", txt)))
+
+
+def _raise(rc: int):
+    L = lib()
+    if rc < 0:
+        raise MGError(rc, "%s: %s" % (L.mg_status_string(rc).decode(), L.mg_last_error().decode()))
+    return rc
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check_mesh(t, name, dtype=torch.float64):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a GPU tensor" % name)
+    if t.dtype != dtype or not t.is_contiguous() or t.dim() != 3 or len(set(t.shape)) != 1:
+        raise ValueError("%s must be a contiguous %s cube" % (name, dtype))
+    return t
+
+
+def workspace(n: int, model: int = MODEL_DGP, adjoint: bool = False, device=None):
+    nbytes = lib().mg_workspace_bytes(n, 0, model, int(adjoint))
+    if nbytes == 0:
+        raise ValueError("invalid mesh size %d" % n)
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def make_opts(n, tol=1e-8, max_cycles=50, nu_pre=1, nu_post=1, nu_coarse=32, profile=False):
+    return Opts(n, max_cycles, tol, nu_pre, nu_post, nu_coarse, 0, 0, int(profile))
+
+
+def dgp_params(a=1.0, omega_m=OMEGA_M, h0rc=1.0):
+    return DgpParams(a, omega_m, h0rc)
+
+
+def kmo_params(n_mesh, box_mpch, n_k=3, k0=1.0, beta=0.1, lam=None, a=1.0, omega_m=OMEGA_M,
+               phibar=0.0, dphibar_dtau_over_h0=0.0):
+    if lam is None:
+        lam = (3.0 * (1.0 - omega_m)) ** 0.5
+    return KmoParams(n_k, k0, beta, lam, a, omega_m, box_mpch, phibar, dphibar_dtau_over_h0)
+
+
+def _solve(fn, par, model, delta, phi0, ws, **kw):
+    _check_mesh(delta, "delta")
+    n = delta.shape[0]
+    phi = torch.zeros_like(delta) if phi0 is None else _check_mesh(phi0, "phi0").clone()
+    if ws is None:
+        ws = workspace(n, model, False, delta.device)
+    o = make_opts(n, **kw)
+    st = Stats()
+    rc = fn(C.byref(o), C.byref(par), _ptr(delta), _ptr(phi), _ptr(ws), ws.numel(), _stream(),
+            C.byref(st))
+    _raise(rc)
+    return phi, st.as_dict()
+
+
+def solve_dgp(delta, phi0=None, a=1.0, omega_m=OMEGA_M, h0rc=1.0, ws=None, **kw):
+    """nDGP field (eq:dgp_eom_code); returns (zero-mean phi, stats)."""
+    return _solve(lib().mg_solve_dgp, dgp_params(a, omega_m, h0rc), MODEL_DGP, delta, phi0, ws, **kw)
+
+
+def solve_kmouflage(delta, phi0=None, box_mpch=512.0, n_k=3, k0=1.0, beta=0.1, lam=None, a=1.0,
+                    omega_m=OMEGA_M, phibar=0.0, dphibar_dtau_over_h0=0.0, ws=None, **kw):
+    """Kmouflage field (eq:kmf_eqn_codeunit_final); returns (phi, stats)."""
+    par = kmo_params(delta.shape[0], box_mpch, n_k, k0, beta, lam, a, omega_m, phibar,
+                     dphibar_dtau_over_h0)
+    return _solve(lib().mg_solve_kmouflage, par, MODEL_KMOUFLAGE, delta, phi0, ws, **kw)
+
+
+def solve_poisson(delta, s, phi0=None, ws=None, **kw):
+    """lap(phi) = s (delta - mean delta) by the same multigrid."""
+    return _solve(lib().mg_solve_poisson, PoissonParams(s), MODEL_POISSON, delta, phi0, ws, **kw)
+
+
+def _params_for(model, par):
+    if isinstance(par, (DgpParams, KmoParams, PoissonParams)):
+        return par
+    raise TypeError("params must be DgpParams, KmoParams or PoissonParams")
+
+
+def solve_adjoint(model, par, delta, phi, w, mu0=None, ws=None, tol=1e-10, max_cycles=60, **kw):
+    """Gradient of sum(phi*w) w.r.t. delta at the converged phi.
+    Returns (grad_delta, mu, stats)."""
+    par = _params_for(model, par)
+    for t, nm in ((delta, "delta"), (phi, "phi"), (w, "w")):
+        _check_mesh(t, nm)
+    n = delta.shape[0]
+    mu = torch.zeros_like(delta) if mu0 is None else _check_mesh(mu0, "mu0").clone()
+    grad = torch.empty_like(delta)
+    if ws is None:
+        ws = workspace(n, model, True, delta.device)
+    o = make_opts(n, tol=tol, max_cycles=max_cycles, **kw)
+    st = Stats()
+    rc = lib().mg_solve_adjoint(C.byref(o), model, C.byref(par), _ptr(delta), _ptr(phi), _ptr(w),
+                                _ptr(grad), _ptr(mu), _ptr(ws), ws.numel(), _stream(),
+                                C.byref(st))
+    _raise(rc)
+    return grad, mu, st.as_dict()
+
+
+class DGPSolve(torch.autograd.Function):
+    """phi = solve_dgp(delta); backward through the adjoint multigrid."""
+
+    @staticmethod
+    def forward(ctx, delta, h0rc=1.0, a=1.0, omega_m=OMEGA_M, tol=1e-10):
+        phi, _ = solve_dgp(delta.detach(), a=a, omega_m=omega_m, h0rc=h0rc, tol=tol,
+                           max_cycles=100)
+        ctx.save_for_backward(delta.detach(), phi)
+        ctx.par = dgp_params(a, omega_m, h0rc)
+        ctx.tol = tol
+        return phi
+
+    @staticmethod
+    def backward(ctx, grad_phi):
+        delta, phi = ctx.saved_tensors
+        g, _, _ = solve_adjoint(MODEL_DGP, ctx.par, delta, phi, grad_phi.contiguous(),
+                                tol=ctx.tol, max_cycles=100)
+        return g, None, None, None, None
+
+
+def cic_delta(pos, n_mesh: int, ws=None):
+    """CIC density contrast (float64 n_mesh^3) of float32 [n_part^3, 3] positions."""
+    if not pos.is_cuda or pos.dtype != torch.float32 or pos.dim() != 2 or pos.shape[1] != 3:
+        raise ValueError("pos must be a GPU float32 [n_part^3, 3] tensor")
+    n_part = round(pos.shape[0] ** (1.0 / 3.0))
+    if n_part ** 3 != pos.shape[0]:
+        raise ValueError("number of particles must be a cube")
+    delta = torch.empty((n_mesh,) * 3, dtype=torch.float64, device=pos.device)
+    if ws is None:
+        ws = torch.empty(lib().mg_pm_workspace_bytes(n_mesh), dtype=torch.uint8, device=pos.device)
+    _raise(lib().mg_cic_delta(n_mesh, n_part, _ptr(pos.contiguous()), _ptr(delta), _ptr(ws),
+                              ws.numel(), _stream()))
+    return delta
+
+
+def pm_step(pos, mom, phi, phi_newton, n_mesh, a, da, h0rc=1.0, omega_m=OMEGA_M, ws=None, **kw):
+    """One nDGP PM step in place on pos/mom (float32 [n^3,3]), phi and phi_newton
+    (float64 warm starts, updated).  Returns (delta, stats)."""
+    n_part = round(pos.shape[0] ** (1.0 / 3.0))
+    delta = torch.empty((n_mesh,) * 3, dtype=torch.float64, device=pos.device)
+    if ws is None:
+        ws = torch.empty(lib().mg_pm_workspace_bytes(n_mesh), dtype=torch.uint8, device=pos.device)
+    par = PmParams(n_mesh, n_part, omega_m, h0rc, a, da, make_opts(n_mesh, **kw))
+    st = Stats()
+    _raise(lib().mg_pm_step(C.byref(par), _ptr(pos), _ptr(mom), _ptr(phi), _ptr(phi_newton),
+                            _ptr(delta), _ptr(ws), ws.numel(), _stream(), C.byref(st)))
+    return delta, st.as_dict()
+
+
+# ------------------------------------------------------------ single ops
+
+def _op_ws(n, device):
+    return torch.empty(lib().mg_op_workspace_bytes(n), dtype=torch.uint8, device=device)
+
+
+def _model_of(par):
+    return {DgpParams: MODEL_DGP, KmoParams: MODEL_KMOUFLAGE, PoissonParams: MODEL_POISSON}[type(par)]
+
+
+def op_residual(par, phi, delta, f=0.0, h=1.0):
+    n = phi.shape[0]
+    out = torch.empty_like(phi)
+    ws = _op_ws(n, phi.device)
+    fa = f if isinstance(f, torch.Tensor) else None
+    fs = 0.0 if fa is not None else float(f)
+    _raise(lib().mg_op_residual(_model_of(par), C.byref(par), n, h, _ptr(phi), _ptr(delta),
+                                _ptr(fa), fs, _ptr(out), _ptr(ws), ws.numel(), _stream()))
+    return out
+
+
+def op_colour_pass(par, phi, delta, colour, f=0.0, h=1.0):
+    n = phi.shape[0]
+    out = torch.empty_like(phi)
+    ws = _op_ws(n, phi.device)
+    fa = f if isinstance(f, torch.Tensor) else None
+    fs = 0.0 if fa is not None else float(f)
+    _raise(lib().mg_op_colour_pass(_model_of(par), C.byref(par), n, h, colour, _ptr(phi),
+                                   _ptr(delta), _ptr(fa), fs, _ptr(out), _ptr(ws), ws.numel(),
+                                   _stream()))
+    return out
+
+
+def op_restrict(fine):
+    n = fine.shape[0]
+    out = torch.empty((n // 2,) * 3, dtype=fine.dtype, device=fine.device)
+    ws = _op_ws(n, fine.device)
+    _raise(lib().mg_op_restrict(n, _ptr(fine), _ptr(out), _ptr(ws), ws.numel(), _stream()))
+    return out
+
+
+def op_prolong_add(fine, uc, rc):
+    n = fine.shape[0]
+    out = fine.clone()
+    ws = _op_ws(n, fine.device)
+    _raise(lib().mg_op_prolong_add(n, _ptr(out), _ptr(uc), _ptr(rc), _ptr(ws), ws.numel(),
+                                   _stream()))
+    return out
+
+
+def op_jt_apply(par, phi, delta, v, h=1.0):
+    n = phi.shape[0]
+    out = torch.empty_like(phi)
+    ws = _op_ws(n, phi.device)
+    _raise(lib().mg_op_jt_apply(_model_of(par), C.byref(par), n, h, _ptr(phi), _ptr(delta),
+                                _ptr(v), _ptr(out), _ptr(ws), ws.numel(), _stream()))
+    return out

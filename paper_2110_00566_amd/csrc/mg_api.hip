@@ -1,0 +1,813 @@
+// Host driver and C ABI of the multigrid solver (see include/mgglam.h).
+//
+// The solve follows the FAS scheme of Sec. 3.2.1 of the paper: V-cycles of
+// nonlinear red-black Gauss-Seidel smoothing (eq:relaxation_iteration with
+// the exact per-cell solve of eq:nonlinear_GS_DGP), residual and 8-cell mean
+// restriction, the coarse equation eq:general_pde_numerical_coarse with
+// R(u) as initial guess, 27/9/3/1 prolongation of the correction
+// (eq:solution_correction), down to a 4^3 level.  The periodic discrete
+// problem is solved in bordered form: the finest right-hand side is the mean
+// of L(phi), refreshed at the residual step of every cycle, and the returned
+// field has zero mean.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mgglam.h"
+#include "mg_adjoint.h"
+
+using namespace mgk;
+
+namespace {
+
+thread_local std::string g_err;
+
+mg_status fail(mg_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIPCHK(x)                                                                  \
+    do {                                                                           \
+        hipError_t e_ = (x);                                                       \
+        if (e_ != hipSuccess) {                                                    \
+            g_err = std::string(#x) + ": " + hipGetErrorString(e_);                \
+            return MG_ERR_HIP;                                                     \
+        }                                                                          \
+    } while (0)
+
+int ilog2(long n) {
+    int l = 0;
+    while ((1L << l) < n) ++l;
+    return l;
+}
+bool is_pow2(long n) { return n > 0 && (n & (n - 1)) == 0; }
+
+constexpr int MAX_LEVELS = 12;
+
+struct Carve {
+    char *base;
+    size_t off;
+    template <class T>
+    T *take(size_t count) {
+        off = (off + 255) & ~(size_t)255;
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+struct HLevel {
+    int n = 0, logn = 0;
+    double h = 1.0;
+    size_t half = 0;
+    double *u[2] = {nullptr, nullptr};
+    double *spare = nullptr;
+    double *d[2] = {nullptr, nullptr};
+    double *f[2] = {nullptr, nullptr};
+    double *ru[2] = {nullptr, nullptr};
+    double *lin[2] = {nullptr, nullptr};
+    double *cf[9][2] = {};
+};
+
+struct Ctx {
+    int nlev = 0;
+    HLevel lv[MAX_LEVELS];
+    double *partials = nullptr;
+    size_t npartials = 0;
+    double *scal = nullptr;
+    unsigned long long *clamp = nullptr;
+    hipStream_t st = nullptr;
+    Mod M{};
+    int nu1 = 1, nu2 = 1, nuc = 32;
+    double kappa = 6.0;
+    bool profile = false;
+    std::vector<hipEvent_t> ev;
+    int ev_used = 0;
+    double pass_ms = 0.0;
+    int pass_count = 0;
+};
+
+// Lay the workspace out (base == nullptr: only measure).
+void layout(Ctx &C, Carve &cv, int n, bool adjoint) {
+    int L = 0;
+    for (int m = n; m >= 4; m >>= 1) {
+        HLevel &H = C.lv[L];
+        H.n = m;
+        H.logn = ilog2(m);
+        H.h = (double)n / m;
+        H.half = (size_t)m * m * m / 2;
+        H.u[0] = cv.take<double>(H.half);
+        H.u[1] = cv.take<double>(H.half);
+        H.spare = cv.take<double>(H.half);
+        H.d[0] = cv.take<double>(H.half);
+        H.d[1] = cv.take<double>(H.half);
+        if (L > 0 || adjoint) {
+            H.f[0] = cv.take<double>(H.half);
+            H.f[1] = cv.take<double>(H.half);
+        }
+        if (L > 0) {
+            H.ru[0] = cv.take<double>(H.half);
+            H.ru[1] = cv.take<double>(H.half);
+        }
+        if (adjoint) {
+            H.lin[0] = cv.take<double>(H.half);
+            H.lin[1] = cv.take<double>(H.half);
+            for (int q = 0; q < 9; ++q)
+                for (int c = 0; c < 2; ++c) H.cf[q][c] = cv.take<double>(H.half);
+        }
+        ++L;
+    }
+    C.nlev = L;
+    C.npartials = std::max<size_t>((size_t)n * n * n / TPB + 1, 1024);
+    C.partials = cv.take<double>(2 * C.npartials);
+    C.scal = cv.take<double>(S_NSCAL);
+    C.clamp = cv.take<unsigned long long>(4);
+}
+
+Lvl view(const HLevel &H, bool with_f) {
+    Lvl L;
+    L.u0 = H.u[0];
+    L.u1 = H.u[1];
+    L.d0 = H.d[0];
+    L.d1 = H.d[1];
+    L.f0 = with_f ? H.f[0] : nullptr;
+    L.f1 = with_f ? H.f[1] : nullptr;
+    L.n = H.n;
+    L.logn = H.logn;
+    L.lognh = H.logn - 1;
+    const double h2 = H.h * H.h, h4 = h2 * h2;
+    L.h2 = h2;
+    L.c3h4 = 1.0 / (3.0 * h4);
+    L.c8h4 = 1.0 / (8.0 * h4);
+    L.c12h4 = 1.0 / (12.0 * h4);
+    L.c4h2 = 1.0 / (4.0 * h2);
+    return L;
+}
+
+Coefs coefs(const HLevel &H) {
+    Coefs C;
+    for (int q = 0; q < 9; ++q)
+        for (int c = 0; c < 2; ++c) C.c[q][c] = H.cf[q][c];
+    return C;
+}
+
+unsigned nblocks(size_t threads) { return (unsigned)((threads + TPB - 1) / TPB); }
+
+// ---------------------------------------------------------------- model set-up
+
+bool setup_dgp(const mg_dgp_params *p, Mod &M) {
+    if (!(p->a > 0.0) || !(p->omega_m > 0.0) || !(p->omega_m < 1.0) || !(p->h0rc > 0.0) ||
+        !std::isfinite(p->a) || !std::isfinite(p->h0rc))
+        return false;
+    // eq:beta_dgp with the LCDM H(a) of eq:H_lcdm; Omega_rc = 1/(4 R_c^2)
+    const double a3 = p->a * p->a * p->a;
+    const double om = p->omega_m, ol = 1.0 - om;
+    const double orc = 1.0 / (4.0 * p->h0rc * p->h0rc);
+    const double beta = 1.0 + (om / a3 + 2.0 * ol) / (2.0 * std::sqrt(orc * (om / a3 + ol)));
+    M = Mod{};
+    M.alpha = 3.0 * beta * p->a * p->a / (p->h0rc * p->h0rc);
+    M.sgn = M.alpha >= 0.0 ? 1.0 : -1.0;
+    M.s = M.alpha / beta * om / p->a;
+    return true;
+}
+
+bool setup_kmo(const mg_kmo_params *p, int n, Mod &M) {
+    if (p->n_k < 2 || p->n_k > 8 || !(p->k0 >= 0.0) || !(p->lambda > 0.0) || !(p->a > 0.0) ||
+        !(p->omega_m > 0.0) || !(p->box_mpch > 0.0) || !std::isfinite(p->beta) ||
+        !std::isfinite(p->phibar) || !std::isfinite(p->dphibar_dtau_over_h0))
+        return false;
+    const double x0 = 1.0 / (2.0 * p->a * p->a * p->lambda * p->lambda);
+    const double b = p->dphibar_dtau_over_h0 * p->dphibar_dtau_over_h0;
+    double xp = 1.0, bp = 1.0;
+    for (int q = 0; q < p->n_k - 1; ++q) {
+        xp *= x0;
+        bp *= b;
+    }
+    const double gamma = p->n_k * p->k0 * xp;
+    M = Mod{};
+    M.ctil = (double)n / p->box_mpch * 2997.92458;
+    M.c0 = 1.0 + gamma * bp;
+    M.a1 = (2.0 * p->n_k + 1.0) * gamma / 3.0;
+    M.b2 = -2.0 * M.ctil * (p->n_k - 1) * gamma;
+    M.src = 3.0 * p->beta * std::exp(p->beta * p->phibar) * p->omega_m / p->a;
+    M.nk = p->n_k;
+    return true;
+}
+
+mg_status check_opts(const mg_opts *o) {
+    if (!o) return fail(MG_ERR_ARG, "opts is NULL");
+    if (!is_pow2(o->n) || o->n < 8 || o->n > 2048)
+        return fail(MG_ERR_ARG, "opts.n must be a power of two in [8, 2048]");
+    if (o->max_cycles < 0 || o->max_cycles > 100000)
+        return fail(MG_ERR_ARG, "opts.max_cycles must be in [0, 100000]");
+    if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return fail(MG_ERR_ARG, "opts.tol must be >= 0");
+    if (o->nu_pre < 0 || o->nu_post < 0 || o->nu_coarse < 1 || o->nu_pre > 64 || o->nu_post > 64 ||
+        o->nu_coarse > 4096)
+        return fail(MG_ERR_ARG, "sweep counts out of range");
+    if (o->precision != MG_FP64) return fail(MG_ERR_ARG, "only MG_FP64 precision is available");
+    if (o->cycle != 0) return fail(MG_ERR_ARG, "only the V-cycle (cycle = 0) is available");
+    return MG_OK;
+}
+
+// ---------------------------------------------------------------- V-cycle
+
+template <int OP>
+struct Solver {
+    Ctx &C;
+    explicit Solver(Ctx &c) : C(c) {}
+
+    hipError_t launch_err() { return hipGetLastError(); }
+
+    void mean_of(double *a0, double *a1, size_t half) {
+        const unsigned nb = nblocks(2 * half);
+        k_sum<<<nb, TPB, 0, C.st>>>(a0, a1, half, C.partials);
+        k_finalize<<<1, 1024, 0, C.st>>>(C.partials, nb, (double)(2 * half), C.scal, 1, 0.0);
+    }
+
+    void pass(int l, int c) {
+        HLevel &H = C.lv[l];
+        const double *fptr = nullptr;
+        double fs = 0.0;
+        if (l == 0) {
+            if (OP == OP_ADJ) {
+                mean_of(H.u[0], H.u[1], H.half);
+                fptr = C.scal + S_MEAN;
+                fs = C.kappa;
+            } else {
+                fptr = C.scal + S_MU;
+                fs = 1.0;
+            }
+        }
+        const bool timed = C.profile && l == 0 && C.ev_used + 2 <= (int)C.ev.size();
+        if (timed) (void)hipEventRecord(C.ev[C.ev_used], C.st);
+        k_pass<OP><<<nblocks(H.half), TPB, 0, C.st>>>(C.M, view(H, l > 0 || OP == OP_ADJ),
+                                                       coefs(H), c, H.spare, fptr, fs, C.clamp);
+        if (timed) {
+            (void)hipEventRecord(C.ev[C.ev_used + 1], C.st);
+            C.ev_used += 2;
+        }
+        std::swap(H.u[c], H.spare);
+    }
+
+    void sweep(int l) {
+        pass(l, 0);
+        pass(l, 1);
+    }
+
+    // finest residual statistics (and restriction into level 1)
+    void resid_restrict(int l) {
+        HLevel &H = C.lv[l], &Hc = C.lv[l + 1];
+        const size_t ncoarse = (size_t)Hc.n * Hc.n * Hc.n;
+        const unsigned nb = nblocks(ncoarse);
+        const bool with_f = l > 0 || OP == OP_ADJ;
+        const double *fptr = (l == 0 && OP != OP_ADJ) ? C.scal + S_MU : nullptr;
+        if (l == 0) {
+            if (OP == OP_ADJ) mean_of(H.u[0], H.u[1], H.half);
+            k_resid_restrict<OP, true><<<nb, TPB, 0, C.st>>>(C.M, view(H, with_f), coefs(H), fptr,
+                                                             1.0, Hc.ru[0], Hc.ru[1], Hc.f[0],
+                                                             Hc.f[1], C.partials, C.clamp);
+            k_finalize<<<1, 1024, 0, C.st>>>(C.partials, nb, (double)H.n * H.n * H.n, C.scal,
+                                             OP == OP_ADJ ? 2 : 0, C.kappa);
+        } else {
+            k_resid_restrict<OP, false><<<nb, TPB, 0, C.st>>>(C.M, view(H, with_f), coefs(H),
+                                                              fptr, 1.0, Hc.ru[0], Hc.ru[1],
+                                                              Hc.f[0], Hc.f[1], C.partials,
+                                                              C.clamp);
+        }
+    }
+
+    void coarse_source(int lc) {
+        HLevel &Hc = C.lv[lc];
+        Lvl L = view(Hc, false);
+        L.u0 = Hc.ru[0];
+        L.u1 = Hc.ru[1];
+        const double *shift = (lc == 1 && OP != OP_ADJ) ? C.scal + S_SHIFT : nullptr;
+        k_coarse_source<OP><<<nblocks(2 * Hc.half), TPB, 0, C.st>>>(
+            C.M, L, coefs(Hc), Hc.f[0], Hc.f[1], Hc.u[0], Hc.u[1], shift);
+    }
+
+    void prolong(int l) {
+        HLevel &H = C.lv[l], &Hc = C.lv[l + 1];
+        k_prolong<<<nblocks(2 * H.half), TPB, 0, C.st>>>(H.u[0], H.u[1], H.logn, Hc.u[0],
+                                                         Hc.u[1], Hc.ru[0], Hc.ru[1]);
+    }
+
+    void vcycle(int l) {
+        if (l == C.nlev - 1) {
+            for (int s = 0; s < C.nuc; ++s) sweep(l);
+            return;
+        }
+        for (int s = 0; s < C.nu1; ++s) sweep(l);
+        resid_restrict(l);
+        coarse_source(l + 1);
+        vcycle(l + 1);
+        prolong(l);
+        for (int s = 0; s < C.nu2; ++s) sweep(l);
+    }
+
+    mg_status read_scal(double *hs) {
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(hs, C.scal, sizeof(double) * S_NSCAL, hipMemcpyDeviceToHost, C.st));
+        HIPCHK(hipStreamSynchronize(C.st));
+        if (C.profile) {
+            for (int q = 0; q + 1 < C.ev_used; q += 2) {
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, C.ev[q], C.ev[q + 1]));
+                C.pass_ms += ms;
+                ++C.pass_count;
+            }
+            C.ev_used = 0;
+        }
+        return MG_OK;
+    }
+
+    // Cycle loop shared by the forward and the adjoint solves.  phi (finest
+    // packed u) is already initialised; the right-hand side is set up.
+    mg_status cycles(const mg_opts *o, mg_stats *st) {
+        double hs[S_NSCAL];
+        mg_status rc;
+        // initial residual
+        resid_restrict(0);
+        if ((rc = read_scal(hs)) != MG_OK) return rc;
+        double eps = std::sqrt(hs[S_EPS2]);
+        st->eps0 = eps;
+        if (!std::isfinite(eps)) return fail(MG_ERR_NONFINITE, "initial residual is not finite");
+        int status = (eps <= o->tol) ? MG_OK : MG_NOT_CONVERGED;
+        double best = eps;
+        int cyc = 0;
+        if (status != MG_OK) {
+            for (cyc = 1; cyc <= o->max_cycles; ++cyc) {
+                vcycle(0);
+                if ((rc = read_scal(hs)) != MG_OK) return rc;
+                const double em = std::sqrt(hs[S_EPS2]);
+                if (cyc - 1 < MG_HIST) st->eps_hist[cyc - 1] = em;
+                if (!std::isfinite(em)) {
+                    status = MG_ERR_NONFINITE;
+                    break;
+                }
+                if (em > 1e3 * best) {
+                    status = MG_ERR_DIVERGED;
+                    break;
+                }
+                if (em < best) best = em;
+                if (em <= o->tol || cyc == o->max_cycles) {
+                    resid_restrict(0);
+                    if ((rc = read_scal(hs)) != MG_OK) return rc;
+                    eps = std::sqrt(hs[S_EPS2]);
+                    if (eps <= o->tol) {
+                        status = MG_OK;
+                        break;
+                    }
+                }
+            }
+            if (cyc > o->max_cycles) cyc = o->max_cycles;
+        }
+        st->cycles = cyc;
+        st->eps = eps;
+        st->lambda = -hs[S_MU];
+        st->cell_updates = (long long)o->n * o->n * o->n * (o->nu_pre + o->nu_post) * cyc;
+        return (mg_status)status;
+    }
+};
+
+// Pack delta into the finest level and restrict it down the hierarchy.
+void density_hierarchy(Ctx &C, const double *delta) {
+    HLevel &F = C.lv[0];
+    k_pack<<<nblocks(2 * F.half), TPB, 0, C.st>>>(delta, F.logn, F.d[0], F.d[1], nullptr);
+    for (int l = 0; l + 1 < C.nlev; ++l) {
+        HLevel &H = C.lv[l], &Hc = C.lv[l + 1];
+        k_restrict<<<nblocks(2 * Hc.half), TPB, 0, C.st>>>(H.d[0], H.d[1], H.logn, Hc.d[0],
+                                                          Hc.d[1]);
+    }
+}
+
+void reset_scalars(Ctx &C) {
+    k_fill<<<1, TPB, 0, C.st>>>(C.scal, S_NSCAL, 0.0);
+    k_fill_u64<<<1, TPB, 0, C.st>>>(C.clamp, 4);
+}
+
+struct Profiler {
+    Ctx &C;
+    Profiler(Ctx &c, bool on, int per_cycle) : C(c) {
+        C.profile = on;
+        if (on) {
+            C.ev.resize(2 * per_cycle);
+            for (auto &e : C.ev) (void)hipEventCreate(&e);
+        }
+    }
+    ~Profiler() {
+        for (auto &e : C.ev) (void)hipEventDestroy(e);
+        C.ev.clear();
+    }
+};
+
+template <int OP>
+mg_status forward_solve(const mg_opts *o, const Mod &M, const double *delta, double *phi,
+                        void *ws, size_t ws_bytes, hipStream_t stream, mg_stats *st) {
+    auto t0 = std::chrono::steady_clock::now();
+    Ctx C;
+    Carve cv{static_cast<char *>(ws), 0};
+    layout(C, cv, o->n, false);
+    if (!ws || ws_bytes < cv.off)
+        return fail(MG_ERR_WORKSPACE, "workspace too small: need " + std::to_string(cv.off) +
+                                          " bytes");
+    C.st = stream;
+    C.M = M;
+    C.nu1 = o->nu_pre;
+    C.nu2 = o->nu_post;
+    C.nuc = o->nu_coarse;
+    Profiler prof(C, o->profile != 0, 2 * (o->nu_pre + o->nu_post) + 2);
+    reset_scalars(C);
+    density_hierarchy(C, delta);
+    HLevel &F = C.lv[0];
+    k_pack<<<nblocks(2 * F.half), TPB, 0, C.st>>>(phi, F.logn, F.u[0], F.u[1], nullptr);
+    Solver<OP> S(C);
+    mg_status rc = S.cycles(o, st);
+    if (rc < 0) {
+        st->status = rc;
+        return rc;
+    }
+    // zero-mean gauge
+    S.mean_of(F.u[0], F.u[1], F.half);
+    k_unpack<<<nblocks(2 * F.half), TPB, 0, C.st>>>(F.u[0], F.u[1], F.logn, phi,
+                                                    C.scal + S_MEAN);
+    unsigned long long ncl = 0;
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(&ncl, C.clamp, sizeof(ncl), hipMemcpyDeviceToHost, C.st));
+    HIPCHK(hipStreamSynchronize(C.st));
+    st->n_clamped = (long long)ncl;
+    if (rc == MG_OK && ncl > 0) rc = MG_WARN_CLAMPED;
+    st->status = rc;
+    st->pass_ms_avg = C.pass_count ? C.pass_ms / C.pass_count : 0.0;
+    st->pass_count = C.pass_count;
+    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
+}
+
+template <int MODEL>
+void adj_coefficients(Ctx &C, const double *phi, const double *delta) {
+    // linearisation points: packed phi on the finest level, restricted below
+    HLevel &F = C.lv[0];
+    k_pack<<<nblocks(2 * F.half), TPB, 0, C.st>>>(phi, F.logn, F.lin[0], F.lin[1], nullptr);
+    for (int l = 0; l < C.nlev; ++l) {
+        HLevel &H = C.lv[l];
+        if (l + 1 < C.nlev) {
+            HLevel &Hc = C.lv[l + 1];
+            k_restrict<<<nblocks(2 * Hc.half), TPB, 0, C.st>>>(H.lin[0], H.lin[1], H.logn,
+                                                              Hc.lin[0], Hc.lin[1]);
+        }
+        Lvl L = view(H, false);
+        L.u0 = H.lin[0];
+        L.u1 = H.lin[1];
+        CoefsW W;
+        for (int q = 0; q < 9; ++q)
+            for (int c = 0; c < 2; ++c) W.c[q][c] = H.cf[q][c];
+        k_adj_coefs<MODEL><<<nblocks(2 * H.half), TPB, 0, C.st>>>(C.M, L, W, H.h);
+    }
+    (void)delta;
+}
+
+template <int MODEL>
+mg_status adjoint_solve(const mg_opts *o, const Mod &M, const double *delta, const double *phi,
+                        const double *w, double *grad, double *mu, void *ws, size_t ws_bytes,
+                        hipStream_t stream, mg_stats *st) {
+    auto t0 = std::chrono::steady_clock::now();
+    Ctx C;
+    Carve cv{static_cast<char *>(ws), 0};
+    layout(C, cv, o->n, true);
+    if (!ws || ws_bytes < cv.off)
+        return fail(MG_ERR_WORKSPACE, "workspace too small: need " + std::to_string(cv.off) +
+                                          " bytes");
+    C.st = stream;
+    C.M = M;
+    C.nu1 = o->nu_pre;
+    C.nu2 = o->nu_post;
+    C.nuc = o->nu_coarse;
+    C.kappa = 6.0;   // 6/h^2 on the finest level: removes the mean of mu in one pass
+    Profiler prof(C, false, 0);
+    reset_scalars(C);
+    density_hierarchy(C, delta);
+    adj_coefficients<MODEL>(C, phi, delta);
+    HLevel &F = C.lv[0];
+    // right-hand side b = w - mean(w) on the finest level
+    k_pack<<<nblocks(2 * F.half), TPB, 0, C.st>>>(w, F.logn, F.f[0], F.f[1], nullptr);
+    Solver<OP_ADJ> S(C);
+    S.mean_of(F.f[0], F.f[1], F.half);
+    k_pack<<<nblocks(2 * F.half), TPB, 0, C.st>>>(w, F.logn, F.f[0], F.f[1], C.scal + S_MEAN);
+    k_pack<<<nblocks(2 * F.half), TPB, 0, C.st>>>(mu, F.logn, F.u[0], F.u[1], nullptr);
+    mg_status rc = S.cycles(o, st);
+    if (rc < 0) {
+        st->status = rc;
+        return rc;
+    }
+    k_unpack<<<nblocks(2 * F.half), TPB, 0, C.st>>>(F.u[0], F.u[1], F.logn, mu, nullptr);
+    Lvl L = view(F, false);
+    L.u0 = F.lin[0];
+    L.u1 = F.lin[1];
+    k_adj_grad<MODEL><<<nblocks(2 * F.half), TPB, 0, C.st>>>(C.M, L, F.u[0], F.u[1], grad);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(C.st));
+    st->status = rc;
+    st->lambda = 0.0;
+    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
+}
+
+}  // namespace
+
+namespace {
+
+size_t op_workspace_bytes(int n) {
+    if (!is_pow2(n) || n < 4 || n > 2048) return 0;
+    const size_t half = (size_t)n * n * n / 2;
+    // u(2) + spare + d(2) + f(2) + out(2) + coefficients(18) + coarse (2+2)
+    return (half * (2 + 1 + 2 + 2 + 2 + 18 + 2 + 2) + 64) * sizeof(double) + 256 * 40;
+}
+struct OpWs {
+    HLevel H;
+    double *out[2];
+    double *coarse[2];
+};
+
+mg_status op_layout(int n, double h, void *ws, size_t ws_bytes, OpWs &W) {
+    if (!is_pow2(n) || n < 4 || n > 2048) return fail(MG_ERR_ARG, "n must be a power of two in [4, 2048]");
+    if (!(h > 0.0)) return fail(MG_ERR_ARG, "h must be > 0");
+    if (!ws || ws_bytes < op_workspace_bytes(n)) return fail(MG_ERR_WORKSPACE, "workspace too small");
+    Carve cv{static_cast<char *>(ws), 0};
+    HLevel &H = W.H;
+    H.n = n;
+    H.logn = ilog2(n);
+    H.h = h;
+    H.half = (size_t)n * n * n / 2;
+    for (int c = 0; c < 2; ++c) H.u[c] = cv.take<double>(H.half);
+    H.spare = cv.take<double>(H.half);
+    for (int c = 0; c < 2; ++c) H.d[c] = cv.take<double>(H.half);
+    for (int c = 0; c < 2; ++c) H.f[c] = cv.take<double>(H.half);
+    for (int c = 0; c < 2; ++c) W.out[c] = cv.take<double>(H.half);
+    for (int q = 0; q < 9; ++q)
+        for (int c = 0; c < 2; ++c) H.cf[q][c] = cv.take<double>(H.half);
+    for (int c = 0; c < 2; ++c) W.coarse[c] = cv.take<double>(H.half / 4 + 1);
+    return MG_OK;
+}
+
+template <int OP>
+void op_residual_launch(const Mod &M, OpWs &W, const double *fptr, hipStream_t s, bool with_f,
+                        unsigned long long *clamp) {
+    HLevel &H = W.H;
+    k_residual<OP><<<nblocks(2 * H.half), TPB, 0, s>>>(M, view(H, with_f), coefs(H), fptr, 1.0,
+                                                       W.out[0], W.out[1], clamp);
+}
+
+template <int OP>
+void op_pass_launch(const Mod &M, OpWs &W, int colour, hipStream_t s, bool with_f) {
+    HLevel &H = W.H;
+    k_pass<OP><<<nblocks(H.half), TPB, 0, s>>>(M, view(H, with_f), coefs(H), colour,
+                                               colour ? W.out[1] : W.out[0], nullptr, 0.0, nullptr);
+}
+}  // namespace
+
+// ===================================================================== C ABI
+
+extern "C" {
+
+size_t mg_workspace_bytes(int n, int precision, int model, int adjoint) {
+    if (!is_pow2(n) || n < 8 || n > 2048 || precision != MG_FP64 || model < 0 || model > 2)
+        return 0;
+    Ctx C;
+    Carve cv{nullptr, 0};
+    layout(C, cv, n, adjoint != 0);
+    return cv.off + 256;
+}
+
+static mg_status common_checks(const mg_opts *o, const void *delta, const void *phi, void *ws,
+                               mg_stats *st) {
+    mg_status rc = check_opts(o);
+    if (rc != MG_OK) return rc;
+    if (!delta || !phi) return fail(MG_ERR_ARG, "delta and phi must be device pointers");
+    if (!st) return fail(MG_ERR_ARG, "stats is NULL");
+    if (!ws) return fail(MG_ERR_WORKSPACE, "workspace is NULL");
+    std::memset(st, 0, sizeof(*st));
+    g_err.clear();
+    return MG_OK;
+}
+
+mg_status mg_solve_dgp(const mg_opts *opts, const mg_dgp_params *par, const double *delta,
+                       double *phi, void *ws, size_t ws_bytes, hipStream_t stream,
+                       mg_stats *stats) {
+    mg_status rc = common_checks(opts, delta, phi, ws, stats);
+    if (rc != MG_OK) return rc;
+    Mod M;
+    if (!par || !setup_dgp(par, M)) return fail(MG_ERR_ARG, "invalid nDGP parameters");
+    return forward_solve<OP_DGP>(opts, M, delta, phi, ws, ws_bytes, stream, stats);
+}
+
+mg_status mg_solve_kmouflage(const mg_opts *opts, const mg_kmo_params *par, const double *delta,
+                             double *phi, void *ws, size_t ws_bytes, hipStream_t stream,
+                             mg_stats *stats) {
+    mg_status rc = common_checks(opts, delta, phi, ws, stats);
+    if (rc != MG_OK) return rc;
+    Mod M;
+    if (!par || !setup_kmo(par, opts->n, M)) return fail(MG_ERR_ARG, "invalid Kmouflage parameters");
+    return forward_solve<OP_KMO>(opts, M, delta, phi, ws, ws_bytes, stream, stats);
+}
+
+mg_status mg_solve_poisson(const mg_opts *opts, const mg_poisson_params *par, const double *delta,
+                           double *phi, void *ws, size_t ws_bytes, hipStream_t stream,
+                           mg_stats *stats) {
+    mg_status rc = common_checks(opts, delta, phi, ws, stats);
+    if (rc != MG_OK) return rc;
+    if (!par || !std::isfinite(par->s)) return fail(MG_ERR_ARG, "invalid Poisson parameters");
+    Mod M{};
+    M.s = par->s;
+    return forward_solve<OP_POISSON>(opts, M, delta, phi, ws, ws_bytes, stream, stats);
+}
+
+static bool model_mod(int model, const void *params, int n, Mod &M) {
+    if (!params) return false;
+    if (model == MG_MODEL_DGP) return setup_dgp((const mg_dgp_params *)params, M);
+    if (model == MG_MODEL_KMOUFLAGE) return setup_kmo((const mg_kmo_params *)params, n, M);
+    if (model == MG_MODEL_POISSON) {
+        M = Mod{};
+        M.s = ((const mg_poisson_params *)params)->s;
+        return std::isfinite(M.s);
+    }
+    return false;
+}
+
+mg_status mg_solve_adjoint(const mg_opts *opts, int model, const void *params,
+                           const double *delta, const double *phi, const double *w,
+                           double *grad_delta, double *mu, void *ws, size_t ws_bytes,
+                           hipStream_t stream, mg_stats *stats) {
+    mg_status rc = common_checks(opts, delta, phi, ws, stats);
+    if (rc != MG_OK) return rc;
+    if (!w || !grad_delta || !mu) return fail(MG_ERR_ARG, "w, grad_delta and mu must be device pointers");
+    Mod M;
+    if (!model_mod(model, params, opts->n, M)) return fail(MG_ERR_ARG, "invalid model or parameters");
+    switch (model) {
+        case MG_MODEL_DGP:
+            return adjoint_solve<MODEL_DGP>(opts, M, delta, phi, w, grad_delta, mu, ws, ws_bytes,
+                                            stream, stats);
+        case MG_MODEL_KMOUFLAGE:
+            return adjoint_solve<MODEL_KMO>(opts, M, delta, phi, w, grad_delta, mu, ws, ws_bytes,
+                                            stream, stats);
+        default:
+            return adjoint_solve<MODEL_POISSON>(opts, M, delta, phi, w, grad_delta, mu, ws,
+                                                ws_bytes, stream, stats);
+    }
+}
+
+// ------------------------------------------------------- single operations
+
+size_t mg_op_workspace_bytes(int n) { return op_workspace_bytes(n); }
+
+
+mg_status mg_op_residual(int model, const void *params, int n, double h, const double *phi,
+                         const double *delta, const double *f, double fs, double *out, void *ws,
+                         size_t ws_bytes, hipStream_t stream) {
+    OpWs W;
+    mg_status rc = op_layout(n, h, ws, ws_bytes, W);
+    if (rc != MG_OK) return rc;
+    if (!phi || !delta || !out) return fail(MG_ERR_ARG, "NULL array");
+    Mod M;
+    if (!model_mod(model, params, n, M)) return fail(MG_ERR_ARG, "invalid model or parameters");
+    HLevel &H = W.H;
+    const unsigned nb = nblocks(2 * H.half);
+    k_pack<<<nb, TPB, 0, stream>>>(phi, H.logn, H.u[0], H.u[1], nullptr);
+    k_pack<<<nb, TPB, 0, stream>>>(delta, H.logn, H.d[0], H.d[1], nullptr);
+    // f: array, or a constant written into the f arrays
+    if (f) k_pack<<<nb, TPB, 0, stream>>>(f, H.logn, H.f[0], H.f[1], nullptr);
+    else {
+        k_fill<<<nblocks(H.half), TPB, 0, stream>>>(H.f[0], H.half, fs);
+        k_fill<<<nblocks(H.half), TPB, 0, stream>>>(H.f[1], H.half, fs);
+    }
+    switch (model) {
+        case MG_MODEL_DGP: op_residual_launch<OP_DGP>(M, W, nullptr, stream, true, nullptr); break;
+        case MG_MODEL_KMOUFLAGE: op_residual_launch<OP_KMO>(M, W, nullptr, stream, true, nullptr); break;
+        default: op_residual_launch<OP_POISSON>(M, W, nullptr, stream, true, nullptr); break;
+    }
+    k_unpack<<<nb, TPB, 0, stream>>>(W.out[0], W.out[1], H.logn, out, nullptr);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(stream));
+    return MG_OK;
+}
+
+mg_status mg_op_colour_pass(int model, const void *params, int n, double h, int colour,
+                            const double *phi_in, const double *delta, const double *f, double fs,
+                            double *phi_out, void *ws, size_t ws_bytes, hipStream_t stream) {
+    OpWs W;
+    mg_status rc = op_layout(n, h, ws, ws_bytes, W);
+    if (rc != MG_OK) return rc;
+    if (!phi_in || !delta || !phi_out) return fail(MG_ERR_ARG, "NULL array");
+    if (colour != 0 && colour != 1) return fail(MG_ERR_ARG, "colour must be 0 or 1");
+    Mod M;
+    if (!model_mod(model, params, n, M)) return fail(MG_ERR_ARG, "invalid model or parameters");
+    HLevel &H = W.H;
+    const unsigned nb = nblocks(2 * H.half);
+    k_pack<<<nb, TPB, 0, stream>>>(phi_in, H.logn, H.u[0], H.u[1], nullptr);
+    k_pack<<<nb, TPB, 0, stream>>>(phi_in, H.logn, W.out[0], W.out[1], nullptr);
+    k_pack<<<nb, TPB, 0, stream>>>(delta, H.logn, H.d[0], H.d[1], nullptr);
+    if (f) k_pack<<<nb, TPB, 0, stream>>>(f, H.logn, H.f[0], H.f[1], nullptr);
+    else {
+        k_fill<<<nblocks(H.half), TPB, 0, stream>>>(H.f[0], H.half, fs);
+        k_fill<<<nblocks(H.half), TPB, 0, stream>>>(H.f[1], H.half, fs);
+    }
+    switch (model) {
+        case MG_MODEL_DGP: op_pass_launch<OP_DGP>(M, W, colour, stream, true); break;
+        case MG_MODEL_KMOUFLAGE: op_pass_launch<OP_KMO>(M, W, colour, stream, true); break;
+        default: op_pass_launch<OP_POISSON>(M, W, colour, stream, true); break;
+    }
+    k_unpack<<<nb, TPB, 0, stream>>>(W.out[0], W.out[1], H.logn, phi_out, nullptr);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(stream));
+    return MG_OK;
+}
+
+mg_status mg_op_restrict(int n, const double *fine, double *coarse, void *ws, size_t ws_bytes,
+                         hipStream_t stream) {
+    OpWs W;
+    mg_status rc = op_layout(n, 1.0, ws, ws_bytes, W);
+    if (rc != MG_OK) return rc;
+    if (n < 8) return fail(MG_ERR_ARG, "n must be >= 8");
+    if (!fine || !coarse) return fail(MG_ERR_ARG, "NULL array");
+    HLevel &H = W.H;
+    k_pack<<<nblocks(2 * H.half), TPB, 0, stream>>>(fine, H.logn, H.u[0], H.u[1], nullptr);
+    k_restrict<<<nblocks(H.half / 4), TPB, 0, stream>>>(H.u[0], H.u[1], H.logn, W.coarse[0],
+                                                        W.coarse[1]);
+    k_unpack<<<nblocks(H.half / 4), TPB, 0, stream>>>(W.coarse[0], W.coarse[1], H.logn - 1,
+                                                      coarse, nullptr);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(stream));
+    return MG_OK;
+}
+
+mg_status mg_op_prolong_add(int n, double *fine, const double *uc, const double *rc_,
+                            void *ws, size_t ws_bytes, hipStream_t stream) {
+    OpWs W;
+    mg_status rc = op_layout(n, 1.0, ws, ws_bytes, W);
+    if (rc != MG_OK) return rc;
+    if (n < 8) return fail(MG_ERR_ARG, "n must be >= 8");
+    if (!fine || !uc || !rc_) return fail(MG_ERR_ARG, "NULL array");
+    HLevel &H = W.H;
+    const unsigned nbc = nblocks(H.half / 4);
+    k_pack<<<nblocks(2 * H.half), TPB, 0, stream>>>(fine, H.logn, H.u[0], H.u[1], nullptr);
+    k_pack<<<nbc, TPB, 0, stream>>>(uc, H.logn - 1, W.coarse[0], W.coarse[1], nullptr);
+    k_pack<<<nbc, TPB, 0, stream>>>(rc_, H.logn - 1, W.out[0], W.out[1], nullptr);
+    k_prolong<<<nblocks(2 * H.half), TPB, 0, stream>>>(H.u[0], H.u[1], H.logn, W.coarse[0],
+                                                       W.coarse[1], W.out[0], W.out[1]);
+    k_unpack<<<nblocks(2 * H.half), TPB, 0, stream>>>(H.u[0], H.u[1], H.logn, fine, nullptr);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(stream));
+    return MG_OK;
+}
+
+mg_status mg_op_jt_apply(int model, const void *params, int n, double h, const double *phi,
+                         const double *delta, const double *v, double *out, void *ws,
+                         size_t ws_bytes, hipStream_t stream) {
+    OpWs W;
+    mg_status rc = op_layout(n, h, ws, ws_bytes, W);
+    if (rc != MG_OK) return rc;
+    if (!phi || !delta || !v || !out) return fail(MG_ERR_ARG, "NULL array");
+    Mod M;
+    if (!model_mod(model, params, n, M)) return fail(MG_ERR_ARG, "invalid model or parameters");
+    HLevel &H = W.H;
+    const unsigned nb = nblocks(2 * H.half);
+    k_pack<<<nb, TPB, 0, stream>>>(phi, H.logn, H.u[0], H.u[1], nullptr);
+    k_pack<<<nb, TPB, 0, stream>>>(delta, H.logn, H.d[0], H.d[1], nullptr);
+    CoefsW Wc;
+    for (int q = 0; q < 9; ++q)
+        for (int c = 0; c < 2; ++c) Wc.c[q][c] = H.cf[q][c];
+    switch (model) {
+        case MG_MODEL_DGP: k_adj_coefs<MODEL_DGP><<<nb, TPB, 0, stream>>>(M, view(H, false), Wc, h); break;
+        case MG_MODEL_KMOUFLAGE: k_adj_coefs<MODEL_KMO><<<nb, TPB, 0, stream>>>(M, view(H, false), Wc, h); break;
+        default: k_adj_coefs<MODEL_POISSON><<<nb, TPB, 0, stream>>>(M, view(H, false), Wc, h); break;
+    }
+    k_pack<<<nb, TPB, 0, stream>>>(v, H.logn, H.u[0], H.u[1], nullptr);
+    op_residual_launch<OP_ADJ>(M, W, nullptr, stream, false, nullptr);
+    k_unpack<<<nb, TPB, 0, stream>>>(W.out[0], W.out[1], H.logn, out, nullptr);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(stream));
+    return MG_OK;
+}
+
+const char *mg_status_string(mg_status s) {
+    switch (s) {
+        case MG_OK: return "MG_OK";
+        case MG_NOT_CONVERGED: return "MG_NOT_CONVERGED: cycle cap reached before the tolerance";
+        case MG_WARN_CLAMPED: return "MG_WARN_CLAMPED: converged; negative discriminants were clamped";
+        case MG_ERR_ARG: return "MG_ERR_ARG: invalid argument";
+        case MG_ERR_HIP: return "MG_ERR_HIP: HIP runtime error";
+        case MG_ERR_NONFINITE: return "MG_ERR_NONFINITE: residual is not finite";
+        case MG_ERR_DIVERGED: return "MG_ERR_DIVERGED: residual grew 1e3 above its minimum";
+        case MG_ERR_WORKSPACE: return "MG_ERR_WORKSPACE: workspace missing or too small";
+    }
+    return "unknown mg_status";
+}
+
+const char *mg_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

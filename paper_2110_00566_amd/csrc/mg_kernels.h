@@ -1,0 +1,368 @@
+// Kernels of the FAS multigrid solve.  See mg_device.h for the storage
+// layout.  Every kernel is one thread per cell (or per coarse cell), 256
+// threads per block, with the block index remapped so that each of the 8
+// XCDs works on a contiguous z-slab (its halo rows stay in its own L2).
+#pragma once
+#include "mg_device.h"
+
+namespace mgk {
+
+constexpr int TPB = 256;
+
+// device scalar slots (one small array in the workspace)
+enum {
+    S_MU = 0,      // finest right-hand side mu = mean L(phi), lagged
+    S_SHIFT = 1,   // mean change of the finest residual since mu was last set
+    S_EPS2 = 2,    // squared RMS of the last reduced residual
+    S_MEAN = 3,    // mean of the last summed field
+    S_NSCAL = 16
+};
+
+enum { OP_DGP = MODEL_DGP, OP_KMO = MODEL_KMO, OP_POISSON = MODEL_POISSON, OP_ADJ = 3 };
+
+// Blocks are dispatched round-robin over the 8 XCDs; hand XCD x the x-th
+// contiguous eighth of the logical tiles.
+__device__ __forceinline__ size_t xcd_block(unsigned b, unsigned nb) {
+    if (nb & 7u) return b;
+    return (size_t)(b & 7u) * (nb >> 3) + (b >> 3);
+}
+
+// Adjoint coefficient arrays of one level: for every cell m the derivative of
+// its model term K_m with respect to the 6 face neighbours (x+ x- y+ y- z+ z-)
+// and the 3 edge pairs (the (+,+)/(-,-) corners carry +e, the (+,-)/(-,+)
+// corners -e).
+struct Coefs {
+    const double *c[9][2];
+};
+
+// Sum of the six face values and the non-Laplacian term at the cell of
+// colour c, packed (m, j, k).
+template <int OP>
+__device__ __forceinline__ double cell_term(const Mod &M, const Lvl &L, const Coefs &Cf, int c,
+                                            int m, int j, int k, double &faces,
+                                            unsigned long long *clamp) {
+    const double *A = c ? L.u1 : L.u0;
+    const double *B = c ? L.u0 : L.u1;
+    if (OP != OP_ADJ) {
+        const Nb s = load_nb(A, B, c, m, j, k, L.n, L.logn, L.lognh);
+        faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
+        const double *D = c ? L.d1 : L.d0;
+        const double delta = D[prow(j, k, L.logn, L.lognh) + m];
+        return model_term<OP>(M, L, s, delta, clamp);
+    } else {
+        // (J^T mu)_p = lap(mu)_p - sum over the neighbours q of p of
+        // dK_q/dphi_p mu_q.  The face neighbour at p - x carries its x+
+        // coefficient, the one at p + x its x- coefficient; edge corners carry
+        // +e_xy at p-x-y and p+x+y, -e_xy at p-x+y and p+x-y.
+        const int nm1 = L.n - 1, hm1 = (L.n >> 1) - 1;
+        const int p = (j + k + c) & 1;
+        const int mp = (m + p) & hm1, mm = (m + p - 1) & hm1;
+        const int jp = (j + 1) & nm1, jm = (j - 1) & nm1;
+        const int kp = (k + 1) & nm1, km = (k - 1) & nm1;
+        const int ln = L.logn, lh = L.lognh;
+        const size_t r00 = prow(j, k, ln, lh);
+        const size_t rp0 = prow(jp, k, ln, lh), rm0 = prow(jm, k, ln, lh);
+        const size_t r0p = prow(j, kp, ln, lh), r0m = prow(j, km, ln, lh);
+        const size_t rpp = prow(jp, kp, ln, lh), rmm = prow(jm, km, ln, lh);
+        const size_t rpm = prow(jp, km, ln, lh), rmp = prow(jm, kp, ln, lh);
+        const int o = c ^ 1;
+        const size_t ixp = r00 + mp, ixm = r00 + mm, iyp = rp0 + m, iym = rm0 + m,
+                     izp = r0p + m, izm = r0m + m;
+        const double vxp = B[ixp], vxm = B[ixm], vyp = B[iyp], vym = B[iym], vzp = B[izp],
+                     vzm = B[izm];
+        faces = (vxp + vxm) + (vyp + vym) + (vzp + vzm);
+        double g = Cf.c[0][o][ixm] * vxm + Cf.c[1][o][ixp] * vxp + Cf.c[2][o][iym] * vym
+                 + Cf.c[3][o][iyp] * vyp + Cf.c[4][o][izm] * vzm + Cf.c[5][o][izp] * vzp;
+        const double *exy = Cf.c[6][c], *exz = Cf.c[7][c], *eyz = Cf.c[8][c];
+        g += (exy[rm0 + mm] * A[rm0 + mm] + exy[rp0 + mp] * A[rp0 + mp])
+           - (exy[rp0 + mm] * A[rp0 + mm] + exy[rm0 + mp] * A[rm0 + mp]);
+        g += (exz[r0m + mm] * A[r0m + mm] + exz[r0p + mp] * A[r0p + mp])
+           - (exz[r0p + mm] * A[r0p + mm] + exz[r0m + mp] * A[r0m + mp]);
+        g += (eyz[rmm + m] * A[rmm + m] + eyz[rpp + m] * A[rpp + m])
+           - (eyz[rmp + m] * A[rmp + m] + eyz[rpm + m] * A[rpm + m]);
+        (void)clamp;
+        return g;
+    }
+}
+
+__device__ __forceinline__ double rhs_at(const Lvl &L, int c, size_t idx, const double *fptr,
+                                         double fscale) {
+    const double *fa = c ? L.f1 : L.f0;
+    double f = fa ? fa[idx] : 0.0;
+    if (fptr) f += fscale * (*fptr);
+    return f;
+}
+
+// One colour pass: every cell of colour c gets the exact solution of its own
+// equation (faces - 6 u)/h^2 - K = f given its neighbours.
+template <int OP>
+__global__ __launch_bounds__(TPB) void k_pass(Mod M, Lvl L, Coefs Cf, int c,
+                                              double *__restrict__ out, const double *fptr,
+                                              double fscale, unsigned long long *clamp) {
+    const size_t t = xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
+    const size_t half = (size_t)1 << (3 * L.logn - 1);
+    if (t >= half) return;
+    const int m = (int)(t & ((1u << L.lognh) - 1));
+    const int j = (int)((t >> L.lognh) & (L.n - 1));
+    const int k = (int)(t >> (L.lognh + L.logn));
+    double faces;
+    const double K = cell_term<OP>(M, L, Cf, c, m, j, k, faces, clamp);
+    const double f = rhs_at(L, c, t, fptr, fscale);
+    out[t] = (faces - L.h2 * (K + f)) * (1.0 / 6.0);
+}
+
+// Deterministic block sum of two values into partials[2*blk .. 2*blk+1].
+__device__ __forceinline__ void block_sum2(double a, double b, double *partials, size_t blk) {
+    __shared__ double sa[TPB / 64], sb[TPB / 64];
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_down(a, off, 64);
+        b += __shfl_down(b, off, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sa[w] = a;
+        sb[w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double x = 0.0, y = 0.0;
+        for (int q = 0; q < TPB / 64; ++q) {
+            x += sa[q];
+            y += sb[q];
+        }
+        partials[2 * blk] = x;
+        partials[2 * blk + 1] = y;
+    }
+}
+
+// Residual d = (faces - 6u)/h^2 - K - f at the 8 children of every coarse
+// cell, restricted (8-cell mean) together with u.  With REDUCE the block
+// sums of d and d^2 go to partials (finest level: residual norm and mean).
+template <int OP, bool REDUCE>
+__global__ __launch_bounds__(TPB) void k_resid_restrict(Mod M, Lvl L, Coefs Cf, const double *fptr,
+                                                        double fscale, double *ru0, double *ru1,
+                                                        double *rd0, double *rd1,
+                                                        double *partials,
+                                                        unsigned long long *clamp) {
+    const size_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const size_t t = blk * TPB + threadIdx.x;
+    const int lnc = L.logn - 1, nc = 1 << lnc;
+    const size_t ncoarse = (size_t)1 << (3 * lnc);
+    double s1 = 0.0, s2 = 0.0;
+    if (t < ncoarse) {
+        const int I = (int)(t & (nc - 1));
+        const int J = (int)((t >> lnc) & (nc - 1));
+        const int K = (int)(t >> (2 * lnc));
+        double sd = 0.0, su = 0.0;
+        const double inv_h2 = 1.0 / L.h2;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int a = q & 1, b = (q >> 1) & 1, cc = q >> 2;
+            const int j = 2 * J + b, k = 2 * K + cc;
+            const int col = (a + b + cc) & 1;
+            double faces;
+            const double term = cell_term<OP>(M, L, Cf, col, I, j, k, faces, clamp);
+            const size_t idx = prow(j, k, L.logn, L.lognh) + I;
+            const double u = (col ? L.u1 : L.u0)[idx];
+            const double d = (faces - 6.0 * u) * inv_h2 - term - rhs_at(L, col, idx, fptr, fscale);
+            sd += d;
+            su += u;
+            if (REDUCE) {
+                s1 += d;
+                s2 += d * d;
+            }
+        }
+        const int ccol = (I + J + K) & 1;
+        const size_t cidx = ((size_t)K << (2 * lnc - 1)) + ((size_t)J << (lnc - 1)) + (I >> 1);
+        (ccol ? ru1 : ru0)[cidx] = 0.125 * su;
+        (ccol ? rd1 : rd0)[cidx] = 0.125 * sd;
+    }
+    if (REDUCE) block_sum2(s1, s2, partials, blk);
+}
+
+// FAS source on the coarse level: S = L^H(R u) - (R d - shift), written over
+// the restricted residual; the coarse unknown starts from R u.
+template <int OP>
+__global__ __launch_bounds__(TPB) void k_coarse_source(Mod M, Lvl Lc, Coefs Cf, double *s0,
+                                                       double *s1, double *u0, double *u1,
+                                                       const double *shift) {
+    const size_t t = xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
+    const size_t half = (size_t)1 << (3 * Lc.logn - 1);
+    if (t >= 2 * half) return;
+    const int c = t >= half;
+    const size_t tt = t - (c ? half : 0);
+    const int m = (int)(tt & ((1u << Lc.lognh) - 1));
+    const int j = (int)((tt >> Lc.lognh) & (Lc.n - 1));
+    const int k = (int)(tt >> (Lc.lognh + Lc.logn));
+    double faces;
+    const double term = cell_term<OP>(M, Lc, Cf, c, m, j, k, faces, nullptr);
+    const double ru = (c ? Lc.u1 : Lc.u0)[tt];
+    double *S = c ? s1 : s0;
+    const double rd = S[tt] - (shift ? *shift : 0.0);
+    S[tt] = (faces - 6.0 * ru) / Lc.h2 - term - rd;
+    (c ? u1 : u0)[tt] = ru;
+}
+
+// u_fine += P(uc - rc) with the cell-centred trilinear weights 27/9/3/1 (/64).
+__global__ __launch_bounds__(TPB) void k_prolong(double *f0, double *f1, int logn,
+                                                 const double *uc0, const double *uc1,
+                                                 const double *rc0, const double *rc1) {
+    const size_t t = xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
+    const int n = 1 << logn, lognh = logn - 1;
+    const size_t half = (size_t)1 << (3 * logn - 1);
+    if (t >= 2 * half) return;
+    const int c = t >= half;
+    const size_t tt = t - (c ? half : 0);
+    const int m = (int)(tt & ((1u << lognh) - 1));
+    const int j = (int)((tt >> lognh) & (n - 1));
+    const int k = (int)(tt >> (lognh + logn));
+    const int p = (j + k + c) & 1;   // i = 2m + p, parent I = m
+    const int lnc = logn - 1, ncm1 = (1 << lnc) - 1;
+    const int I = m, J = j >> 1, K = k >> 1;
+    const int di = p ? 1 : -1, dj = (j & 1) ? 1 : -1, dk = (k & 1) ? 1 : -1;
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int a = q & 1, b = (q >> 1) & 1, cc = q >> 2;
+        const int I2 = (I + a * di) & ncm1, J2 = (J + b * dj) & ncm1, K2 = (K + cc * dk) & ncm1;
+        const size_t idx = ((size_t)K2 << (2 * lnc - 1)) + ((size_t)J2 << (lnc - 1)) + (I2 >> 1);
+        const double v = ((I2 + J2 + K2) & 1) ? (uc1[idx] - rc1[idx]) : (uc0[idx] - rc0[idx]);
+        const double w = (a ? 1.0 : 3.0) * (b ? 1.0 : 3.0) * (cc ? 1.0 : 3.0);
+        acc += w * v;
+    }
+    (c ? f1 : f0)[tt] += acc * (1.0 / 64.0);
+}
+
+// 8-cell mean of a packed field (density hierarchy, linearisation points).
+__global__ __launch_bounds__(TPB) void k_restrict(const double *f0, const double *f1, int logn,
+                                                  double *c0, double *c1) {
+    const size_t t = xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
+    const int lnc = logn - 1, nc = 1 << lnc;
+    if (t >= ((size_t)1 << (3 * lnc))) return;
+    const int I = (int)(t & (nc - 1)), J = (int)((t >> lnc) & (nc - 1)), K = (int)(t >> (2 * lnc));
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int a = q & 1, b = (q >> 1) & 1, cc = q >> 2;
+        const int j = 2 * J + b, k = 2 * K + cc;
+        const size_t idx = ((size_t)k << (2 * logn - 1)) + ((size_t)j << (logn - 1)) + I;
+        s += ((a + b + cc) & 1) ? f1[idx] : f0[idx];
+    }
+    const size_t cidx = ((size_t)K << (2 * lnc - 1)) + ((size_t)J << (lnc - 1)) + (I >> 1);
+    (((I + J + K) & 1) ? c1 : c0)[cidx] = 0.125 * s;
+}
+
+// natural [z][y][x] -> packed colours (optionally minus a device scalar)
+__global__ __launch_bounds__(TPB) void k_pack(const double *nat, int logn, double *c0, double *c1,
+                                              const double *shift) {
+    const size_t t = xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
+    if (t >= ((size_t)1 << (3 * logn))) return;
+    const int n = 1 << logn;
+    const int i = (int)(t & (n - 1)), j = (int)((t >> logn) & (n - 1)), k = (int)(t >> (2 * logn));
+    const size_t idx = ((size_t)k << (2 * logn - 1)) + ((size_t)j << (logn - 1)) + (i >> 1);
+    const double v = nat[t] - (shift ? *shift : 0.0);
+    (((i + j + k) & 1) ? c1 : c0)[idx] = v;
+}
+
+// packed colours -> natural (optionally minus a device scalar)
+__global__ __launch_bounds__(TPB) void k_unpack(const double *c0, const double *c1, int logn,
+                                                double *nat, const double *shift) {
+    const size_t t = xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
+    if (t >= ((size_t)1 << (3 * logn))) return;
+    const int n = 1 << logn;
+    const int i = (int)(t & (n - 1)), j = (int)((t >> logn) & (n - 1)), k = (int)(t >> (2 * logn));
+    const size_t idx = ((size_t)k << (2 * logn - 1)) + ((size_t)j << (logn - 1)) + (i >> 1);
+    const double v = (((i + j + k) & 1) ? c1 : c0)[idx];
+    nat[t] = v - (shift ? *shift : 0.0);
+}
+
+// Block sums of a (and a^2) over n elements of up to two arrays laid end to end.
+__global__ __launch_bounds__(TPB) void k_sum(const double *a0, const double *a1, size_t nhalf,
+                                             double *partials) {
+    const size_t blk = blockIdx.x;
+    const size_t t = blk * TPB + threadIdx.x;
+    double v = 0.0;
+    if (t < nhalf) v = a0[t];
+    else if (a1 && t < 2 * nhalf) v = a1[t - nhalf];
+    block_sum2(v, v * v, partials, blk);
+}
+
+// Finalise a reduction.  mode 0: residual of the finest level with lagged mu
+// (mu += mean, shift = mean, eps2 = variance); mode 1: plain mean into
+// S_MEAN; mode 2: adjoint residual r = d - kappa*mean(mu) with mean(mu) in
+// S_MEAN (shift = 0, eps2 = mean r^2).  Summation order is fixed.
+__global__ __launch_bounds__(1024) void k_finalize(const double *partials, size_t nblocks,
+                                                   double ncells, double *scal, int mode,
+                                                   double kappa) {
+    __shared__ double sa[16], sb[16];
+    double a = 0.0, b = 0.0;
+    for (size_t q = threadIdx.x; q < nblocks; q += 1024) {
+        a += partials[2 * q];
+        b += partials[2 * q + 1];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_down(a, off, 64);
+        b += __shfl_down(b, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sa[threadIdx.x >> 6] = a;
+        sb[threadIdx.x >> 6] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double x = 0.0, y = 0.0;
+        for (int q = 0; q < 16; ++q) {
+            x += sa[q];
+            y += sb[q];
+        }
+        const double mean = x / ncells, msq = y / ncells;
+        if (mode == 0) {
+            scal[S_MU] += mean;
+            scal[S_SHIFT] = mean;
+            const double v = msq - mean * mean;
+            scal[S_EPS2] = v < 0.0 ? 0.0 : v;   // keeps NaN
+        } else if (mode == 1) {
+            scal[S_MEAN] = mean;
+        } else {
+            const double km = kappa * scal[S_MEAN];
+            scal[S_SHIFT] = 0.0;
+            const double v = msq - 2.0 * km * mean + km * km;
+            scal[S_EPS2] = v < 0.0 ? 0.0 : v;   // keeps NaN
+        }
+    }
+}
+
+__global__ void k_fill(double *a, size_t n, double v) {
+    const size_t t = (size_t)blockIdx.x * TPB + threadIdx.x;
+    if (t < n) a[t] = v;
+}
+
+__global__ void k_fill_u64(unsigned long long *a, size_t n) {
+    const size_t t = (size_t)blockIdx.x * TPB + threadIdx.x;
+    if (t < n) a[t] = 0ull;
+}
+
+}  // namespace mgk
+
+namespace mgk {
+
+// Residual r = (faces - 6u)/h^2 - term - f at every cell, packed output.
+template <int OP>
+__global__ __launch_bounds__(TPB) void k_residual(Mod M, Lvl L, Coefs Cf, const double *fptr,
+                                                  double fscale, double *r0, double *r1,
+                                                  unsigned long long *clamp) {
+    const size_t t = xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
+    const size_t half = (size_t)1 << (3 * L.logn - 1);
+    if (t >= 2 * half) return;
+    const int c = t >= half;
+    const size_t tt = t - (c ? half : 0);
+    const int m = (int)(tt & ((1u << L.lognh) - 1));
+    const int j = (int)((tt >> L.lognh) & (L.n - 1));
+    const int k = (int)(tt >> (L.lognh + L.logn));
+    double faces;
+    const double term = cell_term<OP>(M, L, Cf, c, m, j, k, faces, clamp);
+    const double u = (c ? L.u1 : L.u0)[tt];
+    (c ? r1 : r0)[tt] = (faces - 6.0 * u) / L.h2 - term - rhs_at(L, c, tt, fptr, fscale);
+}
+
+}  // namespace mgk

@@ -1,0 +1,187 @@
+// Particle-mesh substrate around the scalar-field solve (Sec. 3.1 of the
+// paper): cloud-in-cell density assignment, the Newtonian and scalar
+// potentials, 3-point central-difference forces interpolated back to the
+// particles with the same CIC weights, and a leapfrog kick-drift in a.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+
+#include "../../include/mgglam.h"
+
+namespace {
+
+constexpr int PTPB = 256;
+constexpr double FIX_SCALE = 4294967296.0;   // 2^32 fixed-point units per particle
+
+__device__ __forceinline__ void cic_weights(const float *p, double f[3], int i0[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double x = (double)p[a] - 0.5;   // cell i has centre i + 1/2
+        const double fl = floor(x);
+        i0[a] = (int)fl;
+        f[a] = x - fl;
+    }
+}
+
+// Deposit: the eight weights of every particle, rounded to 64-bit fixed
+// point, are added with integer atomics, so the sum is independent of order.
+__global__ __launch_bounds__(PTPB) void k_cic(const float *__restrict__ pos, size_t np, int logn,
+                                               unsigned long long *__restrict__ counts) {
+    const size_t t = (size_t)blockIdx.x * PTPB + threadIdx.x;
+    if (t >= np) return;
+    const int nm1 = (1 << logn) - 1;
+    double f[3];
+    int i0[3];
+    cic_weights(pos + 3 * t, f, i0);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int a = q & 1, b = (q >> 1) & 1, c = q >> 2;
+        const double w = ((a ? f[0] : 1.0 - f[0]) * (b ? f[1] : 1.0 - f[1])) * (c ? f[2] : 1.0 - f[2]);
+        const int i = (i0[0] + a) & nm1, j = (i0[1] + b) & nm1, k = (i0[2] + c) & nm1;
+        const size_t idx = ((size_t)k << (2 * logn)) + ((size_t)j << logn) + i;
+        atomicAdd(counts + idx, __double2ull_rn(w * FIX_SCALE));
+    }
+}
+
+__global__ __launch_bounds__(PTPB) void k_counts_to_delta(const unsigned long long *counts,
+                                                           size_t ncell, double scale,
+                                                           double *delta) {
+    const size_t t = (size_t)blockIdx.x * PTPB + threadIdx.x;
+    if (t >= ncell) return;
+    delta[t] = (double)counts[t] * scale - 1.0;
+}
+
+__global__ void k_zero_u64(unsigned long long *a, size_t n) {
+    const size_t t = (size_t)blockIdx.x * PTPB + threadIdx.x;
+    if (t < n) a[t] = 0ull;
+}
+
+// g = -grad(Phi_N + phi/2) by 3-point differences at the 8 CIC cells,
+// interpolated with the CIC weights; p += g*kick; x += p*drift (periodic).
+__global__ __launch_bounds__(PTPB) void k_kick_drift(float *__restrict__ pos,
+                                                      float *__restrict__ mom, size_t np, int logn,
+                                                      const double *__restrict__ phin,
+                                                      const double *__restrict__ phi, double kick,
+                                                      double drift) {
+    const size_t t = (size_t)blockIdx.x * PTPB + threadIdx.x;
+    if (t >= np) return;
+    const int n = 1 << logn, nm1 = n - 1;
+    double f[3];
+    int i0[3];
+    cic_weights(pos + 3 * t, f, i0);
+    double g[3] = {0.0, 0.0, 0.0};
+    auto psi = [&](int i, int j, int k) {
+        const size_t idx = ((size_t)(k & nm1) << (2 * logn)) + ((size_t)(j & nm1) << logn) + (i & nm1);
+        return phin[idx] + 0.5 * phi[idx];
+    };
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int a = q & 1, b = (q >> 1) & 1, c = q >> 2;
+        const double w = ((a ? f[0] : 1.0 - f[0]) * (b ? f[1] : 1.0 - f[1])) * (c ? f[2] : 1.0 - f[2]);
+        const int i = i0[0] + a, j = i0[1] + b, k = i0[2] + c;
+        g[0] -= w * (psi(i + 1, j, k) - psi(i - 1, j, k)) * 0.5;
+        g[1] -= w * (psi(i, j + 1, k) - psi(i, j - 1, k)) * 0.5;
+        g[2] -= w * (psi(i, j, k + 1) - psi(i, j, k - 1)) * 0.5;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double pn = (double)mom[3 * t + a] + g[a] * kick;
+        double xn = fmod((double)pos[3 * t + a] + pn * drift, (double)n);
+        if (xn < 0.0) xn += n;
+        float xf = (float)xn;
+        if (xf >= (float)n) xf = 0.0f;
+        mom[3 * t + a] = (float)pn;
+        pos[3 * t + a] = xf;
+    }
+}
+
+unsigned nb(size_t threads) { return (unsigned)((threads + PTPB - 1) / PTPB); }
+
+bool pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+int ilog2(int n) {
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+}
+
+mg_status cic(int n_mesh, int n_part, const float *pos, double *delta, unsigned long long *counts,
+              hipStream_t s) {
+    const size_t ncell = (size_t)n_mesh * n_mesh * n_mesh;
+    const size_t np = (size_t)n_part * n_part * n_part;
+    const int logn = ilog2(n_mesh);
+    k_zero_u64<<<nb(ncell), PTPB, 0, s>>>(counts, ncell);
+    k_cic<<<nb(np), PTPB, 0, s>>>(pos, np, logn, counts);
+    const double scale = (1.0 / FIX_SCALE) * ((double)ncell / (double)np);
+    k_counts_to_delta<<<nb(ncell), PTPB, 0, s>>>(counts, ncell, scale, delta);
+    return hipGetLastError() == hipSuccess ? MG_OK : MG_ERR_HIP;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+extern "C" {
+
+size_t mg_pm_workspace_bytes(int n_mesh) {
+    if (!pow2(n_mesh) || n_mesh < 8 || n_mesh > 2048) return 0;
+    const size_t ncell = (size_t)n_mesh * n_mesh * n_mesh;
+    return align256(ncell * sizeof(unsigned long long)) +
+           mg_workspace_bytes(n_mesh, MG_FP64, MG_MODEL_DGP, 0) + 256;
+}
+
+mg_status mg_cic_delta(int n_mesh, int n_part, const float *pos, double *delta, void *ws,
+                       size_t ws_bytes, hipStream_t stream) {
+    if (!pow2(n_mesh) || n_mesh < 8 || n_mesh > 2048 || n_part < 1 || n_part > 2048 || !pos ||
+        !delta)
+        return MG_ERR_ARG;
+    const size_t need = (size_t)n_mesh * n_mesh * n_mesh * sizeof(unsigned long long);
+    if (!ws || ws_bytes < need) return MG_ERR_WORKSPACE;
+    mg_status rc = cic(n_mesh, n_part, pos, delta, (unsigned long long *)ws, stream);
+    if (rc != MG_OK) return rc;
+    return hipStreamSynchronize(stream) == hipSuccess ? MG_OK : MG_ERR_HIP;
+}
+
+mg_status mg_pm_step(const mg_pm_params *par, float *pos, float *mom, double *phi,
+                     double *phi_newton, double *delta_out, void *ws, size_t ws_bytes,
+                     hipStream_t stream, mg_stats *stats) {
+    if (!par || !pos || !mom || !phi || !phi_newton || !delta_out || !stats) return MG_ERR_ARG;
+    const int n = par->n_mesh;
+    if (!pow2(n) || n < 8 || n > 2048 || par->mg.n != n || par->n_part < 1 || par->n_part > 2048 ||
+        !(par->a > 0.0) || !std::isfinite(par->da) || !(par->omega_m > 0.0) || !(par->omega_m < 1.0))
+        return MG_ERR_ARG;
+    const size_t need = mg_pm_workspace_bytes(n);
+    if (!ws || ws_bytes < need) return MG_ERR_WORKSPACE;
+    const size_t ncell = (size_t)n * n * n;
+    unsigned long long *counts = (unsigned long long *)ws;
+    char *solver_ws = (char *)ws + align256(ncell * sizeof(unsigned long long));
+    const size_t solver_bytes = ws_bytes - align256(ncell * sizeof(unsigned long long));
+
+    mg_status rc = cic(n, par->n_part, pos, delta_out, counts, stream);
+    if (rc != MG_OK) return rc;
+    // Newtonian potential, eq:GR_poisson_codeunit
+    mg_poisson_params pp{1.5 * par->omega_m / par->a};
+    mg_stats pst;
+    rc = mg_solve_poisson(&par->mg, &pp, delta_out, phi_newton, solver_ws, solver_bytes, stream, &pst);
+    if (rc < 0) return rc;
+    // scalar field, eq:dgp_eom_code
+    mg_dgp_params dp{par->a, par->omega_m, par->h0rc};
+    rc = mg_solve_dgp(&par->mg, &dp, delta_out, phi, solver_ws, solver_bytes, stream, stats);
+    if (rc < 0) return rc;
+    // leapfrog: kick with H0/adot = 1/(a E(a)) at a, drift with
+    // H0/(a^2 adot) at a + da/2 (E^2 = Omega_m a^-3 + 1 - Omega_m)
+    const double om = par->omega_m;
+    const double a = par->a, ah = a + 0.5 * par->da;
+    const double E = std::sqrt(om / (a * a * a) + 1.0 - om);
+    const double Eh = std::sqrt(om / (ah * ah * ah) + 1.0 - om);
+    const double kick = par->da / (a * E);
+    const double drift = par->da / (ah * ah * ah * Eh);
+    const size_t np = (size_t)par->n_part * par->n_part * par->n_part;
+    k_kick_drift<<<nb(np), PTPB, 0, stream>>>(pos, mom, np, ilog2(n), phi_newton, phi, kick, drift);
+    if (hipGetLastError() != hipSuccess) return MG_ERR_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return MG_ERR_HIP;
+    if (pst.status == MG_NOT_CONVERGED && rc == MG_OK) rc = MG_NOT_CONVERGED;
+    return rc;
+}
+
+}  // extern "C"

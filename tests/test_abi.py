@@ -1,0 +1,91 @@
+"""The C ABI library loads, exports every function include/mgglam.h declares,
+and rejects invalid arguments before touching the GPU (CPU only)."""
+import ctypes as C
+
+import pytest
+
+import paper_2110_00566_amd as mg
+
+
+@pytest.fixture(scope="module")
+def L():
+    return mg.lib()
+
+
+def test_header_declares_the_entry_points():
+    names = mg.header_functions()
+    for must in ("mg_solve_dgp", "mg_solve_kmouflage", "mg_solve_adjoint", "mg_pm_step",
+                 "mg_workspace_bytes", "mg_status_string", "mg_last_error", "mg_cic_delta"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    missing = [n for n in mg.header_functions() if not hasattr(L, n)]
+    assert missing == []
+
+
+def test_workspace_sizes(L):
+    assert L.mg_workspace_bytes(7, 0, 0, 0) == 0
+    assert L.mg_workspace_bytes(4096, 0, 0, 0) == 0
+    assert L.mg_workspace_bytes(32, 1, 0, 0) == 0          # precision not available
+    a = L.mg_workspace_bytes(64, 0, 0, 0)
+    b = L.mg_workspace_bytes(64, 0, 0, 1)
+    # finest level: 5 half-arrays of FP64 = 20 bytes per cell, coarse levels add < 1/2
+    assert 20 * 64 ** 3 <= a <= 40 * 64 ** 3
+    assert b > a
+    assert L.mg_workspace_bytes(64, 0, 0, 0) == a          # deterministic
+    assert L.mg_pm_workspace_bytes(64) >= a + 8 * 64 ** 3
+
+
+def _bad_solve(L, **over):
+    o = mg.make_opts(32)
+    for k, v in over.items():
+        setattr(o, k, v)
+    st = mg.Stats()
+    par = mg.dgp_params()
+    dummy = C.c_void_p(0x1000)
+    return L.mg_solve_dgp(C.byref(o), C.byref(par), dummy, dummy, dummy, 1 << 30, None,
+                          C.byref(st))
+
+
+@pytest.mark.parametrize("field,value", [("n", 24), ("n", 4), ("n", 4096), ("tol", -1.0),
+                                         ("tol", float("nan")), ("max_cycles", -1),
+                                         ("nu_coarse", 0), ("precision", 7), ("cycle", 2)])
+def test_invalid_options_rejected_before_gpu(L, field, value):
+    assert _bad_solve(L, **{field: value}) == mg.MG_ERR_ARG
+    assert len(L.mg_last_error()) > 0
+
+
+def test_invalid_model_parameters_rejected(L):
+    o = mg.make_opts(32)
+    st = mg.Stats()
+    d = C.c_void_p(0x1000)
+    bad = mg.DgpParams(1.0, 0.3089, -1.0)
+    assert L.mg_solve_dgp(C.byref(o), C.byref(bad), d, d, d, 1 << 30, None, C.byref(st)) == mg.MG_ERR_ARG
+    badk = mg.kmo_params(32, 64.0, n_k=1)
+    assert L.mg_solve_kmouflage(C.byref(o), C.byref(badk), d, d, d, 1 << 30, None,
+                                C.byref(st)) == mg.MG_ERR_ARG
+
+
+def test_null_pointers_and_workspace(L):
+    o = mg.make_opts(32)
+    st = mg.Stats()
+    par = mg.dgp_params()
+    d = C.c_void_p(0x1000)
+    assert L.mg_solve_dgp(C.byref(o), C.byref(par), None, d, d, 1 << 30, None, C.byref(st)) == mg.MG_ERR_ARG
+    assert L.mg_solve_dgp(C.byref(o), C.byref(par), d, d, None, 1 << 30, None, C.byref(st)) == mg.MG_ERR_WORKSPACE
+    assert L.mg_solve_dgp(C.byref(o), C.byref(par), d, d, d, 16, None, C.byref(st)) == mg.MG_ERR_WORKSPACE
+    assert L.mg_solve_dgp(None, C.byref(par), d, d, d, 1 << 30, None, C.byref(st)) == mg.MG_ERR_ARG
+
+
+def test_status_strings(L):
+    for s in (0, 1, 2, -1, -2, -3, -4, -5):
+        assert L.mg_status_string(s).startswith(b"MG_")
+
+
+def test_product_does_not_import_the_oracle():
+    import pathlib
+    pkg = pathlib.Path(mg.__file__).parent
+    for f in list(pkg.rglob("*.py")) + list(pkg.rglob("*.hip")) + list(pkg.rglob("*.h")):
+        txt = f.read_text()
+        assert "import oracle" not in txt and "from oracle" not in txt and "mg_oracle" not in txt

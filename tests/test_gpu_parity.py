@@ -1,0 +1,269 @@
+"""GPU parity: every kernel of the HIP path against the FP64 oracle.
+
+Single operations are compared element by element at sizes from the 4^3
+coarsest level (one partial block) to 64^3 (hundreds of blocks), on both
+colours and with array and scalar right-hand sides.  Whole solves are compared
+cycle for cycle.  Tolerances: the kernels and the oracle evaluate the same
+FP64 expressions in different algebraic forms (rationalised root, compact
+Sigma, fused multiply-adds), so single operations agree to a few ulps of the
+largest term (1e-12 relative) and fixed-cycle iterates to 1e-11 relative.
+"""
+import numpy as np
+import pytest
+import torch
+
+import inputs
+import oracle
+import paper_2110_00566_amd as mg
+
+pytestmark = pytest.mark.gpu
+OM = 0.3089
+DEV = "cuda"
+
+
+def g(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def c(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def models(n):
+    return {
+        "dgp": (mg.dgp_params(1.0, OM, 1.0), oracle.dgp_model(1.0, OM, 1.0)),
+        "dgp_h05": (mg.dgp_params(0.7, OM, 0.5), oracle.dgp_model(0.7, OM, 0.5)),
+        "kmo3": (mg.kmo_params(n, 0.02 * n, 3, 1.0, 0.1), oracle.kmo_model(n, 0.02 * n, 3, 1.0, 0.1)),
+        "kmo2": (mg.kmo_params(n, 0.05 * n, 2, 5.0, 0.2), oracle.kmo_model(n, 0.05 * n, 2, 5.0, 0.2)),
+        "poisson": (mg.PoissonParams(1.3), oracle.linear_model(1.3)),
+    }
+
+
+def field(n, seed, amp=1.0):
+    return amp * inputs.gaussian_field(n, seed, lambda k: k ** -3.0)
+
+
+@pytest.mark.parametrize("n", [4, 8, 32, 64])
+@pytest.mark.parametrize("name", ["dgp", "dgp_h05", "kmo3", "kmo2", "poisson"])
+@pytest.mark.parametrize("h", [1.0, 4.0])
+def test_residual_parity(n, name, h):
+    gp, om = models(n)[name]
+    phi = field(n, 1, 3.0 if "kmo" not in name else 0.5)
+    delta = inputs.lognormal_delta(n, 2)
+    f = field(n, 3, 0.1)
+    ref = oracle.residual(om, phi, delta, f, h=h)
+    out = c(mg.op_residual(gp, g(phi), g(delta), g(f), h=h))
+    assert rel(out, ref) <= 1e-12
+    ref_s = oracle.residual(om, phi, delta, 0.25, h=h)
+    out_s = c(mg.op_residual(gp, g(phi), g(delta), 0.25, h=h))
+    assert rel(out_s, ref_s) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [4, 8, 32, 64])
+@pytest.mark.parametrize("name", ["dgp", "kmo3", "kmo2", "poisson"])
+@pytest.mark.parametrize("colour", [0, 1])
+def test_colour_pass_parity(n, name, colour):
+    gp, om = models(n)[name]
+    phi = field(n, 4, 3.0 if "kmo" not in name else 0.5)
+    delta = inputs.lognormal_delta(n, 5)
+    f = field(n, 6, 0.1)
+    for h in (1.0, 2.0):
+        ref = oracle.colour_pass(om, phi, delta, colour, f, h=h)
+        out = c(mg.op_colour_pass(gp, g(phi), g(delta), colour, g(f), h=h))
+        assert rel(out, ref) <= 1e-12
+        # the other colour is untouched, bit for bit
+        k, j, i = np.indices(phi.shape)
+        other = (i + j + k) % 2 != colour
+        assert np.array_equal(out[other], phi[other])
+
+
+@pytest.mark.parametrize("n", [8, 16, 64])
+def test_restrict_and_prolong_parity(n):
+    fine = field(n, 7)
+    assert rel(c(mg.op_restrict(g(fine))), oracle.restrict(fine)) <= 1e-15
+    uc, rc = field(n // 2, 8), field(n // 2, 9)
+    assert rel(c(mg.op_prolong_add(g(fine), g(uc), g(rc))), oracle.prolong_add(fine, uc, rc)) <= 1e-14
+
+
+@pytest.mark.parametrize("n", [4, 8, 32])
+@pytest.mark.parametrize("name", ["dgp", "kmo3", "kmo2", "poisson"])
+def test_transpose_jacobian_parity(n, name):
+    gp, om = models(n)[name]
+    phi = field(n, 10, 3.0 if "kmo" not in name else 0.5)
+    delta = inputs.lognormal_delta(n, 11)
+    v = field(n, 12)
+    for h in (1.0, 2.0):
+        ref = oracle.jac_t_apply(oracle.jac_rows(om, phi, delta, h), v, h)
+        out = c(mg.op_jt_apply(gp, g(phi), g(delta), g(v), h=h))
+        assert rel(out, ref) <= 1e-11
+
+
+# ------------------------------------------------------------- whole solves
+
+def test_config1_fixed_cycles_parity():
+    # 32^3 lognormal (sigma = 1), nDGP H0 r_c = 1, a = 1: three V(1,1) cycles
+    n = 32
+    delta = inputs.lognormal_delta(n, 1)
+    r = oracle.solve(oracle.dgp_model(1.0, OM, 1.0), delta, tol=0.0, max_cycles=3)
+    phi, st = mg.solve_dgp(g(delta), tol=0.0, max_cycles=3)
+    assert st["cycles"] == 3 and r.cycles == 3
+    assert rel(c(phi), r.phi) <= 1e-11
+    assert st["eps0"] == pytest.approx(r.eps0, rel=1e-11)
+    assert np.allclose(st["eps_hist"], r.hist[:3], rtol=1e-9, atol=0)
+    assert st["lam"] == pytest.approx(-r.mu, rel=1e-9)
+
+
+def test_config1_converged_parity():
+    n = 32
+    delta = inputs.lognormal_delta(n, 1)
+    r = oracle.solve(oracle.dgp_model(1.0, OM, 1.0), delta, tol=1e-8)
+    phi, st = mg.solve_dgp(g(delta), tol=1e-8)
+    assert st["status"] == 0 and st["eps"] <= 1e-8
+    assert st["cycles"] == r.cycles
+    assert rel(c(phi), r.phi) <= 1e-10
+    # fifth force -1/2 grad phi (eq:dgp_accel), central differences
+    for ax in range(3):
+        f_g = -0.25 * (np.roll(c(phi), -1, ax) - np.roll(c(phi), 1, ax))
+        f_o = -0.25 * (np.roll(r.phi, -1, ax) - np.roll(r.phi, 1, ax))
+        assert rel(f_g, f_o) <= 1e-9
+
+
+@pytest.mark.parametrize("name,n", [("kmo3", 32), ("kmo2", 32), ("dgp_h05", 64), ("poisson", 32)])
+def test_other_models_fixed_cycles_parity(name, n):
+    gp, om = models(n)[name]
+    delta = inputs.lognormal_delta(n, 3)
+    r = oracle.solve(om, delta, tol=0.0, max_cycles=4)
+    fn = {"kmo3": mg.lib().mg_solve_kmouflage, "kmo2": mg.lib().mg_solve_kmouflage,
+          "dgp_h05": mg.lib().mg_solve_dgp, "poisson": mg.lib().mg_solve_poisson}[name]
+    model = {"kmo3": 1, "kmo2": 1, "dgp_h05": 0, "poisson": 2}[name]
+    phi, st = mg._solve(fn, gp, model, g(delta), None, None, tol=0.0, max_cycles=4)
+    assert rel(c(phi), r.phi) <= 1e-11
+    assert np.allclose(st["eps_hist"], r.hist[:4], rtol=1e-8, atol=1e-300)
+
+
+def test_kmouflage_sphere_converges_like_oracle():
+    # Sec. 4.2.3 stress case: delta = 5000 top-hat, n = 2, beta = 0.2, K0 = 100
+    n = 32
+    d = inputs.tophat_delta(n, 5000.0, 0.1 * n)
+    d -= d.mean()
+    om = oracle.kmo_model(n, float(n), 2, 100.0, 0.2)
+    r = oracle.solve(om, d, tol=1e-9, max_cycles=100)
+    phi, st = mg.solve_kmouflage(g(d), box_mpch=float(n), n_k=2, k0=100.0, beta=0.2, tol=1e-9,
+                                 max_cycles=100)
+    assert st["status"] == 0 and st["cycles"] == r.cycles
+    assert rel(c(phi), r.phi) <= 1e-9
+
+
+def test_initial_guess_and_uniform_density():
+    # Sec. 4.2.1 on the GPU: delta = 0, random phi0 -> constant (0) field
+    n = 32
+    phi0 = inputs.uniform_phi(n, 7)
+    phi, st = mg.solve_dgp(g(np.zeros((n, n, n))), g(phi0), tol=1e-8)
+    assert st["status"] == 0
+    assert np.abs(c(phi)).max() <= 1e-8
+
+
+def test_solve_is_deterministic():
+    n = 64
+    delta = g(inputs.lognormal_delta(n, 1))
+    a, _ = mg.solve_dgp(delta, tol=0.0, max_cycles=2)
+    b, _ = mg.solve_dgp(delta, tol=0.0, max_cycles=2)
+    assert torch.equal(a, b)
+
+
+def test_nonfinite_input_reported():
+    n = 16
+    d = inputs.lognormal_delta(n, 1)
+    d[3, 4, 5] = np.nan
+    with pytest.raises(mg.MGError) as e:
+        mg.solve_dgp(g(d), tol=1e-8)
+    assert e.value.status == mg.MG_ERR_NONFINITE
+
+
+def test_cycle_cap_status():
+    n = 32
+    _, st = mg.solve_dgp(g(inputs.lognormal_delta(n, 1)), tol=1e-14, max_cycles=2)
+    assert st["status"] == mg.MG_NOT_CONVERGED and st["cycles"] == 2
+    assert st["eps"] > 1e-14
+
+
+# ---------------------------------------------------------------- adjoint
+
+@pytest.mark.parametrize("name,n", [("dgp", 16), ("dgp", 32), ("kmo3", 16), ("poisson", 16)])
+def test_adjoint_parity(name, n):
+    gp, om = models(n)[name]
+    delta = inputs.lognormal_delta(n, 4) * (1.0 if "kmo" not in name else 2.0)
+    w = inputs.gaussian_weights(n, 5)
+    phi = oracle.solve(om, delta, tol=1e-13, max_cycles=80).phi
+    r = oracle.adjoint(om, delta, phi, w, tol=0.0, max_cycles=4)
+    model = {"dgp": 0, "kmo3": 1, "poisson": 2}[name]
+    grad, mu, st = mg.solve_adjoint(model, gp, g(delta), g(phi), g(w), tol=0.0, max_cycles=4)
+    assert rel(c(mu), r.mu) <= 1e-10
+    assert rel(c(grad), r.grad) <= 1e-10
+    r2 = oracle.adjoint(om, delta, phi, w, tol=1e-11, max_cycles=80)
+    grad2, mu2, st2 = mg.solve_adjoint(model, gp, g(delta), g(phi), g(w), tol=1e-11,
+                                       max_cycles=80)
+    assert st2["status"] == 0 and st2["cycles"] == r2.cycles
+    assert rel(c(grad2), r2.grad) <= 1e-9
+
+
+def test_autograd_matches_finite_differences():
+    n = 32
+    delta = g(inputs.lognormal_delta(n, 1)).requires_grad_(True)
+    w = g(inputs.gaussian_weights(n, 3))
+    phi = mg.DGPSolve.apply(delta, 1.0, 1.0, OM, 1e-13)
+    (phi * w).sum().backward()
+    cells = inputs.random_cells(n, 8, 4)
+    eps = 1e-4
+    base = delta.detach()
+    for cidx in cells:
+        vals = []
+        for s in (1, -1):
+            d2 = base.clone().view(-1)
+            d2[cidx] += s * eps
+            p2, _ = mg.solve_dgp(d2.view(base.shape), phi.detach(), tol=1e-13, max_cycles=100)
+            vals.append(float((p2 * w).sum()))
+        fd = (vals[0] - vals[1]) / (2 * eps)
+        assert float(delta.grad.view(-1)[cidx]) == pytest.approx(fd, rel=1e-5, abs=1e-9)
+
+
+# -------------------------------------------------------- CIC and PM step
+
+@pytest.mark.parametrize("np_,nm", [(16, 32), (32, 32), (8, 16)])
+def test_cic_parity(np_, nm):
+    pos = inputs.za_particles(np_, nm, 2, amplitude=30.0)
+    _, ref = oracle.cic_density(pos, nm)
+    out = c(mg.cic_delta(g(pos), nm))
+    # fixed point: each of the <= 8 * n_part^3 contributions is rounded to
+    # 2^-33, scaled by n_mesh^3 / n_part^3
+    rho, _ = oracle.cic_density(pos, nm)
+    bound = 8 * (rho.max() + 1) * 2.0 ** -33 * nm ** 3 / np_ ** 3 + 1e-14
+    assert np.abs(out - ref).max() <= bound
+    assert abs(out.mean()) <= 1e-9
+
+
+def test_cic_lattice_is_exactly_uniform():
+    pos = inputs.lattice_positions(16, 32).astype(np.float32)
+    assert np.abs(c(mg.cic_delta(g(pos), 32))).max() == 0.0
+
+
+def test_pm_step_parity():
+    nm, np_ = 32, 16
+    pos = inputs.za_particles(np_, nm, 2, amplitude=30.0)
+    mom = np.zeros_like(pos)
+    p_o, m_o, phi_o, delta_o, phin_o = oracle.pm_step(pos, mom, nm, 1.0, 0.0063, tol=1e-10)
+    gpos, gmom = g(pos), g(mom)
+    phi = torch.zeros((nm,) * 3, dtype=torch.float64, device=DEV)
+    phin = torch.zeros_like(phi)
+    delta, st = mg.pm_step(gpos, gmom, phi, phin, nm, 1.0, 0.0063, tol=1e-10)
+    assert rel(c(delta), delta_o) <= 1e-8
+    assert rel(c(phin), phin_o) <= 1e-8
+    assert rel(c(phi), phi_o) <= 1e-8
+    assert rel(c(gmom), m_o) <= 1e-5
+    dp = np.abs(c(gpos) - p_o)
+    dp = np.minimum(dp, nm - dp)
+    assert dp.max() <= 1e-4
