@@ -19,6 +19,7 @@
 
 #include "../../include/mgglam.h"
 #include "mg_adjoint.h"
+#include "mg_tiled.h"
 
 using namespace mgk;
 
@@ -158,6 +159,74 @@ Coefs coefs(const HLevel &H) {
 
 unsigned nblocks(size_t threads) { return (unsigned)((threads + TPB - 1) / TPB); }
 
+
+// ------------------------------------------------------------ kernel launchers
+// Levels with >= 128 cells per side use the LDS-tiled kernels (64 packed
+// columns x 8 rows per tile); smaller levels and the adjoint use the
+// one-thread-per-cell kernels.
+
+bool tiled_level(int n) { return n >= 128; }
+
+// z-planes per block so that a launch has ~4096 blocks (at least 4 planes).
+TileGeom tile_geom(int n, int planes) {
+    TileGeom G;
+    G.ntx = (n / 2) / TX;
+    G.nty = n / TY;
+    const long per = (long)G.ntx * G.nty;
+    int kz = 64;
+    while (kz > 4 && (long)planes * per / kz < 4096) kz >>= 1;
+    while (planes % kz) kz >>= 1;
+    G.kz = kz;
+    return G;
+}
+
+unsigned tile_blocks(const TileGeom &G, int planes) {
+    return (unsigned)((long)G.ntx * G.nty * (planes / G.kz));
+}
+
+template <int OP>
+void launch_pass(const Mod &M, const Lvl &L, const Coefs &Cf, int c, double *out, const double *fptr,
+                 double fs, unsigned long long *clamp, hipStream_t st) {
+    if (OP != OP_ADJ && tiled_level(L.n)) {
+        const TileGeom G = tile_geom(L.n, L.n);
+        k_pass_tiled<OP == OP_ADJ ? OP_DGP : OP><<<tile_blocks(G, L.n), TPB, 0, st>>>(
+            M, L, c, out, fptr, fs, clamp, G);
+    } else {
+        const size_t half = (size_t)L.n * L.n * L.n / 2;
+        k_pass<OP><<<nblocks(half), TPB, 0, st>>>(M, L, Cf, c, out, fptr, fs, clamp);
+    }
+}
+
+template <int OP, bool REDUCE>
+unsigned launch_resid_restrict(const Mod &M, const Lvl &L, const Coefs &Cf, const double *fptr,
+                               double fs, double *ru0, double *ru1, double *rd0, double *rd1,
+                               double *partials, unsigned long long *clamp, hipStream_t st) {
+    if (OP != OP_ADJ && tiled_level(L.n)) {
+        const TileGeom G = tile_geom(L.n, L.n / 2);
+        const unsigned nb = tile_blocks(G, L.n / 2);
+        k_resid_restrict_tiled<OP == OP_ADJ ? OP_DGP : OP, REDUCE><<<nb, TPB, 0, st>>>(
+            M, L, fptr, fs, ru0, ru1, rd0, rd1, partials, clamp, G);
+        return nb;
+    }
+    const size_t ncoarse = (size_t)L.n * L.n * L.n / 8;
+    const unsigned nb = nblocks(ncoarse);
+    k_resid_restrict<OP, REDUCE><<<nb, TPB, 0, st>>>(M, L, Cf, fptr, fs, ru0, ru1, rd0, rd1,
+                                                     partials, clamp);
+    return nb;
+}
+
+void launch_prolong(double *f0, double *f1, int logn, const double *uc0, const double *uc1,
+                    const double *rc0, const double *rc1, hipStream_t st) {
+    const int n = 1 << logn;
+    if (tiled_level(n)) {
+        const TileGeom G = tile_geom(n, n / 2);
+        k_prolong_tiled<<<tile_blocks(G, n / 2), TPB, 0, st>>>(f0, f1, logn, uc0, uc1, rc0, rc1, G);
+    } else {
+        const size_t cells = (size_t)n * n * n;
+        k_prolong<<<nblocks(cells), TPB, 0, st>>>(f0, f1, logn, uc0, uc1, rc0, rc1);
+    }
+}
+
 // ---------------------------------------------------------------- model set-up
 
 bool setup_dgp(const mg_dgp_params *p, Mod &M) {
@@ -245,8 +314,8 @@ struct Solver {
         }
         const bool timed = C.profile && l == 0 && C.ev_used + 2 <= (int)C.ev.size();
         if (timed) (void)hipEventRecord(C.ev[C.ev_used], C.st);
-        k_pass<OP><<<nblocks(H.half), TPB, 0, C.st>>>(C.M, view(H, l > 0 || OP == OP_ADJ),
-                                                       coefs(H), c, H.spare, fptr, fs, C.clamp);
+        launch_pass<OP>(C.M, view(H, l > 0 || OP == OP_ADJ), coefs(H), c, H.spare, fptr, fs,
+                        C.clamp, C.st);
         if (timed) {
             (void)hipEventRecord(C.ev[C.ev_used + 1], C.st);
             C.ev_used += 2;
@@ -262,22 +331,19 @@ struct Solver {
     // finest residual statistics (and restriction into level 1)
     void resid_restrict(int l) {
         HLevel &H = C.lv[l], &Hc = C.lv[l + 1];
-        const size_t ncoarse = (size_t)Hc.n * Hc.n * Hc.n;
-        const unsigned nb = nblocks(ncoarse);
         const bool with_f = l > 0 || OP == OP_ADJ;
         const double *fptr = (l == 0 && OP != OP_ADJ) ? C.scal + S_MU : nullptr;
         if (l == 0) {
             if (OP == OP_ADJ) mean_of(H.u[0], H.u[1], H.half);
-            k_resid_restrict<OP, true><<<nb, TPB, 0, C.st>>>(C.M, view(H, with_f), coefs(H), fptr,
-                                                             1.0, Hc.ru[0], Hc.ru[1], Hc.f[0],
-                                                             Hc.f[1], C.partials, C.clamp);
+            const unsigned nb = launch_resid_restrict<OP, true>(
+                C.M, view(H, with_f), coefs(H), fptr, 1.0, Hc.ru[0], Hc.ru[1], Hc.f[0], Hc.f[1],
+                C.partials, C.clamp, C.st);
             k_finalize<<<1, 1024, 0, C.st>>>(C.partials, nb, (double)H.n * H.n * H.n, C.scal,
                                              OP == OP_ADJ ? 2 : 0, C.kappa);
         } else {
-            k_resid_restrict<OP, false><<<nb, TPB, 0, C.st>>>(C.M, view(H, with_f), coefs(H),
-                                                              fptr, 1.0, Hc.ru[0], Hc.ru[1],
-                                                              Hc.f[0], Hc.f[1], C.partials,
-                                                              C.clamp);
+            launch_resid_restrict<OP, false>(C.M, view(H, with_f), coefs(H), fptr, 1.0, Hc.ru[0],
+                                             Hc.ru[1], Hc.f[0], Hc.f[1], C.partials, C.clamp,
+                                             C.st);
         }
     }
 
@@ -287,17 +353,65 @@ struct Solver {
         L.u0 = Hc.ru[0];
         L.u1 = Hc.ru[1];
         const double *shift = (lc == 1 && OP != OP_ADJ) ? C.scal + S_SHIFT : nullptr;
-        k_coarse_source<OP><<<nblocks(2 * Hc.half), TPB, 0, C.st>>>(
-            C.M, L, coefs(Hc), Hc.f[0], Hc.f[1], Hc.u[0], Hc.u[1], shift);
+        if (OP != OP_ADJ && tiled_level(Hc.n)) {
+            const TileGeom G = tile_geom(Hc.n, Hc.n);
+            k_coarse_source_tiled<OP == OP_ADJ ? OP_DGP : OP><<<tile_blocks(G, Hc.n), TPB, 0, C.st>>>(
+                C.M, L, Hc.f[0], Hc.f[1], Hc.u[0], Hc.u[1], shift, G);
+        } else {
+            k_coarse_source<OP><<<nblocks(2 * Hc.half), TPB, 0, C.st>>>(
+                C.M, L, coefs(Hc), Hc.f[0], Hc.f[1], Hc.u[0], Hc.u[1], shift);
+        }
     }
 
     void prolong(int l) {
         HLevel &H = C.lv[l], &Hc = C.lv[l + 1];
-        k_prolong<<<nblocks(2 * H.half), TPB, 0, C.st>>>(H.u[0], H.u[1], H.logn, Hc.u[0],
-                                                         Hc.u[1], Hc.ru[0], Hc.ru[1]);
+        launch_prolong(H.u[0], H.u[1], H.logn, Hc.u[0], Hc.u[1], Hc.ru[0], Hc.ru[1], C.st);
+    }
+
+    // Levels l.. (all <= 16^3, l >= 1) in one single-workgroup launch.
+    void tail(int l) {
+        TailArgs A;
+        A.nlev = C.nlev - l;
+        A.nu1 = C.nu1;
+        A.nu2 = C.nu2;
+        A.nuc = C.nuc;
+        for (int q = 0; q < A.nlev; ++q) {
+            HLevel &H = C.lv[l + q];
+            A.lv[q].L = view(H, true);
+            A.lv[q].ru0 = H.ru[0];
+            A.lv[q].ru1 = H.ru[1];
+            A.cf[q] = coefs(H);
+        }
+        const size_t lds = sizeof(double) * tail_lds_doubles(C.lv[l].logn, A.nlev);
+        switch (A.nlev) {
+            case 1: launch_tail<1>(A, lds); break;
+            case 2: launch_tail<2>(A, lds); break;
+            default: launch_tail<3>(A, lds); break;
+        }
+    }
+
+    template <int NL>
+    void launch_tail(const TailArgs &A, size_t lds) {
+        static bool attr_set = false;   // per instantiation, process-wide
+        if (!attr_set) {
+            (void)hipFuncSetAttribute((const void *)k_tail<OP, NL>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            attr_set = true;
+        }
+        k_tail<OP, NL><<<1, TAIL_THREADS, lds, C.st>>>(C.M, A);
+    }
+
+    int tail_start() const {
+        for (int l = 1; l < C.nlev; ++l)
+            if (C.lv[l].n <= TAIL_MAX_N && C.nlev - l <= TAIL_MAX_LEVELS) return l;
+        return C.nlev;   // no tail (single-level hierarchy)
     }
 
     void vcycle(int l) {
+        if (l > 0 && l == tail_start()) {
+            tail(l);
+            return;
+        }
         if (l == C.nlev - 1) {
             for (int s = 0; s < C.nuc; ++s) sweep(l);
             return;
@@ -566,8 +680,8 @@ void op_residual_launch(const Mod &M, OpWs &W, const double *fptr, hipStream_t s
 template <int OP>
 void op_pass_launch(const Mod &M, OpWs &W, int colour, hipStream_t s, bool with_f) {
     HLevel &H = W.H;
-    k_pass<OP><<<nblocks(H.half), TPB, 0, s>>>(M, view(H, with_f), coefs(H), colour,
-                                               colour ? W.out[1] : W.out[0], nullptr, 0.0, nullptr);
+    launch_pass<OP>(M, view(H, with_f), coefs(H), colour, colour ? W.out[1] : W.out[0], nullptr,
+                    0.0, nullptr, s);
 }
 }  // namespace
 
@@ -757,8 +871,7 @@ mg_status mg_op_prolong_add(int n, double *fine, const double *uc, const double 
     k_pack<<<nblocks(2 * H.half), TPB, 0, stream>>>(fine, H.logn, H.u[0], H.u[1], nullptr);
     k_pack<<<nbc, TPB, 0, stream>>>(uc, H.logn - 1, W.coarse[0], W.coarse[1], nullptr);
     k_pack<<<nbc, TPB, 0, stream>>>(rc_, H.logn - 1, W.out[0], W.out[1], nullptr);
-    k_prolong<<<nblocks(2 * H.half), TPB, 0, stream>>>(H.u[0], H.u[1], H.logn, W.coarse[0],
-                                                       W.coarse[1], W.out[0], W.out[1]);
+    launch_prolong(H.u[0], H.u[1], H.logn, W.coarse[0], W.coarse[1], W.out[0], W.out[1], stream);
     k_unpack<<<nblocks(2 * H.half), TPB, 0, stream>>>(H.u[0], H.u[1], H.logn, fine, nullptr);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(stream));

@@ -139,16 +139,13 @@ __device__ __forceinline__ void block_sum2(double a, double b, double *partials,
 // cell, restricted (8-cell mean) together with u.  With REDUCE the block
 // sums of d and d^2 go to partials (finest level: residual norm and mean).
 template <int OP, bool REDUCE>
-__global__ __launch_bounds__(TPB) void k_resid_restrict(Mod M, Lvl L, Coefs Cf, const double *fptr,
-                                                        double fscale, double *ru0, double *ru1,
-                                                        double *rd0, double *rd1,
-                                                        double *partials,
-                                                        unsigned long long *clamp) {
-    const size_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const size_t t = blk * TPB + threadIdx.x;
+__device__ __forceinline__ void dev_resid_restrict(const Mod &M, const Lvl &L, const Coefs &Cf,
+                                                   const double *fptr, double fscale, double *ru0,
+                                                   double *ru1, double *rd0, double *rd1,
+                                                   unsigned long long *clamp, size_t t, double &s1,
+                                                   double &s2) {
     const int lnc = L.logn - 1, nc = 1 << lnc;
     const size_t ncoarse = (size_t)1 << (3 * lnc);
-    double s1 = 0.0, s2 = 0.0;
     if (t < ncoarse) {
         const int I = (int)(t & (nc - 1));
         const int J = (int)((t >> lnc) & (nc - 1));
@@ -177,16 +174,27 @@ __global__ __launch_bounds__(TPB) void k_resid_restrict(Mod M, Lvl L, Coefs Cf, 
         (ccol ? ru1 : ru0)[cidx] = 0.125 * su;
         (ccol ? rd1 : rd0)[cidx] = 0.125 * sd;
     }
+}
+
+template <int OP, bool REDUCE>
+__global__ __launch_bounds__(TPB) void k_resid_restrict(Mod M, Lvl L, Coefs Cf, const double *fptr,
+                                                        double fscale, double *ru0, double *ru1,
+                                                        double *rd0, double *rd1,
+                                                        double *partials,
+                                                        unsigned long long *clamp) {
+    const size_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const size_t t = blk * TPB + threadIdx.x;
+    double s1 = 0.0, s2 = 0.0;
+    dev_resid_restrict<OP, REDUCE>(M, L, Cf, fptr, fscale, ru0, ru1, rd0, rd1, clamp, t, s1, s2);
     if (REDUCE) block_sum2(s1, s2, partials, blk);
 }
 
 // FAS source on the coarse level: S = L^H(R u) - (R d - shift), written over
 // the restricted residual; the coarse unknown starts from R u.
 template <int OP>
-__global__ __launch_bounds__(TPB) void k_coarse_source(Mod M, Lvl Lc, Coefs Cf, double *s0,
-                                                       double *s1, double *u0, double *u1,
-                                                       const double *shift) {
-    const size_t t = xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
+__device__ __forceinline__ void dev_coarse_source(const Mod &M, const Lvl &Lc, const Coefs &Cf,
+                                                  double *s0, double *s1, double *u0, double *u1,
+                                                  const double *shift, size_t t) {
     const size_t half = (size_t)1 << (3 * Lc.logn - 1);
     if (t >= 2 * half) return;
     const int c = t >= half;
@@ -203,11 +211,18 @@ __global__ __launch_bounds__(TPB) void k_coarse_source(Mod M, Lvl Lc, Coefs Cf, 
     (c ? u1 : u0)[tt] = ru;
 }
 
-// u_fine += P(uc - rc) with the cell-centred trilinear weights 27/9/3/1 (/64).
-__global__ __launch_bounds__(TPB) void k_prolong(double *f0, double *f1, int logn,
-                                                 const double *uc0, const double *uc1,
-                                                 const double *rc0, const double *rc1) {
+template <int OP>
+__global__ __launch_bounds__(TPB) void k_coarse_source(Mod M, Lvl Lc, Coefs Cf, double *s0,
+                                                       double *s1, double *u0, double *u1,
+                                                       const double *shift) {
     const size_t t = xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
+    dev_coarse_source<OP>(M, Lc, Cf, s0, s1, u0, u1, shift, t);
+}
+
+// u_fine += P(uc - rc) with the cell-centred trilinear weights 27/9/3/1 (/64).
+__device__ __forceinline__ void dev_prolong(double *f0, double *f1, int logn, const double *uc0,
+                                            const double *uc1, const double *rc0,
+                                            const double *rc1, size_t t) {
     const int n = 1 << logn, lognh = logn - 1;
     const size_t half = (size_t)1 << (3 * logn - 1);
     if (t >= 2 * half) return;
@@ -231,6 +246,13 @@ __global__ __launch_bounds__(TPB) void k_prolong(double *f0, double *f1, int log
         acc += w * v;
     }
     (c ? f1 : f0)[tt] += acc * (1.0 / 64.0);
+}
+
+__global__ __launch_bounds__(TPB) void k_prolong(double *f0, double *f1, int logn,
+                                                 const double *uc0, const double *uc1,
+                                                 const double *rc0, const double *rc1) {
+    const size_t t = xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
+    dev_prolong(f0, f1, logn, uc0, uc1, rc0, rc1, t);
 }
 
 // 8-cell mean of a packed field (density hierarchy, linearisation points).
@@ -363,6 +385,162 @@ __global__ __launch_bounds__(TPB) void k_residual(Mod M, Lvl L, Coefs Cf, const 
     const double term = cell_term<OP>(M, L, Cf, c, m, j, k, faces, clamp);
     const double u = (c ? L.u1 : L.u0)[tt];
     (c ? r1 : r0)[tt] = (faces - 6.0 * u) / L.h2 - term - rhs_at(L, c, tt, fptr, fscale);
+}
+
+}  // namespace mgk
+
+namespace mgk {
+
+// ---------------------------------------------------------------- coarse tail
+// All levels from 16^3 down to 4^3 in one workgroup: the sub-cycle (smoothing,
+// residual + restriction, coarse source, recursion, prolongation) runs with
+// barriers between phases instead of one launch per phase.  A colour pass
+// first computes every new value of the colour into registers, then writes
+// them in place after a barrier, so all cells see the pre-pass state.
+constexpr int TAIL_THREADS = 1024;
+constexpr int TAIL_MAX_N = 16;   // <= 2048 cells per colour: 2 per thread
+constexpr int TAIL_MAX_LEVELS = 3;
+
+struct TailLv {
+    Lvl L;        // u, d and f (the FAS source, workspace: written by the tail) of the level
+    double *ru0, *ru1;   // R u of the finer level (unused on the first tail level)
+};
+
+struct TailArgs {
+    int nlev, nu1, nu2, nuc;
+    TailLv lv[TAIL_MAX_LEVELS];
+    Coefs cf[TAIL_MAX_LEVELS];
+};
+
+template <int OP>
+__device__ void tail_pass(const Mod &M, const TailLv &T, const Coefs &Cf, int c) {
+    const Lvl &L = T.L;
+    const int half = 1 << (3 * L.logn - 1);
+    double nv[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int t = threadIdx.x + q * TAIL_THREADS;
+        if (t < half) {
+            const int m = t & ((1 << L.lognh) - 1);
+            const int j = (t >> L.lognh) & (L.n - 1);
+            const int k = t >> (L.lognh + L.logn);
+            double faces;
+            const double K = cell_term<OP>(M, L, Cf, c, m, j, k, faces, nullptr);
+            nv[q] = (faces - L.h2 * (K + (c ? L.f1 : L.f0)[t])) * (1.0 / 6.0);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int t = threadIdx.x + q * TAIL_THREADS;
+        if (t < half) (c ? L.u1 : L.u0)[t] = nv[q];
+    }
+    __syncthreads();
+}
+
+template <int OP>
+__device__ void tail_sweeps(const Mod &M, const TailLv &T, const Coefs &Cf, int count) {
+    for (int s = 0; s < count; ++s) {
+        tail_pass<OP>(M, T, Cf, 0);
+        tail_pass<OP>(M, T, Cf, 1);
+    }
+}
+
+// Doubles of LDS the tail needs for levels l0 .. (u, d, f of every level,
+// R u of every level below the first).
+__host__ __device__ inline int tail_lds_doubles(int logn0, int nl) {
+    int tot = 0;
+    for (int q = 0; q < nl; ++q) tot += (q ? 8 : 6) * (1 << (3 * (logn0 - q) - 1));
+    return tot;
+}
+
+template <int OP, int NL>
+__device__ __forceinline__ void tail_down(const Mod &M, TailLv (&T)[NL], const Coefs (&Cf)[NL],
+                                          int nu1) {
+#pragma unroll
+    for (int l = 0; l < NL - 1; ++l) {
+        tail_sweeps<OP>(M, T[l], Cf[l], nu1);
+        TailLv &Tc = T[l + 1];
+        double s1 = 0.0, s2 = 0.0;
+        const int ncoarse = 1 << (3 * Tc.L.logn);
+        for (int t = threadIdx.x; t < ncoarse; t += TAIL_THREADS)
+            dev_resid_restrict<OP, false>(M, T[l].L, Cf[l], nullptr, 0.0, Tc.ru0, Tc.ru1,
+                                          const_cast<double *>(Tc.L.f0),
+                                          const_cast<double *>(Tc.L.f1), nullptr, (size_t)t, s1,
+                                          s2);
+        __syncthreads();
+        Lvl Lr = Tc.L;
+        Lr.u0 = Tc.ru0;
+        Lr.u1 = Tc.ru1;
+        for (int t = threadIdx.x; t < ncoarse; t += TAIL_THREADS)
+            dev_coarse_source<OP>(M, Lr, Cf[l + 1], const_cast<double *>(Tc.L.f0),
+                                  const_cast<double *>(Tc.L.f1), Tc.L.u0, Tc.L.u1, nullptr,
+                                  (size_t)t);
+        __syncthreads();
+    }
+}
+
+template <int OP, int NL>
+__device__ __forceinline__ void tail_up(const Mod &M, TailLv (&T)[NL], const Coefs (&Cf)[NL],
+                                        int nu2) {
+#pragma unroll
+    for (int l = NL - 2; l >= 0; --l) {
+        const TailLv &Tf = T[l], &Tc = T[l + 1];
+        const int nfine = 1 << (3 * Tf.L.logn);
+        for (int t = threadIdx.x; t < nfine; t += TAIL_THREADS)
+            dev_prolong(Tf.L.u0, Tf.L.u1, Tf.L.logn, Tc.L.u0, Tc.L.u1, Tc.ru0, Tc.ru1, (size_t)t);
+        __syncthreads();
+        tail_sweeps<OP>(M, Tf, Cf[l], nu2);
+    }
+}
+
+__device__ __forceinline__ void lds_copy(double *dst, const double *src, int n) {
+    for (int t = threadIdx.x; t < n; t += TAIL_THREADS) dst[t] = src[t];
+}
+
+// The tail levels live in LDS for the whole sub-cycle: their fields are
+// copied in, the sub-cycle runs on LDS, and the first level's u goes back.
+template <int OP, int NL>
+__global__ __launch_bounds__(TAIL_THREADS) void k_tail(Mod M, TailArgs A) {
+    extern __shared__ double lds[];
+    TailLv T[NL];
+    Coefs Cf[NL];
+    double *p = lds;
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+        const TailLv &G = A.lv[q];
+        const int half = 1 << (3 * G.L.logn - 1);
+        T[q] = G;
+        Cf[q] = A.cf[q];
+        double *u0 = p, *u1 = p + half, *d0 = p + 2 * half, *d1 = p + 3 * half;
+        double *f0 = p + 4 * half, *f1 = p + 5 * half;
+        p += 6 * half;
+        T[q].L.u0 = u0;
+        T[q].L.u1 = u1;
+        T[q].L.d0 = d0;
+        T[q].L.d1 = d1;
+        T[q].L.f0 = f0;
+        T[q].L.f1 = f1;
+        lds_copy(d0, G.L.d0, half);
+        lds_copy(d1, G.L.d1, half);
+        if (q == 0) {
+            lds_copy(u0, G.L.u0, half);
+            lds_copy(u1, G.L.u1, half);
+            lds_copy(f0, G.L.f0, half);
+            lds_copy(f1, G.L.f1, half);
+        } else {
+            T[q].ru0 = p;
+            T[q].ru1 = p + half;
+            p += 2 * half;
+        }
+    }
+    __syncthreads();
+    tail_down<OP, NL>(M, T, Cf, A.nu1);
+    tail_sweeps<OP>(M, T[NL - 1], Cf[NL - 1], A.nuc);
+    tail_up<OP, NL>(M, T, Cf, A.nu2);
+    const int half0 = 1 << (3 * A.lv[0].L.logn - 1);
+    lds_copy(A.lv[0].L.u0, T[0].L.u0, half0);
+    lds_copy(A.lv[0].L.u1, T[0].L.u1, half0);
 }
 
 }  // namespace mgk

@@ -1,0 +1,395 @@
+// LDS-tiled versions of the three kernels that touch every finest-level cell
+// (colour pass, residual + restriction, prolongation), for levels with at
+// least 128 cells per side.
+//
+// A block owns a tile of TX = 64 packed x-columns (one wave wide) and TY = 8
+// rows and marches through a z-chunk.  The planes it needs are staged once in
+// LDS (tile plus a one-cell halo, periodic wrap) in a small ring, and the next
+// plane is prefetched into registers while the current one is computed, so
+// each global value is read about once per block instead of once per
+// neighbouring thread.  Consecutive logical blocks are neighbours in y; the XCD
+// remapping keeps a whole z-slab on one XCD so y-halos are L2 hits.
+#pragma once
+#include "mg_kernels.h"
+
+namespace mgk {
+
+constexpr int TX = 64, TY = 8, TXH = TX + 2, TYH = TY + 2;
+constexpr int TPLANE = TXH * TYH;   // 660 values per staged plane
+constexpr int TLOADS = (TPLANE + TPB - 1) / TPB;
+
+struct TileGeom {
+    int ntx, nty, kz;   // tiles in x, tiles in y, planes per block
+};
+
+__device__ __forceinline__ size_t tile_gidx(int e, int j0, int m0, int k, int logn, int lognh) {
+    const int r = e / TXH, q = e - r * TXH;
+    const int nm1 = (1 << logn) - 1, hm1 = (1 << lognh) - 1;
+    const int j = (j0 - 1 + r) & nm1, m = (m0 - 1 + q) & hm1;
+    return prow(j, k & nm1, logn, lognh) + m;
+}
+
+// Stencil of the cell at local (r, q) (halo-shifted tile coordinates) with
+// packed-x parity p, from staged planes: B = opposite colour at plane k,
+// A = own colour at k-1 / k / k+1, Bz = opposite colour at k-1 / k+1.
+__device__ __forceinline__ Nb lds_nb(const double *Am, const double *A0, const double *Ap,
+                                     const double *B0, const double *Bm, const double *Bp, int r,
+                                     int q, int p) {
+    const int qp = q + p, qm = q + p - 1;
+    const int o = r * TXH, op = (r + 1) * TXH, om = (r - 1) * TXH;
+    Nb s;
+    s.xp = B0[o + qp];
+    s.xm = B0[o + qm];
+    s.yp = B0[op + q];
+    s.ym = B0[om + q];
+    s.zp = Bp[o + q];
+    s.zm = Bm[o + q];
+    s.nxy = (A0[op + qp] + A0[om + qm]) - (A0[om + qp] + A0[op + qm]);
+    s.nxz = (Ap[o + qp] + Am[o + qm]) - (Am[o + qp] + Ap[o + qm]);
+    s.nyz = (Ap[op + q] + Am[om + q]) - (Am[op + q] + Ap[om + q]);
+    return s;
+}
+
+// One colour pass (see k_pass) on an LDS-staged tile.
+template <int OP>
+__global__ __launch_bounds__(TPB) void k_pass_tiled(Mod M, Lvl L, int c, double *__restrict__ out,
+                                                    const double *fptr, double fscale,
+                                                    unsigned long long *clamp, TileGeom G) {
+    __shared__ double sA[3][TPLANE], sB[3][TPLANE];
+    const size_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int bx = (int)(blk % G.ntx);
+    const int by = (int)((blk / G.ntx) % G.nty);
+    const int bz = (int)(blk / ((size_t)G.ntx * G.nty));
+    const int m0 = bx * TX, j0 = by * TY, k0 = bz * G.kz;
+    const double *A = c ? L.u1 : L.u0;
+    const double *B = c ? L.u0 : L.u1;
+    const double *D = c ? L.d1 : L.d0;
+    const double *F = c ? L.f1 : L.f0;
+    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+    const double fs = fptr ? fscale * (*fptr) : 0.0;
+    double ra[TLOADS], rb[TLOADS];
+    auto fetch = [&](int k) {
+#pragma unroll
+        for (int q = 0; q < TLOADS; ++q) {
+            const int e = tid + q * TPB;
+            if (e < TPLANE) {
+                const size_t g = tile_gidx(e, j0, m0, k, L.logn, L.lognh);
+                ra[q] = A[g];
+                rb[q] = B[g];
+            }
+        }
+    };
+    auto store = [&](int slot) {
+#pragma unroll
+        for (int q = 0; q < TLOADS; ++q) {
+            const int e = tid + q * TPB;
+            if (e < TPLANE) {
+                sA[slot][e] = ra[q];
+                sB[slot][e] = rb[q];
+            }
+        }
+    };
+    // own cells' delta and f, one plane ahead
+    double dn[2], fn[2];
+    auto fetch_cells = [&](int k) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const size_t idx = prow(j0 + ty + 4 * h, k, L.logn, L.lognh) + m0 + tx;
+            dn[h] = D[idx];
+            fn[h] = F ? F[idx] : 0.0;
+        }
+    };
+    // slot of plane k: (k - k0 + 1) mod 3
+    fetch(k0 - 1);
+    store(0);
+    fetch(k0);
+    store(1);
+    fetch(k0 + 1);
+    fetch_cells(k0);
+    for (int k = k0; k < k0 + G.kz; ++k) {
+        const int sm = (k - k0) % 3, s0 = (k - k0 + 1) % 3, sp = (k - k0 + 2) % 3;
+        store(sp);
+        const double d0 = dn[0], d1 = dn[1], f0 = fn[0], f1 = fn[1];
+        __syncthreads();
+        if (k + 2 <= k0 + G.kz) fetch(k + 2);
+        if (k + 1 < k0 + G.kz) fetch_cells(k + 1);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int row = ty + 4 * h;
+            const int j = j0 + row, m = m0 + tx;
+            const int p = (j + k + c) & 1;
+            const Nb s = lds_nb(sA[sm], sA[s0], sA[sp], sB[s0], sB[sm], sB[sp], row + 1, tx + 1, p);
+            const size_t idx = prow(j, k, L.logn, L.lognh) + m;
+            const double faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
+            const double K = model_term<OP>(M, L, s, h ? d1 : d0, clamp);
+            const double f = (h ? f1 : f0) + fs;
+            out[idx] = (faces - L.h2 * (K + f)) * (1.0 / 6.0);
+        }
+        __syncthreads();
+    }
+}
+
+// Residual + restriction (see k_resid_restrict) for a tile of 64 x 4 coarse
+// cells marching over coarse planes: fine planes 2K-1 .. 2K+2 of both colours
+// are staged (ring of 4), two new fine planes per coarse plane.
+template <int OP, bool REDUCE>
+__global__ __launch_bounds__(TPB) void k_resid_restrict_tiled(Mod M, Lvl L, const double *fptr,
+                                                              double fscale, double *ru0,
+                                                              double *ru1, double *rd0,
+                                                              double *rd1, double *partials,
+                                                              unsigned long long *clamp,
+                                                              TileGeom G) {
+    __shared__ double s0[4][TPLANE], s1[4][TPLANE];
+    const size_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int bx = (int)(blk % G.ntx);
+    const int by = (int)((blk / G.ntx) % G.nty);
+    const int bz = (int)(blk / ((size_t)G.ntx * G.nty));
+    // fine tile: packed columns m0.., fine rows j0 .. j0+7 (coarse rows j0/2 ..)
+    const int m0 = bx * TX, j0 = by * TY, K0 = bz * G.kz;
+    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+    const int lnc = L.logn - 1;
+    // two planes in flight: (a0, a1) and (b0, b1) hold colours 0 and 1
+    double a0[TLOADS], a1[TLOADS], b0[TLOADS], b1[TLOADS];
+    auto fetch = [&](int k, double *x0, double *x1) {
+#pragma unroll
+        for (int q = 0; q < TLOADS; ++q) {
+            const int e = tid + q * TPB;
+            if (e < TPLANE) {
+                const size_t g = tile_gidx(e, j0, m0, k, L.logn, L.lognh);
+                x0[q] = L.u0[g];
+                x1[q] = L.u1[g];
+            }
+        }
+    };
+    auto store = [&](int slot, const double *x0, const double *x1) {
+#pragma unroll
+        for (int q = 0; q < TLOADS; ++q) {
+            const int e = tid + q * TPB;
+            if (e < TPLANE) {
+                s0[slot][e] = x0[q];
+                s1[slot][e] = x1[q];
+            }
+        }
+    };
+    const int I = m0 + tx, J = (j0 >> 1) + ty;
+    // the 8 children's delta and f, one coarse plane ahead
+    double dn[8], fn[8];
+    auto fetch_cells = [&](int K) {
+#pragma unroll
+        for (int qc = 0; qc < 8; ++qc) {
+            const int a = qc & 1, b = (qc >> 1) & 1, cc = qc >> 2;
+            const int col = (a + b + cc) & 1;
+            const size_t idx = prow(2 * J + b, 2 * K + cc, L.logn, L.lognh) + I;
+            dn[qc] = (col ? L.d1 : L.d0)[idx];
+            const double *F = col ? L.f1 : L.f0;
+            fn[qc] = F ? F[idx] : 0.0;
+        }
+    };
+    // slot of fine plane k: (k - 2K0 + 1) & 3
+    fetch(2 * K0 - 1, a0, a1);
+    fetch(2 * K0, b0, b1);
+    store(0, a0, a1);
+    store(1, b0, b1);
+    fetch(2 * K0 + 1, a0, a1);
+    fetch(2 * K0 + 2, b0, b1);
+    fetch_cells(K0);
+    double acc1 = 0.0, acc2 = 0.0;
+    const double fs = fptr ? fscale * (*fptr) : 0.0;
+    const double inv_h2 = 1.0 / L.h2;
+    for (int K = K0; K < K0 + G.kz; ++K) {
+        store((2 * K + 1 - 2 * K0 + 1) & 3, a0, a1);
+        store((2 * K + 2 - 2 * K0 + 1) & 3, b0, b1);
+        double dc[8], fc[8];
+#pragma unroll
+        for (int qc = 0; qc < 8; ++qc) {
+            dc[qc] = dn[qc];
+            fc[qc] = fn[qc];
+        }
+        __syncthreads();
+        if (K + 1 < K0 + G.kz) {
+            fetch(2 * K + 3, a0, a1);
+            fetch(2 * K + 4, b0, b1);
+            fetch_cells(K + 1);
+        }
+        double sd = 0.0, su = 0.0;
+#pragma unroll
+        for (int qc = 0; qc < 8; ++qc) {
+            const int a = qc & 1, b = (qc >> 1) & 1, cc = qc >> 2;
+            const int k = 2 * K + cc, j = 2 * J + b;
+            const int col = (a + b + cc) & 1;
+            const int sm = (k - 1 - 2 * K0 + 1) & 3, sz = (k - 2 * K0 + 1) & 3,
+                      sp = (k + 1 - 2 * K0 + 1) & 3;
+            const double *Am = col ? s1[sm] : s0[sm];
+            const double *A0 = col ? s1[sz] : s0[sz];
+            const double *Ap = col ? s1[sp] : s0[sp];
+            const double *Bm = col ? s0[sm] : s1[sm];
+            const double *B0 = col ? s0[sz] : s1[sz];
+            const double *Bp = col ? s0[sp] : s1[sp];
+            const int r = 2 * ty + b + 1, q = tx + 1;
+            const Nb s = lds_nb(Am, A0, Ap, B0, Bm, Bp, r, q, a);
+            const double u = A0[r * TXH + q];
+            const double faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
+            const double f = fc[qc] + fs;
+            (void)j;
+            const double d = (faces - 6.0 * u) * inv_h2 - model_term<OP>(M, L, s, dc[qc], clamp) - f;
+            sd += d;
+            su += u;
+            if (REDUCE) {
+                acc1 += d;
+                acc2 += d * d;
+            }
+        }
+        const size_t cidx = ((size_t)K << (2 * lnc - 1)) + ((size_t)J << (lnc - 1)) + (I >> 1);
+        const int ccol = (I + J + K) & 1;
+        (ccol ? ru1 : ru0)[cidx] = 0.125 * su;
+        (ccol ? rd1 : rd0)[cidx] = 0.125 * sd;
+        __syncthreads();
+    }
+    if (REDUCE) block_sum2(acc1, acc2, partials, blk);
+}
+
+// u_fine += P(uc - rc) (see k_prolong) with the coarse difference staged in
+// LDS: 66 coarse columns x 6 coarse rows, ring of 3 coarse planes.
+__global__ __launch_bounds__(TPB) void k_prolong_tiled(double *f0, double *f1, int logn,
+                                                       const double *uc0, const double *uc1,
+                                                       const double *rc0, const double *rc1,
+                                                       TileGeom G) {
+    constexpr int CR = TY / 2 + 2;   // coarse rows staged
+    constexpr int CPL = TXH * CR;    // 396 values per coarse plane
+    __shared__ double sE[3][CPL];
+    const size_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int bx = (int)(blk % G.ntx);
+    const int by = (int)((blk / G.ntx) % G.nty);
+    const int bz = (int)(blk / ((size_t)G.ntx * G.nty));
+    const int m0 = bx * TX, j0 = by * TY, K0 = bz * G.kz;   // kz counts coarse planes
+    const int lnc = logn - 1, ncm1 = (1 << lnc) - 1;
+    const int lognh = logn - 1;
+    const int tid = threadIdx.x;
+    double re[2];
+    auto fetch = [&](int K) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int e = tid + q * TPB;
+            if (e < CPL) {
+                const int r = e / TXH, cI = e - r * TXH;
+                const int I = (m0 - 1 + cI) & ncm1;
+                const int J = ((j0 >> 1) - 1 + r) & ncm1;
+                const int Kw = K & ncm1;
+                const size_t idx = ((size_t)Kw << (2 * lnc - 1)) + ((size_t)J << (lnc - 1)) + (I >> 1);
+                re[q] = ((I + J + Kw) & 1) ? (uc1[idx] - rc1[idx]) : (uc0[idx] - rc0[idx]);
+            }
+        }
+    };
+    auto store = [&](int slot) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int e = tid + q * TPB;
+            if (e < CPL) sE[slot][e] = re[q];
+        }
+    };
+    // slot of coarse plane K: (K - K0 + 1) mod 3
+    fetch(K0 - 1);
+    store(0);
+    fetch(K0);
+    store(1);
+    fetch(K0 + 1);
+    for (int K = K0; K < K0 + G.kz; ++K) {
+        store((K - K0 + 2) % 3);
+        __syncthreads();
+        if (K + 2 <= K0 + G.kz) fetch(K + 2);
+        // 2 fine planes x 8 rows x 64 columns x 2 colours = 2048 cells, 8 per thread
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+            const int cell = tid + h * TPB;
+            const int tx = cell & 63, row = (cell >> 6) & 7, c = (cell >> 9) & 1, kk = cell >> 10;
+            const int k = 2 * K + kk, j = j0 + row, m = m0 + tx;
+            const int p = (j + k + c) & 1;
+            const int di = p ? 1 : -1, dj = (j & 1) ? 1 : -1, dk = kk ? 1 : -1;
+            const int lc = tx + 1, lr = (j >> 1) - (j0 >> 1) + 1;
+            double acc = 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int a = q & 1, b = (q >> 1) & 1, cc = q >> 2;
+                const int slot = (K + cc * dk - K0 + 1 + 3) % 3;
+                const double w = (a ? 1.0 : 3.0) * (b ? 1.0 : 3.0) * (cc ? 1.0 : 3.0);
+                acc += w * sE[slot][(lr + b * dj) * TXH + lc + a * di];
+            }
+            const size_t idx = prow(j, k, logn, lognh) + m;
+            (c ? f1 : f0)[idx] += acc * (1.0 / 64.0);
+        }
+        __syncthreads();
+    }
+}
+
+// FAS source on a coarse level (see k_coarse_source) on an LDS-staged tile:
+// S = L(R u) - (R d - shift) at both colours, written over R d, and u = R u.
+template <int OP>
+__global__ __launch_bounds__(TPB) void k_coarse_source_tiled(Mod M, Lvl Lc, double *s0,
+                                                             double *s1, double *u0, double *u1,
+                                                             const double *shift, TileGeom G) {
+    __shared__ double sA[3][TPLANE], sB[3][TPLANE];   // colour 0 / colour 1 of R u
+    const size_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int bx = (int)(blk % G.ntx);
+    const int by = (int)((blk / G.ntx) % G.nty);
+    const int bz = (int)(blk / ((size_t)G.ntx * G.nty));
+    const int m0 = bx * TX, j0 = by * TY, k0 = bz * G.kz;
+    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+    const double sh = shift ? *shift : 0.0;
+    double ra[TLOADS], rb[TLOADS];
+    auto fetch = [&](int k) {
+#pragma unroll
+        for (int q = 0; q < TLOADS; ++q) {
+            const int e = tid + q * TPB;
+            if (e < TPLANE) {
+                const size_t g = tile_gidx(e, j0, m0, k, Lc.logn, Lc.lognh);
+                ra[q] = Lc.u0[g];
+                rb[q] = Lc.u1[g];
+            }
+        }
+    };
+    auto store = [&](int slot) {
+#pragma unroll
+        for (int q = 0; q < TLOADS; ++q) {
+            const int e = tid + q * TPB;
+            if (e < TPLANE) {
+                sA[slot][e] = ra[q];
+                sB[slot][e] = rb[q];
+            }
+        }
+    };
+    fetch(k0 - 1);
+    store(0);
+    fetch(k0);
+    store(1);
+    fetch(k0 + 1);
+    for (int k = k0; k < k0 + G.kz; ++k) {
+        const int sm = (k - k0) % 3, sz = (k - k0 + 1) % 3, sp = (k - k0 + 2) % 3;
+        store(sp);
+        __syncthreads();
+        if (k + 2 <= k0 + G.kz) fetch(k + 2);
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int row = ty + 4 * (h & 1), c = h >> 1;
+            const int j = j0 + row, m = m0 + tx;
+            const int p = (j + k + c) & 1;
+            const double *(Am) = c ? sB[sm] : sA[sm];
+            const double *(A0) = c ? sB[sz] : sA[sz];
+            const double *(Ap) = c ? sB[sp] : sA[sp];
+            const double *(Bm) = c ? sA[sm] : sB[sm];
+            const double *(B0) = c ? sA[sz] : sB[sz];
+            const double *(Bp) = c ? sA[sp] : sB[sp];
+            const Nb s = lds_nb(Am, A0, Ap, B0, Bm, Bp, row + 1, tx + 1, p);
+            const size_t idx = prow(j, k, Lc.logn, Lc.lognh) + m;
+            const double ru = A0[(row + 1) * TXH + tx + 1];
+            const double faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
+            const double delta = (c ? Lc.d1 : Lc.d0)[idx];
+            double *S = c ? s1 : s0;
+            const double rd = S[idx] - sh;
+            S[idx] = (faces - 6.0 * ru) / Lc.h2 - model_term<OP>(M, Lc, s, delta, nullptr) - rd;
+            (c ? u1 : u0)[idx] = ru;
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace mgk

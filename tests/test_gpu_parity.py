@@ -63,7 +63,7 @@ def test_residual_parity(n, name, h):
     assert rel(out_s, ref_s) <= 1e-12
 
 
-@pytest.mark.parametrize("n", [4, 8, 32, 64])
+@pytest.mark.parametrize("n", [4, 8, 32, 64, 128, 256])
 @pytest.mark.parametrize("name", ["dgp", "kmo3", "kmo2", "poisson"])
 @pytest.mark.parametrize("colour", [0, 1])
 def test_colour_pass_parity(n, name, colour):
@@ -81,7 +81,7 @@ def test_colour_pass_parity(n, name, colour):
         assert np.array_equal(out[other], phi[other])
 
 
-@pytest.mark.parametrize("n", [8, 16, 64])
+@pytest.mark.parametrize("n", [8, 16, 64, 128, 256])
 def test_restrict_and_prolong_parity(n):
     fine = field(n, 7)
     assert rel(c(mg.op_restrict(g(fine))), oracle.restrict(fine)) <= 1e-15
@@ -103,6 +103,21 @@ def test_transpose_jacobian_parity(n, name):
 
 
 # ------------------------------------------------------------- whole solves
+
+@pytest.mark.parametrize("name,n,cycles", [("dgp", 128, 2), ("kmo3", 128, 2), ("dgp_h05", 256, 1)])
+def test_tiled_levels_fixed_cycles_parity(name, n, cycles):
+    # levels >= 128^3 run the LDS-tiled kernels (pass, residual + restriction
+    # with the residual reduction, prolongation)
+    gp, om = models(n)[name]
+    delta = inputs.lognormal_delta(n, 3)
+    r = oracle.solve(om, delta, tol=0.0, max_cycles=cycles)
+    fn = mg.lib().mg_solve_kmouflage if name.startswith("kmo") else mg.lib().mg_solve_dgp
+    phi, st = mg._solve(fn, gp, 1 if name.startswith("kmo") else 0, g(delta), None, None,
+                        tol=0.0, max_cycles=cycles)
+    assert rel(c(phi), r.phi) <= 1e-11
+    assert st["eps0"] == pytest.approx(r.eps0, rel=1e-10)
+    assert np.allclose(st["eps_hist"], r.hist[:cycles], rtol=1e-8, atol=1e-300)
+
 
 def test_config1_fixed_cycles_parity():
     # 32^3 lognormal (sigma = 1), nDGP H0 r_c = 1, a = 1: three V(1,1) cycles
