@@ -29,7 +29,8 @@ HBM_PEAK_GBS = 8000.0
 # colour halves (8 B), the colour's delta (4 B), write the colour (4 B)
 PASS_BYTES_PER_CELL = 16
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pass_dgp_512_traffic.json")
-KERNEL_SOURCES = ["paper_2110_00566_amd/csrc/mg_device.h", "paper_2110_00566_amd/csrc/mg_kernels.h"]
+KERNEL_SOURCES = ["paper_2110_00566_amd/csrc/mg_device.h", "paper_2110_00566_amd/csrc/mg_kernels.h",
+                  "paper_2110_00566_amd/csrc/mg_tiled.h"]
 
 
 def kernel_hash() -> str:
@@ -151,6 +152,38 @@ def main():
                      "traffic": traffic, "pass_ms_avg": pass_ms,
                      "algorithmic_bytes_per_launch": PASS_BYTES_PER_CELL * N_MESH ** 3},
     }
+    # the same step with the mixed-precision solve (FP32 cycles to the FP32
+    # floor, FP64 cycles to the same FP64 tolerance)
+    phi64 = phi.clone()
+    ws_mix = mg.workspace(N_MESH, mg.MODEL_DGP, False, dev, mg.MG_MIXED)
+    opts_mix = mg.make_opts(N_MESH, tol=TOL, max_cycles=60, precision=mg.MG_MIXED)
+
+    def step_mixed():
+        stream = mg._stream()
+        mg._raise(L.mg_cic_delta(N_MESH, N_PART, mg._ptr(pos), mg._ptr(delta), mg._ptr(ws_pm),
+                                 ws_pm.numel(), stream))
+        phi.zero_()
+        st = mg.Stats()
+        mg._raise(L.mg_solve_dgp(C.byref(opts_mix), C.byref(par), mg._ptr(delta), mg._ptr(phi),
+                                 mg._ptr(ws_mix), ws_mix.numel(), stream, C.byref(st)))
+        return st
+
+    step_mixed()
+    torch.cuda.synchronize()
+    mstats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        mstats.append(step_mixed())
+    torch.cuda.synchronize()
+    dtm = time.perf_counter() - t0
+    assert all(s.status == 0 and s.eps <= TOL for s in mstats), [s.status for s in mstats]
+    err = float((phi - phi64).abs().max() / phi64.abs().max())
+    mix_solve_ms = 1e3 * float(np.mean([s.seconds for s in mstats]))
+    out["mixed"] = {"ms_per_step": 1e3 * dtm / args.steps, "time_to_tol_ms": mix_solve_ms,
+                    "cycles": int(mstats[-1].cycles), "cycles_fp32": int(mstats[-1].cycles_fp32),
+                    "eps_fp32": float(mstats[-1].eps_fp32), "eps": float(mstats[-1].eps),
+                    "speedup_time_to_tol_vs_fp64": solve_ms / mix_solve_ms,
+                    "max_rel_diff_phi_vs_fp64": err}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(pos_np)
     print(json.dumps(out), flush=True)

@@ -57,7 +57,11 @@ typedef struct {
                          pass then colour 1 pass); default 1 */
     int nu_post;      /* sweeps after the coarse-grid correction; default 1 */
     int nu_coarse;    /* sweeps on the 4^3 level; default 32 */
-    int precision;    /* mg_precision; only MG_FP64 in this version */
+    int precision;    /* mg_precision: MG_FP64, or MG_MIXED = FP32-storage FAS cycles
+                         (FP64 discriminant, residuals and reductions) until the FP32
+                         residual stops falling, then FP64 cycles from that field to
+                         tol; the final residual is always the FP64 one (forward
+                         solves only; the adjoint is FP64) */
     int cycle;        /* 0 = V-cycle (the only schedule in this version) */
     int profile;      /* 1: time every finest-level colour pass with HIP events
                          on the caller's stream (stats.pass_ms_avg) */
@@ -76,6 +80,8 @@ typedef struct {
     double seconds;             /* host wall clock of the call */
     double pass_ms_avg;         /* mean finest colour-pass duration (profile=1) */
     int pass_count;             /* number of timed finest colour passes */
+    int cycles_fp32;            /* MG_MIXED: V-cycles of the FP32 phase (included in cycles) */
+    double eps_fp32;            /* MG_MIXED: residual at the end of the FP32 phase */
 } mg_stats;
 
 /* nDGP background (eq:beta_dgp with the LCDM expansion eq:H_lcdm, flat,
@@ -94,8 +100,9 @@ typedef struct {
  * potential, eq:GR_poisson_codeunit with s = 1.5 Omega_m / a). */
 typedef struct { double s; } mg_poisson_params;
 
-/* Bytes of device workspace needed by a solve on an n^3 mesh.  model is an
- * mg_model; adjoint != 0 sizes mg_solve_adjoint.  Returns 0 for invalid n. */
+/* Bytes of device workspace needed by a solve on an n^3 mesh.  precision is
+ * an mg_precision, model an mg_model; adjoint != 0 sizes mg_solve_adjoint
+ * (FP64 only).  Returns 0 for invalid arguments. */
 size_t mg_workspace_bytes(int n, int precision, int model, int adjoint);
 
 /* Solve the nDGP scalar-field equation eq:dgp_eom_code in the form of

@@ -52,7 +52,8 @@ class Stats(C.Structure):
     _fields_ = [("cycles", C.c_int), ("status", C.c_int), ("eps0", C.c_double),
                 ("eps", C.c_double), ("eps_hist", C.c_double * HIST), ("lambda_", C.c_double),
                 ("cell_updates", C.c_longlong), ("n_clamped", C.c_longlong),
-                ("seconds", C.c_double), ("pass_ms_avg", C.c_double), ("pass_count", C.c_int)]
+                ("seconds", C.c_double), ("pass_ms_avg", C.c_double), ("pass_count", C.c_int),
+                ("cycles_fp32", C.c_int), ("eps_fp32", C.c_double)]
 
     def as_dict(self):
         k = min(self.cycles, HIST)
@@ -60,7 +61,8 @@ class Stats(C.Structure):
                     eps_hist=list(self.eps_hist[:k]), lam=self.lambda_,
                     cell_updates=self.cell_updates, n_clamped=self.n_clamped,
                     seconds=self.seconds, pass_ms_avg=self.pass_ms_avg,
-                    pass_count=self.pass_count)
+                    pass_count=self.pass_count, cycles_fp32=self.cycles_fp32,
+                    eps_fp32=self.eps_fp32)
 
 
 class DgpParams(C.Structure):
@@ -166,15 +168,20 @@ def _check_mesh(t, name, dtype=torch.float64):
     return t
 
 
-def workspace(n: int, model: int = MODEL_DGP, adjoint: bool = False, device=None):
-    nbytes = lib().mg_workspace_bytes(n, 0, model, int(adjoint))
+MG_FP64, MG_MIXED = 0, 1
+
+
+def workspace(n: int, model: int = MODEL_DGP, adjoint: bool = False, device=None,
+              precision: int = MG_FP64):
+    nbytes = lib().mg_workspace_bytes(n, precision, model, int(adjoint))
     if nbytes == 0:
         raise ValueError("invalid mesh size %d" % n)
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
-def make_opts(n, tol=1e-8, max_cycles=50, nu_pre=1, nu_post=1, nu_coarse=32, profile=False):
-    return Opts(n, max_cycles, tol, nu_pre, nu_post, nu_coarse, 0, 0, int(profile))
+def make_opts(n, tol=1e-8, max_cycles=50, nu_pre=1, nu_post=1, nu_coarse=32, profile=False,
+              precision=MG_FP64):
+    return Opts(n, max_cycles, tol, nu_pre, nu_post, nu_coarse, precision, 0, int(profile))
 
 
 def dgp_params(a=1.0, omega_m=OMEGA_M, h0rc=1.0):
@@ -193,7 +200,7 @@ def _solve(fn, par, model, delta, phi0, ws, **kw):
     n = delta.shape[0]
     phi = torch.zeros_like(delta) if phi0 is None else _check_mesh(phi0, "phi0").clone()
     if ws is None:
-        ws = workspace(n, model, False, delta.device)
+        ws = workspace(n, model, False, delta.device, kw.get("precision", MG_FP64))
     o = make_opts(n, **kw)
     st = Stats()
     rc = fn(C.byref(o), C.byref(par), _ptr(delta), _ptr(phi), _ptr(ws), ws.numel(), _stream(),
@@ -203,7 +210,9 @@ def _solve(fn, par, model, delta, phi0, ws, **kw):
 
 
 def solve_dgp(delta, phi0=None, a=1.0, omega_m=OMEGA_M, h0rc=1.0, ws=None, **kw):
-    """nDGP field (eq:dgp_eom_code); returns (zero-mean phi, stats)."""
+    """nDGP field (eq:dgp_eom_code); returns (zero-mean phi, stats).
+    Keywords: tol, max_cycles, nu_pre, nu_post, nu_coarse, profile,
+    precision (MG_FP64 or MG_MIXED)."""
     return _solve(lib().mg_solve_dgp, dgp_params(a, omega_m, h0rc), MODEL_DGP, delta, phi0, ws, **kw)
 
 

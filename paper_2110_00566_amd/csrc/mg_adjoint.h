@@ -31,7 +31,7 @@ __global__ __launch_bounds__(TPB) void k_adj_coefs(Mod M, Lvl L, CoefsW W, doubl
     const int k = (int)(tt >> (L.lognh + L.logn));
     const double *A = c ? L.u1 : L.u0;
     const double *B = c ? L.u0 : L.u1;
-    const Nb s = load_nb(A, B, c, m, j, k, L.n, L.logn, L.lognh);
+    const Nb s = load_nb<double, double>(A, B, c, m, j, k, L.n, L.logn, L.lognh);
     const double delta = (c ? L.d1 : L.d0)[tt];
     const double ax = s.xp + s.xm, ay = s.yp + s.ym, az = s.zp + s.zm;
     double f[6], e[3];
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(TPB) void k_adj_grad(Mod M, Lvl L, const double *mu
     const int k = (int)(tt >> (L.lognh + L.logn));
     const double *A = c ? L.u1 : L.u0;
     const double *B = c ? L.u0 : L.u1;
-    const Nb s = load_nb(A, B, c, m, j, k, L.n, L.logn, L.lognh);
+    const Nb s = load_nb<double, double>(A, B, c, m, j, k, L.n, L.logn, L.lognh);
     const double delta = (c ? L.d1 : L.d0)[tt];
     double dk;
     if (MODEL == MODEL_POISSON) {

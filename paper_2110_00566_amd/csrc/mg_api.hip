@@ -11,6 +11,7 @@
 // field has zero mean.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -62,22 +63,31 @@ struct Carve {
     }
 };
 
+// One level of a hierarchy with storage type R.  lin and cf (adjoint
+// linearisation point and Jacobian coefficients) exist in FP64 only.
+template <typename R>
 struct HLevel {
     int n = 0, logn = 0;
     double h = 1.0;
     size_t half = 0;
-    double *u[2] = {nullptr, nullptr};
-    double *spare = nullptr;
-    double *d[2] = {nullptr, nullptr};
-    double *f[2] = {nullptr, nullptr};
-    double *ru[2] = {nullptr, nullptr};
+    R *u[2] = {nullptr, nullptr};
+    R *spare = nullptr;
+    R *d[2] = {nullptr, nullptr};
+    R *f[2] = {nullptr, nullptr};
+    R *ru[2] = {nullptr, nullptr};
     double *lin[2] = {nullptr, nullptr};
     double *cf[9][2] = {};
 };
 
-struct Ctx {
+template <typename R>
+struct Hier {
     int nlev = 0;
-    HLevel lv[MAX_LEVELS];
+    HLevel<R> lv[MAX_LEVELS];
+};
+
+struct Ctx {
+    Hier<double> h64;
+    Hier<float> h32;
     double *partials = nullptr;
     size_t npartials = 0;
     double *scal = nullptr;
@@ -93,27 +103,34 @@ struct Ctx {
     int pass_count = 0;
 };
 
-// Lay the workspace out (base == nullptr: only measure).
-void layout(Ctx &C, Carve &cv, int n, bool adjoint) {
+template <typename R>
+Hier<R> &hier(Ctx &C);
+template <>
+Hier<double> &hier<double>(Ctx &C) { return C.h64; }
+template <>
+Hier<float> &hier<float>(Ctx &C) { return C.h32; }
+
+template <typename R>
+void layout_hier(Hier<R> &Hh, Carve &cv, int n, bool adjoint) {
     int L = 0;
     for (int m = n; m >= 4; m >>= 1) {
-        HLevel &H = C.lv[L];
+        HLevel<R> &H = Hh.lv[L];
         H.n = m;
         H.logn = ilog2(m);
         H.h = (double)n / m;
         H.half = (size_t)m * m * m / 2;
-        H.u[0] = cv.take<double>(H.half);
-        H.u[1] = cv.take<double>(H.half);
-        H.spare = cv.take<double>(H.half);
-        H.d[0] = cv.take<double>(H.half);
-        H.d[1] = cv.take<double>(H.half);
+        H.u[0] = cv.take<R>(H.half);
+        H.u[1] = cv.take<R>(H.half);
+        H.spare = cv.take<R>(H.half);
+        H.d[0] = cv.take<R>(H.half);
+        H.d[1] = cv.take<R>(H.half);
         if (L > 0 || adjoint) {
-            H.f[0] = cv.take<double>(H.half);
-            H.f[1] = cv.take<double>(H.half);
+            H.f[0] = cv.take<R>(H.half);
+            H.f[1] = cv.take<R>(H.half);
         }
         if (L > 0) {
-            H.ru[0] = cv.take<double>(H.half);
-            H.ru[1] = cv.take<double>(H.half);
+            H.ru[0] = cv.take<R>(H.half);
+            H.ru[1] = cv.take<R>(H.half);
         }
         if (adjoint) {
             H.lin[0] = cv.take<double>(H.half);
@@ -123,15 +140,22 @@ void layout(Ctx &C, Carve &cv, int n, bool adjoint) {
         }
         ++L;
     }
-    C.nlev = L;
+    Hh.nlev = L;
+}
+
+// Lay the workspace out (base == nullptr: only measure).
+void layout(Ctx &C, Carve &cv, int n, bool adjoint, bool mixed) {
+    layout_hier(C.h64, cv, n, adjoint);
+    if (mixed) layout_hier(C.h32, cv, n, false);
     C.npartials = std::max<size_t>((size_t)n * n * n / TPB + 1, 1024);
     C.partials = cv.take<double>(2 * C.npartials);
     C.scal = cv.take<double>(S_NSCAL);
     C.clamp = cv.take<unsigned long long>(4);
 }
 
-Lvl view(const HLevel &H, bool with_f) {
-    Lvl L;
+template <typename R>
+LvlT<R> view(const HLevel<R> &H, bool with_f) {
+    LvlT<R> L;
     L.u0 = H.u[0];
     L.u1 = H.u[1];
     L.d0 = H.d[0];
@@ -150,7 +174,8 @@ Lvl view(const HLevel &H, bool with_f) {
     return L;
 }
 
-Coefs coefs(const HLevel &H) {
+template <typename R>
+Coefs coefs(const HLevel<R> &H) {
     Coefs C;
     for (int q = 0; q < 9; ++q)
         for (int c = 0; c < 2; ++c) C.c[q][c] = H.cf[q][c];
@@ -158,7 +183,6 @@ Coefs coefs(const HLevel &H) {
 }
 
 unsigned nblocks(size_t threads) { return (unsigned)((threads + TPB - 1) / TPB); }
-
 
 // ------------------------------------------------------------ kernel launchers
 // Levels with >= 128 cells per side use the LDS-tiled kernels (64 packed
@@ -184,46 +208,50 @@ unsigned tile_blocks(const TileGeom &G, int planes) {
     return (unsigned)((long)G.ntx * G.nty * (planes / G.kz));
 }
 
-template <int OP>
-void launch_pass(const Mod &M, const Lvl &L, const Coefs &Cf, int c, double *out, const double *fptr,
+constexpr int fwd_op(int OP) { return OP == OP_ADJ ? OP_DGP : OP; }
+
+template <int OP, typename R>
+void launch_pass(const Mod &M, const LvlT<R> &L, const Coefs &Cf, int c, R *out, const double *fptr,
                  double fs, unsigned long long *clamp, hipStream_t st) {
     if (OP != OP_ADJ && tiled_level(L.n)) {
         const TileGeom G = tile_geom(L.n, L.n);
-        k_pass_tiled<OP == OP_ADJ ? OP_DGP : OP><<<tile_blocks(G, L.n), TPB, 0, st>>>(
-            M, L, c, out, fptr, fs, clamp, G);
+        k_pass_tiled<fwd_op(OP), R><<<tile_blocks(G, L.n), TPB, 0, st>>>(M, L, c, out, fptr, fs,
+                                                                         clamp, G);
     } else {
         const size_t half = (size_t)L.n * L.n * L.n / 2;
-        k_pass<OP><<<nblocks(half), TPB, 0, st>>>(M, L, Cf, c, out, fptr, fs, clamp);
+        k_pass<OP, R><<<nblocks(half), TPB, 0, st>>>(M, L, Cf, c, out, fptr, fs, clamp);
     }
 }
 
-template <int OP, bool REDUCE>
-unsigned launch_resid_restrict(const Mod &M, const Lvl &L, const Coefs &Cf, const double *fptr,
-                               double fs, double *ru0, double *ru1, double *rd0, double *rd1,
-                               double *partials, unsigned long long *clamp, hipStream_t st) {
+template <int OP, bool REDUCE, typename R>
+unsigned launch_resid_restrict(const Mod &M, const LvlT<R> &L, const Coefs &Cf, const double *fptr,
+                               double fs, R *ru0, R *ru1, R *rd0, R *rd1, double *partials,
+                               unsigned long long *clamp, hipStream_t st) {
     if (OP != OP_ADJ && tiled_level(L.n)) {
         const TileGeom G = tile_geom(L.n, L.n / 2);
         const unsigned nb = tile_blocks(G, L.n / 2);
-        k_resid_restrict_tiled<OP == OP_ADJ ? OP_DGP : OP, REDUCE><<<nb, TPB, 0, st>>>(
+        k_resid_restrict_tiled<fwd_op(OP), REDUCE, R><<<nb, TPB, 0, st>>>(
             M, L, fptr, fs, ru0, ru1, rd0, rd1, partials, clamp, G);
         return nb;
     }
     const size_t ncoarse = (size_t)L.n * L.n * L.n / 8;
     const unsigned nb = nblocks(ncoarse);
-    k_resid_restrict<OP, REDUCE><<<nb, TPB, 0, st>>>(M, L, Cf, fptr, fs, ru0, ru1, rd0, rd1,
-                                                     partials, clamp);
+    k_resid_restrict<OP, REDUCE, R><<<nb, TPB, 0, st>>>(M, L, Cf, fptr, fs, ru0, ru1, rd0, rd1,
+                                                        partials, clamp);
     return nb;
 }
 
-void launch_prolong(double *f0, double *f1, int logn, const double *uc0, const double *uc1,
-                    const double *rc0, const double *rc1, hipStream_t st) {
+template <typename R>
+void launch_prolong(R *f0, R *f1, int logn, const R *uc0, const R *uc1, const R *rc0,
+                    const R *rc1, hipStream_t st) {
     const int n = 1 << logn;
     if (tiled_level(n)) {
         const TileGeom G = tile_geom(n, n / 2);
-        k_prolong_tiled<<<tile_blocks(G, n / 2), TPB, 0, st>>>(f0, f1, logn, uc0, uc1, rc0, rc1, G);
+        k_prolong_tiled<R><<<tile_blocks(G, n / 2), TPB, 0, st>>>(f0, f1, logn, uc0, uc1, rc0, rc1,
+                                                                 G);
     } else {
         const size_t cells = (size_t)n * n * n;
-        k_prolong<<<nblocks(cells), TPB, 0, st>>>(f0, f1, logn, uc0, uc1, rc0, rc1);
+        k_prolong<R><<<nblocks(cells), TPB, 0, st>>>(f0, f1, logn, uc0, uc1, rc0, rc1);
     }
 }
 
@@ -278,28 +306,34 @@ mg_status check_opts(const mg_opts *o) {
     if (o->nu_pre < 0 || o->nu_post < 0 || o->nu_coarse < 1 || o->nu_pre > 64 || o->nu_post > 64 ||
         o->nu_coarse > 4096)
         return fail(MG_ERR_ARG, "sweep counts out of range");
-    if (o->precision != MG_FP64) return fail(MG_ERR_ARG, "only MG_FP64 precision is available");
+    if (o->precision != MG_FP64 && o->precision != MG_MIXED)
+        return fail(MG_ERR_ARG, "opts.precision must be MG_FP64 or MG_MIXED");
     if (o->cycle != 0) return fail(MG_ERR_ARG, "only the V-cycle (cycle = 0) is available");
     return MG_OK;
 }
 
 // ---------------------------------------------------------------- V-cycle
 
-template <int OP>
+struct PhaseResult {
+    int status = MG_NOT_CONVERGED;
+    int cycles = 0;
+    double eps0 = 0.0, eps = 0.0;
+};
+
+template <int OP, typename R>
 struct Solver {
     Ctx &C;
-    explicit Solver(Ctx &c) : C(c) {}
+    Hier<R> &Hh;
+    explicit Solver(Ctx &c) : C(c), Hh(hier<R>(c)) {}
 
-    hipError_t launch_err() { return hipGetLastError(); }
-
-    void mean_of(double *a0, double *a1, size_t half) {
+    void mean_of(R *a0, R *a1, size_t half) {
         const unsigned nb = nblocks(2 * half);
-        k_sum<<<nb, TPB, 0, C.st>>>(a0, a1, half, C.partials);
+        k_sum<R><<<nb, TPB, 0, C.st>>>(a0, a1, half, C.partials);
         k_finalize<<<1, 1024, 0, C.st>>>(C.partials, nb, (double)(2 * half), C.scal, 1, 0.0);
     }
 
     void pass(int l, int c) {
-        HLevel &H = C.lv[l];
+        HLevel<R> &H = Hh.lv[l];
         const double *fptr = nullptr;
         double fs = 0.0;
         if (l == 0) {
@@ -314,8 +348,8 @@ struct Solver {
         }
         const bool timed = C.profile && l == 0 && C.ev_used + 2 <= (int)C.ev.size();
         if (timed) (void)hipEventRecord(C.ev[C.ev_used], C.st);
-        launch_pass<OP>(C.M, view(H, l > 0 || OP == OP_ADJ), coefs(H), c, H.spare, fptr, fs,
-                        C.clamp, C.st);
+        launch_pass<OP, R>(C.M, view(H, l > 0 || OP == OP_ADJ), coefs(H), c, H.spare, fptr, fs,
+                           C.clamp, C.st);
         if (timed) {
             (void)hipEventRecord(C.ev[C.ev_used + 1], C.st);
             C.ev_used += 2;
@@ -328,61 +362,72 @@ struct Solver {
         pass(l, 1);
     }
 
-    // finest residual statistics (and restriction into level 1)
+    // residual (+ statistics on the finest level) and restriction into l+1
     void resid_restrict(int l) {
-        HLevel &H = C.lv[l], &Hc = C.lv[l + 1];
+        HLevel<R> &H = Hh.lv[l], &Hc = Hh.lv[l + 1];
         const bool with_f = l > 0 || OP == OP_ADJ;
         const double *fptr = (l == 0 && OP != OP_ADJ) ? C.scal + S_MU : nullptr;
         if (l == 0) {
             if (OP == OP_ADJ) mean_of(H.u[0], H.u[1], H.half);
-            const unsigned nb = launch_resid_restrict<OP, true>(
+            const unsigned nb = launch_resid_restrict<OP, true, R>(
                 C.M, view(H, with_f), coefs(H), fptr, 1.0, Hc.ru[0], Hc.ru[1], Hc.f[0], Hc.f[1],
                 C.partials, C.clamp, C.st);
             k_finalize<<<1, 1024, 0, C.st>>>(C.partials, nb, (double)H.n * H.n * H.n, C.scal,
                                              OP == OP_ADJ ? 2 : 0, C.kappa);
         } else {
-            launch_resid_restrict<OP, false>(C.M, view(H, with_f), coefs(H), fptr, 1.0, Hc.ru[0],
-                                             Hc.ru[1], Hc.f[0], Hc.f[1], C.partials, C.clamp,
-                                             C.st);
+            launch_resid_restrict<OP, false, R>(C.M, view(H, with_f), coefs(H), fptr, 1.0,
+                                                Hc.ru[0], Hc.ru[1], Hc.f[0], Hc.f[1], C.partials,
+                                                C.clamp, C.st);
         }
     }
 
     void coarse_source(int lc) {
-        HLevel &Hc = C.lv[lc];
-        Lvl L = view(Hc, false);
+        HLevel<R> &Hc = Hh.lv[lc];
+        LvlT<R> L = view(Hc, false);
         L.u0 = Hc.ru[0];
         L.u1 = Hc.ru[1];
         const double *shift = (lc == 1 && OP != OP_ADJ) ? C.scal + S_SHIFT : nullptr;
         if (OP != OP_ADJ && tiled_level(Hc.n)) {
             const TileGeom G = tile_geom(Hc.n, Hc.n);
-            k_coarse_source_tiled<OP == OP_ADJ ? OP_DGP : OP><<<tile_blocks(G, Hc.n), TPB, 0, C.st>>>(
+            k_coarse_source_tiled<fwd_op(OP), R><<<tile_blocks(G, Hc.n), TPB, 0, C.st>>>(
                 C.M, L, Hc.f[0], Hc.f[1], Hc.u[0], Hc.u[1], shift, G);
         } else {
-            k_coarse_source<OP><<<nblocks(2 * Hc.half), TPB, 0, C.st>>>(
+            k_coarse_source<OP, R><<<nblocks(2 * Hc.half), TPB, 0, C.st>>>(
                 C.M, L, coefs(Hc), Hc.f[0], Hc.f[1], Hc.u[0], Hc.u[1], shift);
         }
     }
 
     void prolong(int l) {
-        HLevel &H = C.lv[l], &Hc = C.lv[l + 1];
-        launch_prolong(H.u[0], H.u[1], H.logn, Hc.u[0], Hc.u[1], Hc.ru[0], Hc.ru[1], C.st);
+        HLevel<R> &H = Hh.lv[l], &Hc = Hh.lv[l + 1];
+        launch_prolong<R>(H.u[0], H.u[1], H.logn, Hc.u[0], Hc.u[1], Hc.ru[0], Hc.ru[1], C.st);
+    }
+
+    template <int NL>
+    void launch_tail(const TailArgs<R> &A, size_t lds) {
+        static bool attr_set = false;   // per instantiation, process-wide
+        if (!attr_set) {
+            (void)hipFuncSetAttribute((const void *)k_tail<OP, NL, R>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            attr_set = true;
+        }
+        k_tail<OP, NL, R><<<1, TAIL_THREADS, lds, C.st>>>(C.M, A);
     }
 
     // Levels l.. (all <= 16^3, l >= 1) in one single-workgroup launch.
     void tail(int l) {
-        TailArgs A;
-        A.nlev = C.nlev - l;
+        TailArgs<R> A;
+        A.nlev = Hh.nlev - l;
         A.nu1 = C.nu1;
         A.nu2 = C.nu2;
         A.nuc = C.nuc;
         for (int q = 0; q < A.nlev; ++q) {
-            HLevel &H = C.lv[l + q];
+            HLevel<R> &H = Hh.lv[l + q];
             A.lv[q].L = view(H, true);
             A.lv[q].ru0 = H.ru[0];
             A.lv[q].ru1 = H.ru[1];
             A.cf[q] = coefs(H);
         }
-        const size_t lds = sizeof(double) * tail_lds_doubles(C.lv[l].logn, A.nlev);
+        const size_t lds = sizeof(R) * tail_lds_elems(Hh.lv[l].logn, A.nlev);
         switch (A.nlev) {
             case 1: launch_tail<1>(A, lds); break;
             case 2: launch_tail<2>(A, lds); break;
@@ -390,21 +435,10 @@ struct Solver {
         }
     }
 
-    template <int NL>
-    void launch_tail(const TailArgs &A, size_t lds) {
-        static bool attr_set = false;   // per instantiation, process-wide
-        if (!attr_set) {
-            (void)hipFuncSetAttribute((const void *)k_tail<OP, NL>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            attr_set = true;
-        }
-        k_tail<OP, NL><<<1, TAIL_THREADS, lds, C.st>>>(C.M, A);
-    }
-
     int tail_start() const {
-        for (int l = 1; l < C.nlev; ++l)
-            if (C.lv[l].n <= TAIL_MAX_N && C.nlev - l <= TAIL_MAX_LEVELS) return l;
-        return C.nlev;   // no tail (single-level hierarchy)
+        for (int l = 1; l < Hh.nlev; ++l)
+            if (Hh.lv[l].n <= TAIL_MAX_N && Hh.nlev - l <= TAIL_MAX_LEVELS) return l;
+        return Hh.nlev;
     }
 
     void vcycle(int l) {
@@ -412,7 +446,7 @@ struct Solver {
             tail(l);
             return;
         }
-        if (l == C.nlev - 1) {
+        if (l == Hh.nlev - 1) {
             for (int s = 0; s < C.nuc; ++s) sweep(l);
             return;
         }
@@ -440,26 +474,34 @@ struct Solver {
         return MG_OK;
     }
 
-    // Cycle loop shared by the forward and the adjoint solves.  phi (finest
-    // packed u) is already initialised; the right-hand side is set up.
-    mg_status cycles(const mg_opts *o, mg_stats *st) {
+    // Cycle loop.  The finest field and right-hand side are set up.  Runs
+    // until the residual is <= tol (confirmed by a residual evaluation of the
+    // post-smoothed field), max_cycles, or -- with stall > 0 -- until a cycle
+    // reduces the in-cycle residual by less than the factor stall.  Cycle
+    // residuals go to hist[hist0 ...].
+    mg_status run(double tol, int max_cycles, double stall, mg_stats *st, int hist0,
+                  PhaseResult &pr) {
         double hs[S_NSCAL];
         mg_status rc;
-        // initial residual
         resid_restrict(0);
         if ((rc = read_scal(hs)) != MG_OK) return rc;
         double eps = std::sqrt(hs[S_EPS2]);
-        st->eps0 = eps;
-        if (!std::isfinite(eps)) return fail(MG_ERR_NONFINITE, "initial residual is not finite");
-        int status = (eps <= o->tol) ? MG_OK : MG_NOT_CONVERGED;
-        double best = eps;
+        pr.eps0 = eps;
+        pr.eps = eps;
+        if (!std::isfinite(eps)) {
+            pr.status = MG_ERR_NONFINITE;
+            fail(MG_ERR_NONFINITE, "initial residual is not finite");
+            return MG_OK;
+        }
+        int status = (eps <= tol) ? MG_OK : MG_NOT_CONVERGED;
+        double best = eps, prev = INFINITY;   // stall test compares consecutive cycles
         int cyc = 0;
         if (status != MG_OK) {
-            for (cyc = 1; cyc <= o->max_cycles; ++cyc) {
+            for (cyc = 1; cyc <= max_cycles; ++cyc) {
                 vcycle(0);
                 if ((rc = read_scal(hs)) != MG_OK) return rc;
                 const double em = std::sqrt(hs[S_EPS2]);
-                if (cyc - 1 < MG_HIST) st->eps_hist[cyc - 1] = em;
+                if (hist0 + cyc - 1 < MG_HIST) st->eps_hist[hist0 + cyc - 1] = em;
                 if (!std::isfinite(em)) {
                     status = MG_ERR_NONFINITE;
                     break;
@@ -469,34 +511,40 @@ struct Solver {
                     break;
                 }
                 if (em < best) best = em;
-                if (em <= o->tol || cyc == o->max_cycles) {
+                const bool stalled = stall > 0.0 && em > stall * prev;
+                prev = em;
+                if (em <= tol || cyc == max_cycles || stalled) {
                     resid_restrict(0);
                     if ((rc = read_scal(hs)) != MG_OK) return rc;
                     eps = std::sqrt(hs[S_EPS2]);
-                    if (eps <= o->tol) {
+                    if (eps <= tol) {
                         status = MG_OK;
                         break;
                     }
+                    if (stalled) break;
                 }
             }
-            if (cyc > o->max_cycles) cyc = o->max_cycles;
+            if (cyc > max_cycles) cyc = max_cycles;
         }
-        st->cycles = cyc;
-        st->eps = eps;
+        pr.status = status;
+        pr.cycles = cyc;
+        pr.eps = eps;
         st->lambda = -hs[S_MU];
-        st->cell_updates = (long long)o->n * o->n * o->n * (o->nu_pre + o->nu_post) * cyc;
-        return (mg_status)status;
+        return MG_OK;
     }
 };
 
-// Pack delta into the finest level and restrict it down the hierarchy.
+// Pack delta into the finest level of hierarchy R and restrict it down.
+template <typename R>
 void density_hierarchy(Ctx &C, const double *delta) {
-    HLevel &F = C.lv[0];
-    k_pack<<<nblocks(2 * F.half), TPB, 0, C.st>>>(delta, F.logn, F.d[0], F.d[1], nullptr);
-    for (int l = 0; l + 1 < C.nlev; ++l) {
-        HLevel &H = C.lv[l], &Hc = C.lv[l + 1];
-        k_restrict<<<nblocks(2 * Hc.half), TPB, 0, C.st>>>(H.d[0], H.d[1], H.logn, Hc.d[0],
-                                                          Hc.d[1]);
+    Hier<R> &Hh = hier<R>(C);
+    HLevel<R> &F = Hh.lv[0];
+    k_pack<double, R><<<nblocks(2 * F.half), TPB, 0, C.st>>>(delta, F.logn, F.d[0], F.d[1],
+                                                            nullptr);
+    for (int l = 0; l + 1 < Hh.nlev; ++l) {
+        HLevel<R> &H = Hh.lv[l], &Hc = Hh.lv[l + 1];
+        k_restrict<R><<<nblocks(2 * Hc.half), TPB, 0, C.st>>>(H.d[0], H.d[1], H.logn, Hc.d[0],
+                                                             Hc.d[1]);
     }
 }
 
@@ -524,9 +572,10 @@ template <int OP>
 mg_status forward_solve(const mg_opts *o, const Mod &M, const double *delta, double *phi,
                         void *ws, size_t ws_bytes, hipStream_t stream, mg_stats *st) {
     auto t0 = std::chrono::steady_clock::now();
+    const bool mixed = o->precision == MG_MIXED;
     Ctx C;
     Carve cv{static_cast<char *>(ws), 0};
-    layout(C, cv, o->n, false);
+    layout(C, cv, o->n, false, mixed);
     if (!ws || ws_bytes < cv.off)
         return fail(MG_ERR_WORKSPACE, "workspace too small: need " + std::to_string(cv.off) +
                                           " bytes");
@@ -537,43 +586,75 @@ mg_status forward_solve(const mg_opts *o, const Mod &M, const double *delta, dou
     C.nuc = o->nu_coarse;
     Profiler prof(C, o->profile != 0, 2 * (o->nu_pre + o->nu_post) + 2);
     reset_scalars(C);
-    density_hierarchy(C, delta);
-    HLevel &F = C.lv[0];
-    k_pack<<<nblocks(2 * F.half), TPB, 0, C.st>>>(phi, F.logn, F.u[0], F.u[1], nullptr);
-    Solver<OP> S(C);
-    mg_status rc = S.cycles(o, st);
-    if (rc < 0) {
-        st->status = rc;
-        return rc;
+    HLevel<double> &F = C.h64.lv[0];
+    PhaseResult p32, p64;
+    int cycles32 = 0;
+    if (mixed) {
+        // FP32-storage cycles until the residual stops falling (FP32 floor)
+        density_hierarchy<float>(C, delta);
+        HLevel<float> &G = C.h32.lv[0];
+        k_pack<double, float><<<nblocks(2 * G.half), TPB, 0, C.st>>>(phi, G.logn, G.u[0], G.u[1],
+                                                                     nullptr);
+        Solver<OP, float> S32(C);
+        mg_status rc = S32.run(o->tol, o->max_cycles, 0.5, st, 0, p32);
+        if (rc != MG_OK) return rc;
+        if (p32.status < 0) {
+            st->status = p32.status;
+            return (mg_status)p32.status;
+        }
+        cycles32 = p32.cycles;
+        st->cycles_fp32 = cycles32;
+        st->eps_fp32 = p32.eps;
+        k_convert<float, double><<<nblocks(G.half), TPB, 0, C.st>>>(G.u[0], F.u[0], G.half);
+        k_convert<float, double><<<nblocks(G.half), TPB, 0, C.st>>>(G.u[1], F.u[1], G.half);
+    } else {
+        k_pack<double, double><<<nblocks(2 * F.half), TPB, 0, C.st>>>(phi, F.logn, F.u[0],
+                                                                      F.u[1], nullptr);
+    }
+    // FP64 cycles (the whole solve, or the finish of the mixed one)
+    density_hierarchy<double>(C, delta);
+    Solver<OP, double> S(C);
+    mg_status rc = S.run(o->tol, o->max_cycles - cycles32, 0.0, st, cycles32, p64);
+    if (rc != MG_OK) return rc;
+    st->cycles = cycles32 + p64.cycles;
+    st->eps0 = mixed ? p32.eps0 : p64.eps0;
+    st->eps = p64.eps;
+    st->cell_updates = (long long)o->n * o->n * o->n * (o->nu_pre + o->nu_post) * st->cycles;
+    mg_status status = (mg_status)p64.status;
+    if (status < 0) {
+        st->status = status;
+        return status;
     }
     // zero-mean gauge
     S.mean_of(F.u[0], F.u[1], F.half);
-    k_unpack<<<nblocks(2 * F.half), TPB, 0, C.st>>>(F.u[0], F.u[1], F.logn, phi,
-                                                    C.scal + S_MEAN);
+    k_unpack<double, double><<<nblocks(2 * F.half), TPB, 0, C.st>>>(F.u[0], F.u[1], F.logn, phi,
+                                                                    C.scal + S_MEAN);
     unsigned long long ncl = 0;
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(&ncl, C.clamp, sizeof(ncl), hipMemcpyDeviceToHost, C.st));
     HIPCHK(hipStreamSynchronize(C.st));
     st->n_clamped = (long long)ncl;
-    if (rc == MG_OK && ncl > 0) rc = MG_WARN_CLAMPED;
-    st->status = rc;
+    if (status == MG_OK && ncl > 0) status = MG_WARN_CLAMPED;
+    st->status = status;
     st->pass_ms_avg = C.pass_count ? C.pass_ms / C.pass_count : 0.0;
     st->pass_count = C.pass_count;
     st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    return rc;
+    return status;
 }
 
 template <int MODEL>
-void adj_coefficients(Ctx &C, const double *phi, const double *delta) {
+void adj_coefficients(Ctx &C, const double *phi) {
     // linearisation points: packed phi on the finest level, restricted below
-    HLevel &F = C.lv[0];
-    k_pack<<<nblocks(2 * F.half), TPB, 0, C.st>>>(phi, F.logn, F.lin[0], F.lin[1], nullptr);
-    for (int l = 0; l < C.nlev; ++l) {
-        HLevel &H = C.lv[l];
-        if (l + 1 < C.nlev) {
-            HLevel &Hc = C.lv[l + 1];
-            k_restrict<<<nblocks(2 * Hc.half), TPB, 0, C.st>>>(H.lin[0], H.lin[1], H.logn,
-                                                              Hc.lin[0], Hc.lin[1]);
+    Hier<double> &Hh = C.h64;
+    HLevel<double> &F = Hh.lv[0];
+    k_pack<double, double><<<nblocks(2 * F.half), TPB, 0, C.st>>>(phi, F.logn, F.lin[0],
+                                                                  F.lin[1], nullptr);
+    for (int l = 0; l < Hh.nlev; ++l) {
+        HLevel<double> &H = Hh.lv[l];
+        if (l + 1 < Hh.nlev) {
+            HLevel<double> &Hc = Hh.lv[l + 1];
+            k_restrict<double><<<nblocks(2 * Hc.half), TPB, 0, C.st>>>(H.lin[0], H.lin[1], H.logn,
+                                                                      Hc.lin[0], Hc.lin[1]);
         }
         Lvl L = view(H, false);
         L.u0 = H.lin[0];
@@ -583,7 +664,6 @@ void adj_coefficients(Ctx &C, const double *phi, const double *delta) {
             for (int c = 0; c < 2; ++c) W.c[q][c] = H.cf[q][c];
         k_adj_coefs<MODEL><<<nblocks(2 * H.half), TPB, 0, C.st>>>(C.M, L, W, H.h);
     }
-    (void)delta;
 }
 
 template <int MODEL>
@@ -593,7 +673,7 @@ mg_status adjoint_solve(const mg_opts *o, const Mod &M, const double *delta, con
     auto t0 = std::chrono::steady_clock::now();
     Ctx C;
     Carve cv{static_cast<char *>(ws), 0};
-    layout(C, cv, o->n, true);
+    layout(C, cv, o->n, true, false);
     if (!ws || ws_bytes < cv.off)
         return fail(MG_ERR_WORKSPACE, "workspace too small: need " + std::to_string(cv.off) +
                                           " bytes");
@@ -605,36 +685,44 @@ mg_status adjoint_solve(const mg_opts *o, const Mod &M, const double *delta, con
     C.kappa = 6.0;   // 6/h^2 on the finest level: removes the mean of mu in one pass
     Profiler prof(C, false, 0);
     reset_scalars(C);
-    density_hierarchy(C, delta);
-    adj_coefficients<MODEL>(C, phi, delta);
-    HLevel &F = C.lv[0];
+    density_hierarchy<double>(C, delta);
+    adj_coefficients<MODEL>(C, phi);
+    HLevel<double> &F = C.h64.lv[0];
     // right-hand side b = w - mean(w) on the finest level
-    k_pack<<<nblocks(2 * F.half), TPB, 0, C.st>>>(w, F.logn, F.f[0], F.f[1], nullptr);
-    Solver<OP_ADJ> S(C);
+    k_pack<double, double><<<nblocks(2 * F.half), TPB, 0, C.st>>>(w, F.logn, F.f[0], F.f[1],
+                                                                  nullptr);
+    Solver<OP_ADJ, double> S(C);
     S.mean_of(F.f[0], F.f[1], F.half);
-    k_pack<<<nblocks(2 * F.half), TPB, 0, C.st>>>(w, F.logn, F.f[0], F.f[1], C.scal + S_MEAN);
-    k_pack<<<nblocks(2 * F.half), TPB, 0, C.st>>>(mu, F.logn, F.u[0], F.u[1], nullptr);
-    mg_status rc = S.cycles(o, st);
-    if (rc < 0) {
-        st->status = rc;
-        return rc;
+    k_pack<double, double><<<nblocks(2 * F.half), TPB, 0, C.st>>>(w, F.logn, F.f[0], F.f[1],
+                                                                  C.scal + S_MEAN);
+    k_pack<double, double><<<nblocks(2 * F.half), TPB, 0, C.st>>>(mu, F.logn, F.u[0], F.u[1],
+                                                                  nullptr);
+    PhaseResult pr;
+    mg_status rc = S.run(o->tol, o->max_cycles, 0.0, st, 0, pr);
+    if (rc != MG_OK) return rc;
+    st->cycles = pr.cycles;
+    st->eps0 = pr.eps0;
+    st->eps = pr.eps;
+    st->cell_updates = (long long)o->n * o->n * o->n * (o->nu_pre + o->nu_post) * pr.cycles;
+    if (pr.status < 0) {
+        st->status = pr.status;
+        return (mg_status)pr.status;
     }
-    k_unpack<<<nblocks(2 * F.half), TPB, 0, C.st>>>(F.u[0], F.u[1], F.logn, mu, nullptr);
+    k_unpack<double, double><<<nblocks(2 * F.half), TPB, 0, C.st>>>(F.u[0], F.u[1], F.logn, mu,
+                                                                    nullptr);
     Lvl L = view(F, false);
     L.u0 = F.lin[0];
     L.u1 = F.lin[1];
     k_adj_grad<MODEL><<<nblocks(2 * F.half), TPB, 0, C.st>>>(C.M, L, F.u[0], F.u[1], grad);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(C.st));
-    st->status = rc;
+    st->status = pr.status;
     st->lambda = 0.0;
     st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    return rc;
+    return (mg_status)pr.status;
 }
 
-}  // namespace
-
-namespace {
+// ------------------------------------------------------- single operations
 
 size_t op_workspace_bytes(int n) {
     if (!is_pow2(n) || n < 4 || n > 2048) return 0;
@@ -642,8 +730,9 @@ size_t op_workspace_bytes(int n) {
     // u(2) + spare + d(2) + f(2) + out(2) + coefficients(18) + coarse (2+2)
     return (half * (2 + 1 + 2 + 2 + 2 + 18 + 2 + 2) + 64) * sizeof(double) + 256 * 40;
 }
+
 struct OpWs {
-    HLevel H;
+    HLevel<double> H;
     double *out[2];
     double *coarse[2];
 };
@@ -653,7 +742,7 @@ mg_status op_layout(int n, double h, void *ws, size_t ws_bytes, OpWs &W) {
     if (!(h > 0.0)) return fail(MG_ERR_ARG, "h must be > 0");
     if (!ws || ws_bytes < op_workspace_bytes(n)) return fail(MG_ERR_WORKSPACE, "workspace too small");
     Carve cv{static_cast<char *>(ws), 0};
-    HLevel &H = W.H;
+    HLevel<double> &H = W.H;
     H.n = n;
     H.logn = ilog2(n);
     H.h = h;
@@ -670,36 +759,44 @@ mg_status op_layout(int n, double h, void *ws, size_t ws_bytes, OpWs &W) {
 }
 
 template <int OP>
-void op_residual_launch(const Mod &M, OpWs &W, const double *fptr, hipStream_t s, bool with_f,
-                        unsigned long long *clamp) {
-    HLevel &H = W.H;
-    k_residual<OP><<<nblocks(2 * H.half), TPB, 0, s>>>(M, view(H, with_f), coefs(H), fptr, 1.0,
-                                                       W.out[0], W.out[1], clamp);
+void op_residual_launch(const Mod &M, OpWs &W, hipStream_t s, bool with_f) {
+    HLevel<double> &H = W.H;
+    k_residual<OP><<<nblocks(2 * H.half), TPB, 0, s>>>(M, view(H, with_f), coefs(H), nullptr, 1.0,
+                                                       W.out[0], W.out[1], nullptr);
 }
 
 template <int OP>
-void op_pass_launch(const Mod &M, OpWs &W, int colour, hipStream_t s, bool with_f) {
-    HLevel &H = W.H;
-    launch_pass<OP>(M, view(H, with_f), coefs(H), colour, colour ? W.out[1] : W.out[0], nullptr,
-                    0.0, nullptr, s);
-}
-}  // namespace
-
-// ===================================================================== C ABI
-
-extern "C" {
-
-size_t mg_workspace_bytes(int n, int precision, int model, int adjoint) {
-    if (!is_pow2(n) || n < 8 || n > 2048 || precision != MG_FP64 || model < 0 || model > 2)
-        return 0;
-    Ctx C;
-    Carve cv{nullptr, 0};
-    layout(C, cv, n, adjoint != 0);
-    return cv.off + 256;
+void op_pass_launch(const Mod &M, OpWs &W, int colour, hipStream_t s) {
+    HLevel<double> &H = W.H;
+    launch_pass<OP, double>(M, view(H, true), coefs(H), colour, colour ? W.out[1] : W.out[0],
+                            nullptr, 0.0, nullptr, s);
 }
 
-static mg_status common_checks(const mg_opts *o, const void *delta, const void *phi, void *ws,
-                               mg_stats *st) {
+void pack_f(OpWs &W, const double *f, double fs, hipStream_t s) {
+    HLevel<double> &H = W.H;
+    if (f)
+        k_pack<double, double><<<nblocks(2 * H.half), TPB, 0, s>>>(f, H.logn, H.f[0], H.f[1],
+                                                                   nullptr);
+    else {
+        k_fill<<<nblocks(H.half), TPB, 0, s>>>(H.f[0], H.half, fs);
+        k_fill<<<nblocks(H.half), TPB, 0, s>>>(H.f[1], H.half, fs);
+    }
+}
+
+bool model_mod(int model, const void *params, int n, Mod &M) {
+    if (!params) return false;
+    if (model == MG_MODEL_DGP) return setup_dgp((const mg_dgp_params *)params, M);
+    if (model == MG_MODEL_KMOUFLAGE) return setup_kmo((const mg_kmo_params *)params, n, M);
+    if (model == MG_MODEL_POISSON) {
+        M = Mod{};
+        M.s = ((const mg_poisson_params *)params)->s;
+        return std::isfinite(M.s);
+    }
+    return false;
+}
+
+mg_status common_checks(const mg_opts *o, const void *delta, const void *phi, void *ws,
+                        mg_stats *st) {
     mg_status rc = check_opts(o);
     if (rc != MG_OK) return rc;
     if (!delta || !phi) return fail(MG_ERR_ARG, "delta and phi must be device pointers");
@@ -708,6 +805,22 @@ static mg_status common_checks(const mg_opts *o, const void *delta, const void *
     std::memset(st, 0, sizeof(*st));
     g_err.clear();
     return MG_OK;
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+
+extern "C" {
+
+size_t mg_workspace_bytes(int n, int precision, int model, int adjoint) {
+    if (!is_pow2(n) || n < 8 || n > 2048 || model < 0 || model > 2) return 0;
+    if (precision != MG_FP64 && precision != MG_MIXED) return 0;
+    if (adjoint && precision != MG_FP64) return 0;
+    Ctx C;
+    Carve cv{nullptr, 0};
+    layout(C, cv, n, adjoint != 0, precision == MG_MIXED);
+    return cv.off + 256;
 }
 
 mg_status mg_solve_dgp(const mg_opts *opts, const mg_dgp_params *par, const double *delta,
@@ -741,24 +854,13 @@ mg_status mg_solve_poisson(const mg_opts *opts, const mg_poisson_params *par, co
     return forward_solve<OP_POISSON>(opts, M, delta, phi, ws, ws_bytes, stream, stats);
 }
 
-static bool model_mod(int model, const void *params, int n, Mod &M) {
-    if (!params) return false;
-    if (model == MG_MODEL_DGP) return setup_dgp((const mg_dgp_params *)params, M);
-    if (model == MG_MODEL_KMOUFLAGE) return setup_kmo((const mg_kmo_params *)params, n, M);
-    if (model == MG_MODEL_POISSON) {
-        M = Mod{};
-        M.s = ((const mg_poisson_params *)params)->s;
-        return std::isfinite(M.s);
-    }
-    return false;
-}
-
 mg_status mg_solve_adjoint(const mg_opts *opts, int model, const void *params,
                            const double *delta, const double *phi, const double *w,
                            double *grad_delta, double *mu, void *ws, size_t ws_bytes,
                            hipStream_t stream, mg_stats *stats) {
     mg_status rc = common_checks(opts, delta, phi, ws, stats);
     if (rc != MG_OK) return rc;
+    if (opts->precision != MG_FP64) return fail(MG_ERR_ARG, "the adjoint solve is FP64 only");
     if (!w || !grad_delta || !mu) return fail(MG_ERR_ARG, "w, grad_delta and mu must be device pointers");
     Mod M;
     if (!model_mod(model, params, opts->n, M)) return fail(MG_ERR_ARG, "invalid model or parameters");
@@ -775,10 +877,7 @@ mg_status mg_solve_adjoint(const mg_opts *opts, int model, const void *params,
     }
 }
 
-// ------------------------------------------------------- single operations
-
 size_t mg_op_workspace_bytes(int n) { return op_workspace_bytes(n); }
-
 
 mg_status mg_op_residual(int model, const void *params, int n, double h, const double *phi,
                          const double *delta, const double *f, double fs, double *out, void *ws,
@@ -789,22 +888,17 @@ mg_status mg_op_residual(int model, const void *params, int n, double h, const d
     if (!phi || !delta || !out) return fail(MG_ERR_ARG, "NULL array");
     Mod M;
     if (!model_mod(model, params, n, M)) return fail(MG_ERR_ARG, "invalid model or parameters");
-    HLevel &H = W.H;
+    HLevel<double> &H = W.H;
     const unsigned nb = nblocks(2 * H.half);
-    k_pack<<<nb, TPB, 0, stream>>>(phi, H.logn, H.u[0], H.u[1], nullptr);
-    k_pack<<<nb, TPB, 0, stream>>>(delta, H.logn, H.d[0], H.d[1], nullptr);
-    // f: array, or a constant written into the f arrays
-    if (f) k_pack<<<nb, TPB, 0, stream>>>(f, H.logn, H.f[0], H.f[1], nullptr);
-    else {
-        k_fill<<<nblocks(H.half), TPB, 0, stream>>>(H.f[0], H.half, fs);
-        k_fill<<<nblocks(H.half), TPB, 0, stream>>>(H.f[1], H.half, fs);
-    }
+    k_pack<double, double><<<nb, TPB, 0, stream>>>(phi, H.logn, H.u[0], H.u[1], nullptr);
+    k_pack<double, double><<<nb, TPB, 0, stream>>>(delta, H.logn, H.d[0], H.d[1], nullptr);
+    pack_f(W, f, fs, stream);
     switch (model) {
-        case MG_MODEL_DGP: op_residual_launch<OP_DGP>(M, W, nullptr, stream, true, nullptr); break;
-        case MG_MODEL_KMOUFLAGE: op_residual_launch<OP_KMO>(M, W, nullptr, stream, true, nullptr); break;
-        default: op_residual_launch<OP_POISSON>(M, W, nullptr, stream, true, nullptr); break;
+        case MG_MODEL_DGP: op_residual_launch<OP_DGP>(M, W, stream, true); break;
+        case MG_MODEL_KMOUFLAGE: op_residual_launch<OP_KMO>(M, W, stream, true); break;
+        default: op_residual_launch<OP_POISSON>(M, W, stream, true); break;
     }
-    k_unpack<<<nb, TPB, 0, stream>>>(W.out[0], W.out[1], H.logn, out, nullptr);
+    k_unpack<double, double><<<nb, TPB, 0, stream>>>(W.out[0], W.out[1], H.logn, out, nullptr);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(stream));
     return MG_OK;
@@ -820,22 +914,18 @@ mg_status mg_op_colour_pass(int model, const void *params, int n, double h, int 
     if (colour != 0 && colour != 1) return fail(MG_ERR_ARG, "colour must be 0 or 1");
     Mod M;
     if (!model_mod(model, params, n, M)) return fail(MG_ERR_ARG, "invalid model or parameters");
-    HLevel &H = W.H;
+    HLevel<double> &H = W.H;
     const unsigned nb = nblocks(2 * H.half);
-    k_pack<<<nb, TPB, 0, stream>>>(phi_in, H.logn, H.u[0], H.u[1], nullptr);
-    k_pack<<<nb, TPB, 0, stream>>>(phi_in, H.logn, W.out[0], W.out[1], nullptr);
-    k_pack<<<nb, TPB, 0, stream>>>(delta, H.logn, H.d[0], H.d[1], nullptr);
-    if (f) k_pack<<<nb, TPB, 0, stream>>>(f, H.logn, H.f[0], H.f[1], nullptr);
-    else {
-        k_fill<<<nblocks(H.half), TPB, 0, stream>>>(H.f[0], H.half, fs);
-        k_fill<<<nblocks(H.half), TPB, 0, stream>>>(H.f[1], H.half, fs);
-    }
+    k_pack<double, double><<<nb, TPB, 0, stream>>>(phi_in, H.logn, H.u[0], H.u[1], nullptr);
+    k_pack<double, double><<<nb, TPB, 0, stream>>>(phi_in, H.logn, W.out[0], W.out[1], nullptr);
+    k_pack<double, double><<<nb, TPB, 0, stream>>>(delta, H.logn, H.d[0], H.d[1], nullptr);
+    pack_f(W, f, fs, stream);
     switch (model) {
-        case MG_MODEL_DGP: op_pass_launch<OP_DGP>(M, W, colour, stream, true); break;
-        case MG_MODEL_KMOUFLAGE: op_pass_launch<OP_KMO>(M, W, colour, stream, true); break;
-        default: op_pass_launch<OP_POISSON>(M, W, colour, stream, true); break;
+        case MG_MODEL_DGP: op_pass_launch<OP_DGP>(M, W, colour, stream); break;
+        case MG_MODEL_KMOUFLAGE: op_pass_launch<OP_KMO>(M, W, colour, stream); break;
+        default: op_pass_launch<OP_POISSON>(M, W, colour, stream); break;
     }
-    k_unpack<<<nb, TPB, 0, stream>>>(W.out[0], W.out[1], H.logn, phi_out, nullptr);
+    k_unpack<double, double><<<nb, TPB, 0, stream>>>(W.out[0], W.out[1], H.logn, phi_out, nullptr);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(stream));
     return MG_OK;
@@ -848,12 +938,13 @@ mg_status mg_op_restrict(int n, const double *fine, double *coarse, void *ws, si
     if (rc != MG_OK) return rc;
     if (n < 8) return fail(MG_ERR_ARG, "n must be >= 8");
     if (!fine || !coarse) return fail(MG_ERR_ARG, "NULL array");
-    HLevel &H = W.H;
-    k_pack<<<nblocks(2 * H.half), TPB, 0, stream>>>(fine, H.logn, H.u[0], H.u[1], nullptr);
-    k_restrict<<<nblocks(H.half / 4), TPB, 0, stream>>>(H.u[0], H.u[1], H.logn, W.coarse[0],
-                                                        W.coarse[1]);
-    k_unpack<<<nblocks(H.half / 4), TPB, 0, stream>>>(W.coarse[0], W.coarse[1], H.logn - 1,
-                                                      coarse, nullptr);
+    HLevel<double> &H = W.H;
+    k_pack<double, double><<<nblocks(2 * H.half), TPB, 0, stream>>>(fine, H.logn, H.u[0], H.u[1],
+                                                                    nullptr);
+    k_restrict<double><<<nblocks(H.half / 4), TPB, 0, stream>>>(H.u[0], H.u[1], H.logn,
+                                                                W.coarse[0], W.coarse[1]);
+    k_unpack<double, double><<<nblocks(H.half / 4), TPB, 0, stream>>>(W.coarse[0], W.coarse[1],
+                                                                      H.logn - 1, coarse, nullptr);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(stream));
     return MG_OK;
@@ -866,13 +957,17 @@ mg_status mg_op_prolong_add(int n, double *fine, const double *uc, const double 
     if (rc != MG_OK) return rc;
     if (n < 8) return fail(MG_ERR_ARG, "n must be >= 8");
     if (!fine || !uc || !rc_) return fail(MG_ERR_ARG, "NULL array");
-    HLevel &H = W.H;
+    HLevel<double> &H = W.H;
     const unsigned nbc = nblocks(H.half / 4);
-    k_pack<<<nblocks(2 * H.half), TPB, 0, stream>>>(fine, H.logn, H.u[0], H.u[1], nullptr);
-    k_pack<<<nbc, TPB, 0, stream>>>(uc, H.logn - 1, W.coarse[0], W.coarse[1], nullptr);
-    k_pack<<<nbc, TPB, 0, stream>>>(rc_, H.logn - 1, W.out[0], W.out[1], nullptr);
-    launch_prolong(H.u[0], H.u[1], H.logn, W.coarse[0], W.coarse[1], W.out[0], W.out[1], stream);
-    k_unpack<<<nblocks(2 * H.half), TPB, 0, stream>>>(H.u[0], H.u[1], H.logn, fine, nullptr);
+    k_pack<double, double><<<nblocks(2 * H.half), TPB, 0, stream>>>(fine, H.logn, H.u[0], H.u[1],
+                                                                    nullptr);
+    k_pack<double, double><<<nbc, TPB, 0, stream>>>(uc, H.logn - 1, W.coarse[0], W.coarse[1],
+                                                    nullptr);
+    k_pack<double, double><<<nbc, TPB, 0, stream>>>(rc_, H.logn - 1, W.out[0], W.out[1], nullptr);
+    launch_prolong<double>(H.u[0], H.u[1], H.logn, W.coarse[0], W.coarse[1], W.out[0], W.out[1],
+                           stream);
+    k_unpack<double, double><<<nblocks(2 * H.half), TPB, 0, stream>>>(H.u[0], H.u[1], H.logn,
+                                                                      fine, nullptr);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(stream));
     return MG_OK;
@@ -887,10 +982,10 @@ mg_status mg_op_jt_apply(int model, const void *params, int n, double h, const d
     if (!phi || !delta || !v || !out) return fail(MG_ERR_ARG, "NULL array");
     Mod M;
     if (!model_mod(model, params, n, M)) return fail(MG_ERR_ARG, "invalid model or parameters");
-    HLevel &H = W.H;
+    HLevel<double> &H = W.H;
     const unsigned nb = nblocks(2 * H.half);
-    k_pack<<<nb, TPB, 0, stream>>>(phi, H.logn, H.u[0], H.u[1], nullptr);
-    k_pack<<<nb, TPB, 0, stream>>>(delta, H.logn, H.d[0], H.d[1], nullptr);
+    k_pack<double, double><<<nb, TPB, 0, stream>>>(phi, H.logn, H.u[0], H.u[1], nullptr);
+    k_pack<double, double><<<nb, TPB, 0, stream>>>(delta, H.logn, H.d[0], H.d[1], nullptr);
     CoefsW Wc;
     for (int q = 0; q < 9; ++q)
         for (int c = 0; c < 2; ++c) Wc.c[q][c] = H.cf[q][c];
@@ -899,9 +994,9 @@ mg_status mg_op_jt_apply(int model, const void *params, int n, double h, const d
         case MG_MODEL_KMOUFLAGE: k_adj_coefs<MODEL_KMO><<<nb, TPB, 0, stream>>>(M, view(H, false), Wc, h); break;
         default: k_adj_coefs<MODEL_POISSON><<<nb, TPB, 0, stream>>>(M, view(H, false), Wc, h); break;
     }
-    k_pack<<<nb, TPB, 0, stream>>>(v, H.logn, H.u[0], H.u[1], nullptr);
-    op_residual_launch<OP_ADJ>(M, W, nullptr, stream, false, nullptr);
-    k_unpack<<<nb, TPB, 0, stream>>>(W.out[0], W.out[1], H.logn, out, nullptr);
+    k_pack<double, double><<<nb, TPB, 0, stream>>>(v, H.logn, H.u[0], H.u[1], nullptr);
+    op_residual_launch<OP_ADJ>(M, W, stream, false);
+    k_unpack<double, double><<<nb, TPB, 0, stream>>>(W.out[0], W.out[1], H.logn, out, nullptr);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(stream));
     return MG_OK;

@@ -8,6 +8,12 @@
 // colour, so every cell of the colour is updated from the pre-pass state
 // (the edge neighbours share the centre's colour).  Consecutive threads own
 // consecutive packed x positions, so every load and store is coalesced.
+//
+// Precision: the storage type R is double (FP64 solve) or float (the FP32
+// phase of the mixed solve).  With float storage a colour pass does its
+// stencil arithmetic in float but evaluates the discriminant, the square root
+// and the division of the closed-form update in double; residuals,
+// restriction sums and reductions are always evaluated in double.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -26,31 +32,36 @@ struct Mod {
     int nk;
 };
 
-// One level as seen by a kernel.
-struct Lvl {
-    double *u0, *u1;              // current field, colour 0 / colour 1
-    const double *d0, *d1;        // density contrast
-    const double *f0, *f1;        // FAS right-hand side (null: scalar mu)
+// One level as seen by a kernel (storage type R).
+template <typename R>
+struct LvlT {
+    R *u0, *u1;                   // current field, colour 0 / colour 1
+    const R *d0, *d1;             // density contrast
+    const R *f0, *f1;             // FAS right-hand side (null: scalar mu)
     int n, logn, lognh;
     double h2;                    // h^2
     double c3h4, c8h4;            // 1/(3 h^4), 1/(8 h^4)
     double c12h4, c4h2;           // 1/(12 h^4), 1/(4 h^2)
 };
+using Lvl = LvlT<double>;
 
 __device__ __forceinline__ size_t prow(int j, int k, int logn, int lognh) {
     return ((size_t)k << (logn + lognh)) + ((size_t)j << lognh);
 }
 
 // The 19-point neighbourhood of one cell in the form the operators need.
-struct Nb {
-    double xp, xm, yp, ym, zp, zm;   // face neighbours
-    double nxy, nxz, nyz;            // 4-point cross differences (x 4h^2 D_ij)
+template <typename T>
+struct NbT {
+    T xp, xm, yp, ym, zp, zm;   // face neighbours
+    T nxy, nxz, nyz;            // 4-point cross differences (x 4h^2 D_ij)
 };
+using Nb = NbT<double>;
 
 // Neighbourhood of the cell of colour c at packed (m, j, k).  A holds colour
 // c (edge neighbours), B colour 1-c (face neighbours).
-__device__ __forceinline__ Nb load_nb(const double *__restrict__ A, const double *__restrict__ B,
-                                      int c, int m, int j, int k, int n, int logn, int lognh) {
+template <typename T, typename R>
+__device__ __forceinline__ NbT<T> load_nb(const R *__restrict__ A, const R *__restrict__ B, int c,
+                                          int m, int j, int k, int n, int logn, int lognh) {
     const int nm1 = n - 1, hm1 = (n >> 1) - 1;
     const int p = (j + k + c) & 1;              // i = 2m + p
     const int mp = (m + p) & hm1;               // packed index of i+1
@@ -62,20 +73,21 @@ __device__ __forceinline__ Nb load_nb(const double *__restrict__ A, const double
     const size_t r0p = prow(j, kp, logn, lognh), r0m = prow(j, km, logn, lognh);
     const size_t rpp = prow(jp, kp, logn, lognh), rmm = prow(jm, km, logn, lognh);
     const size_t rpm = prow(jp, km, logn, lognh), rmp = prow(jm, kp, logn, lognh);
-    Nb s;
-    s.xp = B[r00 + mp];
-    s.xm = B[r00 + mm];
-    s.yp = B[rp0 + m];
-    s.ym = B[rm0 + m];
-    s.zp = B[r0p + m];
-    s.zm = B[r0m + m];
-    s.nxy = (A[rp0 + mp] + A[rm0 + mm]) - (A[rm0 + mp] + A[rp0 + mm]);
-    s.nxz = (A[r0p + mp] + A[r0m + mm]) - (A[r0m + mp] + A[r0p + mm]);
-    s.nyz = (A[rpp + m] + A[rmm + m]) - (A[rpm + m] + A[rmp + m]);
+    NbT<T> s;
+    s.xp = (T)B[r00 + mp];
+    s.xm = (T)B[r00 + mm];
+    s.yp = (T)B[rp0 + m];
+    s.ym = (T)B[rm0 + m];
+    s.zp = (T)B[r0p + m];
+    s.zm = (T)B[r0m + m];
+    s.nxy = ((T)A[rp0 + mp] + (T)A[rm0 + mm]) - ((T)A[rm0 + mp] + (T)A[rp0 + mm]);
+    s.nxz = ((T)A[r0p + mp] + (T)A[r0m + mm]) - ((T)A[r0m + mp] + (T)A[r0p + mm]);
+    s.nyz = ((T)A[rpp + m] + (T)A[rmm + m]) - ((T)A[rpm + m] + (T)A[rmp + m]);
     return s;
 }
 
-// Model term K of L = lap(phi) - K at one cell.  K never involves the centre
+// Model term K of L = lap(phi) - K at one cell, arithmetic type T for the
+// stencil combinations, double for the root.  K never involves the centre
 // value, so a colour pass solves each cell's equation exactly.
 //
 // nDGP (Sec. 3.2.3): Sigma = hat(H):hat(H) + s delta where, with
@@ -85,37 +97,38 @@ __device__ __forceinline__ Nb load_nb(const double *__restrict__ A, const double
 // and the root of eq:DGP, (3/4)[-alpha + sign(alpha) sqrt(alpha^2+8 Sigma/3)],
 // is evaluated as 2 Sigma / (alpha + sign(alpha) sqrt(D)), which does not
 // cancel when Sigma << alpha^2.  D < 0 is clamped (Sigma raised to -3 alpha^2/8).
-template <int MODEL>
-__device__ __forceinline__ double model_term(const Mod &M, const Lvl &L, const Nb &s, double delta,
-                                             unsigned long long *clamp) {
-    if (MODEL == MODEL_POISSON) return M.s * delta;
-    const double ax = s.xp + s.xm, ay = s.yp + s.ym, az = s.zp + s.zm;
+template <int MODEL, typename T, typename L_>
+__device__ __forceinline__ T model_term(const Mod &M, const L_ &L, const NbT<T> &s, T delta,
+                                        unsigned long long *clamp) {
+    if (MODEL == MODEL_POISSON) return (T)M.s * delta;
+    const T ax = s.xp + s.xm, ay = s.yp + s.ym, az = s.zp + s.zm;
     if (MODEL == MODEL_DGP) {
-        const double dxy = ax - ay, dxz = ax - az, dyz = ay - az;
-        double sig = (dxy * dxy + dxz * dxz + dyz * dyz) * L.c3h4
-                   + (s.nxy * s.nxy + s.nxz * s.nxz + s.nyz * s.nyz) * L.c8h4 + M.s * delta;
+        const T dxy = ax - ay, dxz = ax - az, dyz = ay - az;
+        const T t3 = dxy * dxy + dxz * dxz + dyz * dyz;
+        const T t8 = s.nxy * s.nxy + s.nxz * s.nxz + s.nyz * s.nyz;
+        double sig = (double)t3 * L.c3h4 + (double)t8 * L.c8h4 + M.s * (double)delta;
         double disc = M.alpha * M.alpha + (8.0 / 3.0) * sig;
         if (disc < 0.0) {
             sig = -0.375 * M.alpha * M.alpha;
             disc = 0.0;
             if (clamp) atomicAdd(clamp, 1ull);
         }
-        return 2.0 * sig / (M.alpha + M.sgn * sqrt(disc));
+        return (T)(2.0 * sig / (M.alpha + M.sgn * sqrt(disc)));
     }
     // Kmouflage split form eq:kmf_eqn_codeunit_final: with e = 2h grad phi,
     //   g = |e|^2/(4h^2),  Q = hat(H)_ij G_i G_j
     //     = [e_x^2 (2A_x-A_y-A_z) + ...]/(12 h^4) + (N_xy e_x e_y + ...)/(8 h^4),
     //   K = (src delta + b2 g^(n-2) Q) / (c~ (c0 + a1 g^(n-1))).
-    const double ex = s.xp - s.xm, ey = s.yp - s.ym, ez = s.zp - s.zm;
-    const double g = (ex * ex + ey * ey + ez * ez) * L.c4h2;
-    const double q = (ex * ex * (2.0 * ax - ay - az) + ey * ey * (2.0 * ay - ax - az)
-                      + ez * ez * (2.0 * az - ax - ay)) * L.c12h4
-                   + (s.nxy * ex * ey + s.nxz * ex * ez + s.nyz * ey * ez) * L.c8h4;
+    const T ex = s.xp - s.xm, ey = s.yp - s.ym, ez = s.zp - s.zm;
+    const double g = (double)(ex * ex + ey * ey + ez * ez) * L.c4h2;
+    const double q = (double)(ex * ex * (2 * ax - ay - az) + ey * ey * (2 * ay - ax - az)
+                              + ez * ez * (2 * az - ax - ay)) * L.c12h4
+                   + (double)(s.nxy * ex * ey + s.nxz * ex * ez + s.nyz * ey * ez) * L.c8h4;
     double gn2 = 1.0;
     for (int t = 0; t < M.nk - 2; ++t) gn2 *= g;
     const double sig1 = M.c0 + M.a1 * gn2 * g;
     const double sig2 = M.b2 * gn2 * q;
-    return (M.src * delta + sig2) / (M.ctil * sig1);
+    return (T)((M.src * (double)delta + sig2) / (M.ctil * sig1));
 }
 
 }  // namespace mgk

@@ -2,6 +2,8 @@
 // layout.  Every kernel is one thread per cell (or per coarse cell), 256
 // threads per block, with the block index remapped so that each of the 8
 // XCDs works on a contiguous z-slab (its halo rows stay in its own L2).
+// R is the storage type (double, or float for the FP32 phase of the mixed
+// solve); the adjoint operator exists for double only.
 #pragma once
 #include "mg_device.h"
 
@@ -36,19 +38,18 @@ struct Coefs {
 };
 
 // Sum of the six face values and the non-Laplacian term at the cell of
-// colour c, packed (m, j, k).
-template <int OP>
-__device__ __forceinline__ double cell_term(const Mod &M, const Lvl &L, const Coefs &Cf, int c,
-                                            int m, int j, int k, double &faces,
-                                            unsigned long long *clamp) {
-    const double *A = c ? L.u1 : L.u0;
-    const double *B = c ? L.u0 : L.u1;
+// colour c, packed (m, j, k), in arithmetic type T.
+template <int OP, typename T, typename R>
+__device__ __forceinline__ T cell_term(const Mod &M, const LvlT<R> &L, const Coefs &Cf, int c,
+                                       int m, int j, int k, T &faces, unsigned long long *clamp) {
+    const R *A = c ? L.u1 : L.u0;
+    const R *B = c ? L.u0 : L.u1;
     if (OP != OP_ADJ) {
-        const Nb s = load_nb(A, B, c, m, j, k, L.n, L.logn, L.lognh);
+        const NbT<T> s = load_nb<T, R>(A, B, c, m, j, k, L.n, L.logn, L.lognh);
         faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
-        const double *D = c ? L.d1 : L.d0;
-        const double delta = D[prow(j, k, L.logn, L.lognh) + m];
-        return model_term<OP>(M, L, s, delta, clamp);
+        const R *D = c ? L.d1 : L.d0;
+        const T delta = (T)D[prow(j, k, L.logn, L.lognh) + m];
+        return model_term<OP == OP_ADJ ? OP_DGP : OP, T>(M, L, s, delta, clamp);
     } else {
         // (J^T mu)_p = lap(mu)_p - sum over the neighbours q of p of
         // dK_q/dphi_p mu_q.  The face neighbour at p - x carries its x+
@@ -68,11 +69,11 @@ __device__ __forceinline__ double cell_term(const Mod &M, const Lvl &L, const Co
         const int o = c ^ 1;
         const size_t ixp = r00 + mp, ixm = r00 + mm, iyp = rp0 + m, iym = rm0 + m,
                      izp = r0p + m, izm = r0m + m;
-        const double vxp = B[ixp], vxm = B[ixm], vyp = B[iyp], vym = B[iym], vzp = B[izp],
-                     vzm = B[izm];
+        const T vxp = B[ixp], vxm = B[ixm], vyp = B[iyp], vym = B[iym], vzp = B[izp],
+                vzm = B[izm];
         faces = (vxp + vxm) + (vyp + vym) + (vzp + vzm);
-        double g = Cf.c[0][o][ixm] * vxm + Cf.c[1][o][ixp] * vxp + Cf.c[2][o][iym] * vym
-                 + Cf.c[3][o][iyp] * vyp + Cf.c[4][o][izm] * vzm + Cf.c[5][o][izp] * vzp;
+        T g = Cf.c[0][o][ixm] * vxm + Cf.c[1][o][ixp] * vxp + Cf.c[2][o][iym] * vym
+            + Cf.c[3][o][iyp] * vyp + Cf.c[4][o][izm] * vzm + Cf.c[5][o][izp] * vzp;
         const double *exy = Cf.c[6][c], *exz = Cf.c[7][c], *eyz = Cf.c[8][c];
         g += (exy[rm0 + mm] * A[rm0 + mm] + exy[rp0 + mp] * A[rp0 + mp])
            - (exy[rp0 + mm] * A[rp0 + mm] + exy[rm0 + mp] * A[rm0 + mp]);
@@ -85,19 +86,20 @@ __device__ __forceinline__ double cell_term(const Mod &M, const Lvl &L, const Co
     }
 }
 
-__device__ __forceinline__ double rhs_at(const Lvl &L, int c, size_t idx, const double *fptr,
-                                         double fscale) {
-    const double *fa = c ? L.f1 : L.f0;
-    double f = fa ? fa[idx] : 0.0;
-    if (fptr) f += fscale * (*fptr);
+template <typename T, typename R>
+__device__ __forceinline__ T rhs_at(const LvlT<R> &L, int c, size_t idx, const double *fptr,
+                                    double fscale) {
+    const R *fa = c ? L.f1 : L.f0;
+    T f = fa ? (T)fa[idx] : (T)0;
+    if (fptr) f += (T)(fscale * (*fptr));
     return f;
 }
 
 // One colour pass: every cell of colour c gets the exact solution of its own
 // equation (faces - 6 u)/h^2 - K = f given its neighbours.
-template <int OP>
-__global__ __launch_bounds__(TPB) void k_pass(Mod M, Lvl L, Coefs Cf, int c,
-                                              double *__restrict__ out, const double *fptr,
+template <int OP, typename R>
+__global__ __launch_bounds__(TPB) void k_pass(Mod M, LvlT<R> L, Coefs Cf, int c,
+                                              R *__restrict__ out, const double *fptr,
                                               double fscale, unsigned long long *clamp) {
     const size_t t = xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
     const size_t half = (size_t)1 << (3 * L.logn - 1);
@@ -105,10 +107,10 @@ __global__ __launch_bounds__(TPB) void k_pass(Mod M, Lvl L, Coefs Cf, int c,
     const int m = (int)(t & ((1u << L.lognh) - 1));
     const int j = (int)((t >> L.lognh) & (L.n - 1));
     const int k = (int)(t >> (L.lognh + L.logn));
-    double faces;
-    const double K = cell_term<OP>(M, L, Cf, c, m, j, k, faces, clamp);
-    const double f = rhs_at(L, c, t, fptr, fscale);
-    out[t] = (faces - L.h2 * (K + f)) * (1.0 / 6.0);
+    R faces;
+    const R K = cell_term<OP, R, R>(M, L, Cf, c, m, j, k, faces, clamp);
+    const R f = rhs_at<R, R>(L, c, t, fptr, fscale);
+    out[t] = (faces - (R)L.h2 * (K + f)) * (R)(1.0 / 6.0);
 }
 
 // Deterministic block sum of two values into partials[2*blk .. 2*blk+1].
@@ -135,13 +137,13 @@ __device__ __forceinline__ void block_sum2(double a, double b, double *partials,
     }
 }
 
-// Residual d = (faces - 6u)/h^2 - K - f at the 8 children of every coarse
-// cell, restricted (8-cell mean) together with u.  With REDUCE the block
-// sums of d and d^2 go to partials (finest level: residual norm and mean).
-template <int OP, bool REDUCE>
-__device__ __forceinline__ void dev_resid_restrict(const Mod &M, const Lvl &L, const Coefs &Cf,
-                                                   const double *fptr, double fscale, double *ru0,
-                                                   double *ru1, double *rd0, double *rd1,
+// Residual d = (faces - 6u)/h^2 - K - f (double arithmetic) at the 8 children
+// of coarse cell t, restricted (8-cell mean) together with u.  With REDUCE
+// the sums of d and d^2 accumulate into s1, s2 (finest level: norm and mean).
+template <int OP, bool REDUCE, typename R>
+__device__ __forceinline__ void dev_resid_restrict(const Mod &M, const LvlT<R> &L, const Coefs &Cf,
+                                                   const double *fptr, double fscale, R *ru0,
+                                                   R *ru1, R *rd0, R *rd1,
                                                    unsigned long long *clamp, size_t t, double &s1,
                                                    double &s2) {
     const int lnc = L.logn - 1, nc = 1 << lnc;
@@ -158,10 +160,11 @@ __device__ __forceinline__ void dev_resid_restrict(const Mod &M, const Lvl &L, c
             const int j = 2 * J + b, k = 2 * K + cc;
             const int col = (a + b + cc) & 1;
             double faces;
-            const double term = cell_term<OP>(M, L, Cf, col, I, j, k, faces, clamp);
+            const double term = cell_term<OP, double, R>(M, L, Cf, col, I, j, k, faces, clamp);
             const size_t idx = prow(j, k, L.logn, L.lognh) + I;
-            const double u = (col ? L.u1 : L.u0)[idx];
-            const double d = (faces - 6.0 * u) * inv_h2 - term - rhs_at(L, col, idx, fptr, fscale);
+            const double u = (double)(col ? L.u1 : L.u0)[idx];
+            const double d = (faces - 6.0 * u) * inv_h2 - term
+                           - rhs_at<double, R>(L, col, idx, fptr, fscale);
             sd += d;
             su += u;
             if (REDUCE) {
@@ -171,30 +174,29 @@ __device__ __forceinline__ void dev_resid_restrict(const Mod &M, const Lvl &L, c
         }
         const int ccol = (I + J + K) & 1;
         const size_t cidx = ((size_t)K << (2 * lnc - 1)) + ((size_t)J << (lnc - 1)) + (I >> 1);
-        (ccol ? ru1 : ru0)[cidx] = 0.125 * su;
-        (ccol ? rd1 : rd0)[cidx] = 0.125 * sd;
+        (ccol ? ru1 : ru0)[cidx] = (R)(0.125 * su);
+        (ccol ? rd1 : rd0)[cidx] = (R)(0.125 * sd);
     }
 }
 
-template <int OP, bool REDUCE>
-__global__ __launch_bounds__(TPB) void k_resid_restrict(Mod M, Lvl L, Coefs Cf, const double *fptr,
-                                                        double fscale, double *ru0, double *ru1,
-                                                        double *rd0, double *rd1,
-                                                        double *partials,
+template <int OP, bool REDUCE, typename R>
+__global__ __launch_bounds__(TPB) void k_resid_restrict(Mod M, LvlT<R> L, Coefs Cf,
+                                                        const double *fptr, double fscale, R *ru0,
+                                                        R *ru1, R *rd0, R *rd1, double *partials,
                                                         unsigned long long *clamp) {
     const size_t blk = xcd_block(blockIdx.x, gridDim.x);
     const size_t t = blk * TPB + threadIdx.x;
     double s1 = 0.0, s2 = 0.0;
-    dev_resid_restrict<OP, REDUCE>(M, L, Cf, fptr, fscale, ru0, ru1, rd0, rd1, clamp, t, s1, s2);
+    dev_resid_restrict<OP, REDUCE, R>(M, L, Cf, fptr, fscale, ru0, ru1, rd0, rd1, clamp, t, s1, s2);
     if (REDUCE) block_sum2(s1, s2, partials, blk);
 }
 
 // FAS source on the coarse level: S = L^H(R u) - (R d - shift), written over
 // the restricted residual; the coarse unknown starts from R u.
-template <int OP>
-__device__ __forceinline__ void dev_coarse_source(const Mod &M, const Lvl &Lc, const Coefs &Cf,
-                                                  double *s0, double *s1, double *u0, double *u1,
-                                                  const double *shift, size_t t) {
+template <int OP, typename R>
+__device__ __forceinline__ void dev_coarse_source(const Mod &M, const LvlT<R> &Lc, const Coefs &Cf,
+                                                  R *s0, R *s1, R *u0, R *u1, const double *shift,
+                                                  size_t t) {
     const size_t half = (size_t)1 << (3 * Lc.logn - 1);
     if (t >= 2 * half) return;
     const int c = t >= half;
@@ -203,26 +205,25 @@ __device__ __forceinline__ void dev_coarse_source(const Mod &M, const Lvl &Lc, c
     const int j = (int)((tt >> Lc.lognh) & (Lc.n - 1));
     const int k = (int)(tt >> (Lc.lognh + Lc.logn));
     double faces;
-    const double term = cell_term<OP>(M, Lc, Cf, c, m, j, k, faces, nullptr);
-    const double ru = (c ? Lc.u1 : Lc.u0)[tt];
-    double *S = c ? s1 : s0;
-    const double rd = S[tt] - (shift ? *shift : 0.0);
-    S[tt] = (faces - 6.0 * ru) / Lc.h2 - term - rd;
+    const double term = cell_term<OP, double, R>(M, Lc, Cf, c, m, j, k, faces, nullptr);
+    const R ru = (c ? Lc.u1 : Lc.u0)[tt];
+    R *S = c ? s1 : s0;
+    const double rd = (double)S[tt] - (shift ? *shift : 0.0);
+    S[tt] = (R)((faces - 6.0 * (double)ru) / Lc.h2 - term - rd);
     (c ? u1 : u0)[tt] = ru;
 }
 
-template <int OP>
-__global__ __launch_bounds__(TPB) void k_coarse_source(Mod M, Lvl Lc, Coefs Cf, double *s0,
-                                                       double *s1, double *u0, double *u1,
-                                                       const double *shift) {
+template <int OP, typename R>
+__global__ __launch_bounds__(TPB) void k_coarse_source(Mod M, LvlT<R> Lc, Coefs Cf, R *s0, R *s1,
+                                                       R *u0, R *u1, const double *shift) {
     const size_t t = xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
-    dev_coarse_source<OP>(M, Lc, Cf, s0, s1, u0, u1, shift, t);
+    dev_coarse_source<OP, R>(M, Lc, Cf, s0, s1, u0, u1, shift, t);
 }
 
 // u_fine += P(uc - rc) with the cell-centred trilinear weights 27/9/3/1 (/64).
-__device__ __forceinline__ void dev_prolong(double *f0, double *f1, int logn, const double *uc0,
-                                            const double *uc1, const double *rc0,
-                                            const double *rc1, size_t t) {
+template <typename R>
+__device__ __forceinline__ void dev_prolong(R *f0, R *f1, int logn, const R *uc0, const R *uc1,
+                                            const R *rc0, const R *rc1, size_t t) {
     const int n = 1 << logn, lognh = logn - 1;
     const size_t half = (size_t)1 << (3 * logn - 1);
     if (t >= 2 * half) return;
@@ -241,23 +242,26 @@ __device__ __forceinline__ void dev_prolong(double *f0, double *f1, int logn, co
         const int a = q & 1, b = (q >> 1) & 1, cc = q >> 2;
         const int I2 = (I + a * di) & ncm1, J2 = (J + b * dj) & ncm1, K2 = (K + cc * dk) & ncm1;
         const size_t idx = ((size_t)K2 << (2 * lnc - 1)) + ((size_t)J2 << (lnc - 1)) + (I2 >> 1);
-        const double v = ((I2 + J2 + K2) & 1) ? (uc1[idx] - rc1[idx]) : (uc0[idx] - rc0[idx]);
+        const double v = ((I2 + J2 + K2) & 1) ? ((double)uc1[idx] - (double)rc1[idx])
+                                              : ((double)uc0[idx] - (double)rc0[idx]);
         const double w = (a ? 1.0 : 3.0) * (b ? 1.0 : 3.0) * (cc ? 1.0 : 3.0);
         acc += w * v;
     }
-    (c ? f1 : f0)[tt] += acc * (1.0 / 64.0);
+    R *f = c ? f1 : f0;
+    f[tt] = (R)((double)f[tt] + acc * (1.0 / 64.0));
 }
 
-__global__ __launch_bounds__(TPB) void k_prolong(double *f0, double *f1, int logn,
-                                                 const double *uc0, const double *uc1,
-                                                 const double *rc0, const double *rc1) {
+template <typename R>
+__global__ __launch_bounds__(TPB) void k_prolong(R *f0, R *f1, int logn, const R *uc0,
+                                                 const R *uc1, const R *rc0, const R *rc1) {
     const size_t t = xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
-    dev_prolong(f0, f1, logn, uc0, uc1, rc0, rc1, t);
+    dev_prolong<R>(f0, f1, logn, uc0, uc1, rc0, rc1, t);
 }
 
 // 8-cell mean of a packed field (density hierarchy, linearisation points).
-__global__ __launch_bounds__(TPB) void k_restrict(const double *f0, const double *f1, int logn,
-                                                  double *c0, double *c1) {
+template <typename R>
+__global__ __launch_bounds__(TPB) void k_restrict(const R *f0, const R *f1, int logn, R *c0,
+                                                  R *c1) {
     const size_t t = xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
     const int lnc = logn - 1, nc = 1 << lnc;
     if (t >= ((size_t)1 << (3 * lnc))) return;
@@ -268,44 +272,55 @@ __global__ __launch_bounds__(TPB) void k_restrict(const double *f0, const double
         const int a = q & 1, b = (q >> 1) & 1, cc = q >> 2;
         const int j = 2 * J + b, k = 2 * K + cc;
         const size_t idx = ((size_t)k << (2 * logn - 1)) + ((size_t)j << (logn - 1)) + I;
-        s += ((a + b + cc) & 1) ? f1[idx] : f0[idx];
+        s += ((a + b + cc) & 1) ? (double)f1[idx] : (double)f0[idx];
     }
     const size_t cidx = ((size_t)K << (2 * lnc - 1)) + ((size_t)J << (lnc - 1)) + (I >> 1);
-    (((I + J + K) & 1) ? c1 : c0)[cidx] = 0.125 * s;
+    (((I + J + K) & 1) ? c1 : c0)[cidx] = (R)(0.125 * s);
 }
 
-// natural [z][y][x] -> packed colours (optionally minus a device scalar)
-__global__ __launch_bounds__(TPB) void k_pack(const double *nat, int logn, double *c0, double *c1,
+// natural [z][y][x] -> packed colours (optionally minus a device scalar),
+// converting the element type
+template <typename Rin, typename Rout>
+__global__ __launch_bounds__(TPB) void k_pack(const Rin *nat, int logn, Rout *c0, Rout *c1,
                                               const double *shift) {
     const size_t t = xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
     if (t >= ((size_t)1 << (3 * logn))) return;
     const int n = 1 << logn;
     const int i = (int)(t & (n - 1)), j = (int)((t >> logn) & (n - 1)), k = (int)(t >> (2 * logn));
     const size_t idx = ((size_t)k << (2 * logn - 1)) + ((size_t)j << (logn - 1)) + (i >> 1);
-    const double v = nat[t] - (shift ? *shift : 0.0);
-    (((i + j + k) & 1) ? c1 : c0)[idx] = v;
+    const double v = (double)nat[t] - (shift ? *shift : 0.0);
+    (((i + j + k) & 1) ? c1 : c0)[idx] = (Rout)v;
 }
 
 // packed colours -> natural (optionally minus a device scalar)
-__global__ __launch_bounds__(TPB) void k_unpack(const double *c0, const double *c1, int logn,
-                                                double *nat, const double *shift) {
+template <typename Rin, typename Rout>
+__global__ __launch_bounds__(TPB) void k_unpack(const Rin *c0, const Rin *c1, int logn,
+                                                Rout *nat, const double *shift) {
     const size_t t = xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
     if (t >= ((size_t)1 << (3 * logn))) return;
     const int n = 1 << logn;
     const int i = (int)(t & (n - 1)), j = (int)((t >> logn) & (n - 1)), k = (int)(t >> (2 * logn));
     const size_t idx = ((size_t)k << (2 * logn - 1)) + ((size_t)j << (logn - 1)) + (i >> 1);
-    const double v = (((i + j + k) & 1) ? c1 : c0)[idx];
-    nat[t] = v - (shift ? *shift : 0.0);
+    const double v = (double)(((i + j + k) & 1) ? c1 : c0)[idx];
+    nat[t] = (Rout)(v - (shift ? *shift : 0.0));
 }
 
-// Block sums of a (and a^2) over n elements of up to two arrays laid end to end.
-__global__ __launch_bounds__(TPB) void k_sum(const double *a0, const double *a1, size_t nhalf,
+// element-wise conversion between precisions (same packed layout)
+template <typename Rin, typename Rout>
+__global__ __launch_bounds__(TPB) void k_convert(const Rin *a, Rout *b, size_t n) {
+    const size_t t = (size_t)blockIdx.x * TPB + threadIdx.x;
+    if (t < n) b[t] = (Rout)a[t];
+}
+
+// Block sums of a (and a^2) over up to two arrays laid end to end.
+template <typename R>
+__global__ __launch_bounds__(TPB) void k_sum(const R *a0, const R *a1, size_t nhalf,
                                              double *partials) {
     const size_t blk = blockIdx.x;
     const size_t t = blk * TPB + threadIdx.x;
     double v = 0.0;
-    if (t < nhalf) v = a0[t];
-    else if (a1 && t < 2 * nhalf) v = a1[t - nhalf];
+    if (t < nhalf) v = (double)a0[t];
+    else if (a1 && t < 2 * nhalf) v = (double)a1[t - nhalf];
     block_sum2(v, v * v, partials, blk);
 }
 
@@ -364,11 +379,7 @@ __global__ void k_fill_u64(unsigned long long *a, size_t n) {
     if (t < n) a[t] = 0ull;
 }
 
-}  // namespace mgk
-
-namespace mgk {
-
-// Residual r = (faces - 6u)/h^2 - term - f at every cell, packed output.
+// Residual r = (faces - 6u)/h^2 - term - f at every cell, packed output (double).
 template <int OP>
 __global__ __launch_bounds__(TPB) void k_residual(Mod M, Lvl L, Coefs Cf, const double *fptr,
                                                   double fscale, double *r0, double *r1,
@@ -382,14 +393,11 @@ __global__ __launch_bounds__(TPB) void k_residual(Mod M, Lvl L, Coefs Cf, const 
     const int j = (int)((tt >> L.lognh) & (L.n - 1));
     const int k = (int)(tt >> (L.lognh + L.logn));
     double faces;
-    const double term = cell_term<OP>(M, L, Cf, c, m, j, k, faces, clamp);
+    const double term = cell_term<OP, double, double>(M, L, Cf, c, m, j, k, faces, clamp);
     const double u = (c ? L.u1 : L.u0)[tt];
-    (c ? r1 : r0)[tt] = (faces - 6.0 * u) / L.h2 - term - rhs_at(L, c, tt, fptr, fscale);
+    (c ? r1 : r0)[tt] = (faces - 6.0 * u) / L.h2 - term
+                      - rhs_at<double, double>(L, c, tt, fptr, fscale);
 }
-
-}  // namespace mgk
-
-namespace mgk {
 
 // ---------------------------------------------------------------- coarse tail
 // All levels from 16^3 down to 4^3 in one workgroup: the sub-cycle (smoothing,
@@ -401,22 +409,24 @@ constexpr int TAIL_THREADS = 1024;
 constexpr int TAIL_MAX_N = 16;   // <= 2048 cells per colour: 2 per thread
 constexpr int TAIL_MAX_LEVELS = 3;
 
+template <typename R>
 struct TailLv {
-    Lvl L;        // u, d and f (the FAS source, workspace: written by the tail) of the level
-    double *ru0, *ru1;   // R u of the finer level (unused on the first tail level)
+    LvlT<R> L;      // u, d and f (the FAS source, workspace: written by the tail)
+    R *ru0, *ru1;   // R u of the finer level (unused on the first tail level)
 };
 
+template <typename R>
 struct TailArgs {
     int nlev, nu1, nu2, nuc;
-    TailLv lv[TAIL_MAX_LEVELS];
+    TailLv<R> lv[TAIL_MAX_LEVELS];
     Coefs cf[TAIL_MAX_LEVELS];
 };
 
-template <int OP>
-__device__ void tail_pass(const Mod &M, const TailLv &T, const Coefs &Cf, int c) {
-    const Lvl &L = T.L;
+template <int OP, typename R>
+__device__ void tail_pass(const Mod &M, const TailLv<R> &T, const Coefs &Cf, int c) {
+    const LvlT<R> &L = T.L;
     const int half = 1 << (3 * L.logn - 1);
-    double nv[2];
+    R nv[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const int t = threadIdx.x + q * TAIL_THREADS;
@@ -424,9 +434,9 @@ __device__ void tail_pass(const Mod &M, const TailLv &T, const Coefs &Cf, int c)
             const int m = t & ((1 << L.lognh) - 1);
             const int j = (t >> L.lognh) & (L.n - 1);
             const int k = t >> (L.lognh + L.logn);
-            double faces;
-            const double K = cell_term<OP>(M, L, Cf, c, m, j, k, faces, nullptr);
-            nv[q] = (faces - L.h2 * (K + (c ? L.f1 : L.f0)[t])) * (1.0 / 6.0);
+            R faces;
+            const R K = cell_term<OP, R, R>(M, L, Cf, c, m, j, k, faces, nullptr);
+            nv[q] = (faces - (R)L.h2 * (K + (c ? L.f1 : L.f0)[t])) * (R)(1.0 / 6.0);
         }
     }
     __syncthreads();
@@ -438,82 +448,84 @@ __device__ void tail_pass(const Mod &M, const TailLv &T, const Coefs &Cf, int c)
     __syncthreads();
 }
 
-template <int OP>
-__device__ void tail_sweeps(const Mod &M, const TailLv &T, const Coefs &Cf, int count) {
+template <int OP, typename R>
+__device__ void tail_sweeps(const Mod &M, const TailLv<R> &T, const Coefs &Cf, int count) {
     for (int s = 0; s < count; ++s) {
-        tail_pass<OP>(M, T, Cf, 0);
-        tail_pass<OP>(M, T, Cf, 1);
+        tail_pass<OP, R>(M, T, Cf, 0);
+        tail_pass<OP, R>(M, T, Cf, 1);
     }
 }
 
-// Doubles of LDS the tail needs for levels l0 .. (u, d, f of every level,
+// Elements of LDS the tail needs for levels l0 .. (u, d, f of every level,
 // R u of every level below the first).
-__host__ __device__ inline int tail_lds_doubles(int logn0, int nl) {
+__host__ __device__ inline int tail_lds_elems(int logn0, int nl) {
     int tot = 0;
     for (int q = 0; q < nl; ++q) tot += (q ? 8 : 6) * (1 << (3 * (logn0 - q) - 1));
     return tot;
 }
 
-template <int OP, int NL>
-__device__ __forceinline__ void tail_down(const Mod &M, TailLv (&T)[NL], const Coefs (&Cf)[NL],
-                                          int nu1) {
+template <int OP, int NL, typename R>
+__device__ __forceinline__ void tail_down(const Mod &M, TailLv<R> (&T)[NL],
+                                          const Coefs (&Cf)[NL], int nu1) {
 #pragma unroll
     for (int l = 0; l < NL - 1; ++l) {
-        tail_sweeps<OP>(M, T[l], Cf[l], nu1);
-        TailLv &Tc = T[l + 1];
+        tail_sweeps<OP, R>(M, T[l], Cf[l], nu1);
+        TailLv<R> &Tc = T[l + 1];
         double s1 = 0.0, s2 = 0.0;
         const int ncoarse = 1 << (3 * Tc.L.logn);
         for (int t = threadIdx.x; t < ncoarse; t += TAIL_THREADS)
-            dev_resid_restrict<OP, false>(M, T[l].L, Cf[l], nullptr, 0.0, Tc.ru0, Tc.ru1,
-                                          const_cast<double *>(Tc.L.f0),
-                                          const_cast<double *>(Tc.L.f1), nullptr, (size_t)t, s1,
-                                          s2);
+            dev_resid_restrict<OP, false, R>(M, T[l].L, Cf[l], nullptr, 0.0, Tc.ru0, Tc.ru1,
+                                             const_cast<R *>(Tc.L.f0), const_cast<R *>(Tc.L.f1),
+                                             nullptr, (size_t)t, s1, s2);
         __syncthreads();
-        Lvl Lr = Tc.L;
+        LvlT<R> Lr = Tc.L;
         Lr.u0 = Tc.ru0;
         Lr.u1 = Tc.ru1;
         for (int t = threadIdx.x; t < ncoarse; t += TAIL_THREADS)
-            dev_coarse_source<OP>(M, Lr, Cf[l + 1], const_cast<double *>(Tc.L.f0),
-                                  const_cast<double *>(Tc.L.f1), Tc.L.u0, Tc.L.u1, nullptr,
-                                  (size_t)t);
+            dev_coarse_source<OP, R>(M, Lr, Cf[l + 1], const_cast<R *>(Tc.L.f0),
+                                     const_cast<R *>(Tc.L.f1), Tc.L.u0, Tc.L.u1, nullptr,
+                                     (size_t)t);
         __syncthreads();
     }
 }
 
-template <int OP, int NL>
-__device__ __forceinline__ void tail_up(const Mod &M, TailLv (&T)[NL], const Coefs (&Cf)[NL],
+template <int OP, int NL, typename R>
+__device__ __forceinline__ void tail_up(const Mod &M, TailLv<R> (&T)[NL], const Coefs (&Cf)[NL],
                                         int nu2) {
 #pragma unroll
     for (int l = NL - 2; l >= 0; --l) {
-        const TailLv &Tf = T[l], &Tc = T[l + 1];
+        const TailLv<R> &Tf = T[l], &Tc = T[l + 1];
         const int nfine = 1 << (3 * Tf.L.logn);
         for (int t = threadIdx.x; t < nfine; t += TAIL_THREADS)
-            dev_prolong(Tf.L.u0, Tf.L.u1, Tf.L.logn, Tc.L.u0, Tc.L.u1, Tc.ru0, Tc.ru1, (size_t)t);
+            dev_prolong<R>(Tf.L.u0, Tf.L.u1, Tf.L.logn, Tc.L.u0, Tc.L.u1, Tc.ru0, Tc.ru1,
+                           (size_t)t);
         __syncthreads();
-        tail_sweeps<OP>(M, Tf, Cf[l], nu2);
+        tail_sweeps<OP, R>(M, Tf, Cf[l], nu2);
     }
 }
 
-__device__ __forceinline__ void lds_copy(double *dst, const double *src, int n) {
+template <typename R>
+__device__ __forceinline__ void lds_copy(R *dst, const R *src, int n) {
     for (int t = threadIdx.x; t < n; t += TAIL_THREADS) dst[t] = src[t];
 }
 
 // The tail levels live in LDS for the whole sub-cycle: their fields are
 // copied in, the sub-cycle runs on LDS, and the first level's u goes back.
-template <int OP, int NL>
-__global__ __launch_bounds__(TAIL_THREADS) void k_tail(Mod M, TailArgs A) {
-    extern __shared__ double lds[];
-    TailLv T[NL];
+template <int OP, int NL, typename R>
+__global__ __launch_bounds__(TAIL_THREADS) void k_tail(Mod M, TailArgs<R> A) {
+    extern __shared__ double lds_raw[];
+    R *lds = reinterpret_cast<R *>(lds_raw);
+    TailLv<R> T[NL];
     Coefs Cf[NL];
-    double *p = lds;
+    R *p = lds;
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
-        const TailLv &G = A.lv[q];
+        const TailLv<R> &G = A.lv[q];
         const int half = 1 << (3 * G.L.logn - 1);
         T[q] = G;
         Cf[q] = A.cf[q];
-        double *u0 = p, *u1 = p + half, *d0 = p + 2 * half, *d1 = p + 3 * half;
-        double *f0 = p + 4 * half, *f1 = p + 5 * half;
+        R *u0 = p, *u1 = p + half, *d0 = p + 2 * half, *d1 = p + 3 * half;
+        R *f0 = p + 4 * half, *f1 = p + 5 * half;
         p += 6 * half;
         T[q].L.u0 = u0;
         T[q].L.u1 = u1;
@@ -521,13 +533,13 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Mod M, TailArgs A) {
         T[q].L.d1 = d1;
         T[q].L.f0 = f0;
         T[q].L.f1 = f1;
-        lds_copy(d0, G.L.d0, half);
-        lds_copy(d1, G.L.d1, half);
+        lds_copy<R>(d0, G.L.d0, half);
+        lds_copy<R>(d1, G.L.d1, half);
         if (q == 0) {
-            lds_copy(u0, G.L.u0, half);
-            lds_copy(u1, G.L.u1, half);
-            lds_copy(f0, G.L.f0, half);
-            lds_copy(f1, G.L.f1, half);
+            lds_copy<R>(u0, G.L.u0, half);
+            lds_copy<R>(u1, G.L.u1, half);
+            lds_copy<R>(f0, G.L.f0, half);
+            lds_copy<R>(f1, G.L.f1, half);
         } else {
             T[q].ru0 = p;
             T[q].ru1 = p + half;
@@ -535,12 +547,12 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Mod M, TailArgs A) {
         }
     }
     __syncthreads();
-    tail_down<OP, NL>(M, T, Cf, A.nu1);
-    tail_sweeps<OP>(M, T[NL - 1], Cf[NL - 1], A.nuc);
-    tail_up<OP, NL>(M, T, Cf, A.nu2);
+    tail_down<OP, NL, R>(M, T, Cf, A.nu1);
+    tail_sweeps<OP, R>(M, T[NL - 1], Cf[NL - 1], A.nuc);
+    tail_up<OP, NL, R>(M, T, Cf, A.nu2);
     const int half0 = 1 << (3 * A.lv[0].L.logn - 1);
-    lds_copy(A.lv[0].L.u0, T[0].L.u0, half0);
-    lds_copy(A.lv[0].L.u1, T[0].L.u1, half0);
+    lds_copy<R>(A.lv[0].L.u0, T[0].L.u0, half0);
+    lds_copy<R>(A.lv[0].L.u1, T[0].L.u1, half0);
 }
 
 }  // namespace mgk

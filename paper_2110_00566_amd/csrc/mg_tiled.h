@@ -32,42 +32,42 @@ __device__ __forceinline__ size_t tile_gidx(int e, int j0, int m0, int k, int lo
 // Stencil of the cell at local (r, q) (halo-shifted tile coordinates) with
 // packed-x parity p, from staged planes: B = opposite colour at plane k,
 // A = own colour at k-1 / k / k+1, Bz = opposite colour at k-1 / k+1.
-__device__ __forceinline__ Nb lds_nb(const double *Am, const double *A0, const double *Ap,
-                                     const double *B0, const double *Bm, const double *Bp, int r,
-                                     int q, int p) {
+template <typename T, typename R>
+__device__ __forceinline__ NbT<T> lds_nb(const R *Am, const R *A0, const R *Ap, const R *B0,
+                                         const R *Bm, const R *Bp, int r, int q, int p) {
     const int qp = q + p, qm = q + p - 1;
     const int o = r * TXH, op = (r + 1) * TXH, om = (r - 1) * TXH;
-    Nb s;
-    s.xp = B0[o + qp];
-    s.xm = B0[o + qm];
-    s.yp = B0[op + q];
-    s.ym = B0[om + q];
-    s.zp = Bp[o + q];
-    s.zm = Bm[o + q];
-    s.nxy = (A0[op + qp] + A0[om + qm]) - (A0[om + qp] + A0[op + qm]);
-    s.nxz = (Ap[o + qp] + Am[o + qm]) - (Am[o + qp] + Ap[o + qm]);
-    s.nyz = (Ap[op + q] + Am[om + q]) - (Am[op + q] + Ap[om + q]);
+    NbT<T> s;
+    s.xp = (T)B0[o + qp];
+    s.xm = (T)B0[o + qm];
+    s.yp = (T)B0[op + q];
+    s.ym = (T)B0[om + q];
+    s.zp = (T)Bp[o + q];
+    s.zm = (T)Bm[o + q];
+    s.nxy = ((T)A0[op + qp] + (T)A0[om + qm]) - ((T)A0[om + qp] + (T)A0[op + qm]);
+    s.nxz = ((T)Ap[o + qp] + (T)Am[o + qm]) - ((T)Am[o + qp] + (T)Ap[o + qm]);
+    s.nyz = ((T)Ap[op + q] + (T)Am[om + q]) - ((T)Am[op + q] + (T)Ap[om + q]);
     return s;
 }
 
 // One colour pass (see k_pass) on an LDS-staged tile.
-template <int OP>
-__global__ __launch_bounds__(TPB) void k_pass_tiled(Mod M, Lvl L, int c, double *__restrict__ out,
+template <int OP, typename R>
+__global__ __launch_bounds__(TPB) void k_pass_tiled(Mod M, LvlT<R> L, int c, R *__restrict__ out,
                                                     const double *fptr, double fscale,
                                                     unsigned long long *clamp, TileGeom G) {
-    __shared__ double sA[3][TPLANE], sB[3][TPLANE];
+    __shared__ R sA[3][TPLANE], sB[3][TPLANE];
     const size_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int bx = (int)(blk % G.ntx);
     const int by = (int)((blk / G.ntx) % G.nty);
     const int bz = (int)(blk / ((size_t)G.ntx * G.nty));
     const int m0 = bx * TX, j0 = by * TY, k0 = bz * G.kz;
-    const double *A = c ? L.u1 : L.u0;
-    const double *B = c ? L.u0 : L.u1;
-    const double *D = c ? L.d1 : L.d0;
-    const double *F = c ? L.f1 : L.f0;
+    const R *A = c ? L.u1 : L.u0;
+    const R *B = c ? L.u0 : L.u1;
+    const R *D = c ? L.d1 : L.d0;
+    const R *F = c ? L.f1 : L.f0;
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
-    const double fs = fptr ? fscale * (*fptr) : 0.0;
-    double ra[TLOADS], rb[TLOADS];
+    const R fs = (R)(fptr ? fscale * (*fptr) : 0.0);
+    R ra[TLOADS], rb[TLOADS];
     auto fetch = [&](int k) {
 #pragma unroll
         for (int q = 0; q < TLOADS; ++q) {
@@ -90,13 +90,13 @@ __global__ __launch_bounds__(TPB) void k_pass_tiled(Mod M, Lvl L, int c, double 
         }
     };
     // own cells' delta and f, one plane ahead
-    double dn[2], fn[2];
+    R dn[2], fn[2];
     auto fetch_cells = [&](int k) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const size_t idx = prow(j0 + ty + 4 * h, k, L.logn, L.lognh) + m0 + tx;
             dn[h] = D[idx];
-            fn[h] = F ? F[idx] : 0.0;
+            fn[h] = F ? F[idx] : (R)0;
         }
     };
     // slot of plane k: (k - k0 + 1) mod 3
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(TPB) void k_pass_tiled(Mod M, Lvl L, int c, double 
     for (int k = k0; k < k0 + G.kz; ++k) {
         const int sm = (k - k0) % 3, s0 = (k - k0 + 1) % 3, sp = (k - k0 + 2) % 3;
         store(sp);
-        const double d0 = dn[0], d1 = dn[1], f0 = fn[0], f1 = fn[1];
+        const R d0 = dn[0], d1 = dn[1], f0 = fn[0], f1 = fn[1];
         __syncthreads();
         if (k + 2 <= k0 + G.kz) fetch(k + 2);
         if (k + 1 < k0 + G.kz) fetch_cells(k + 1);
@@ -118,12 +118,13 @@ __global__ __launch_bounds__(TPB) void k_pass_tiled(Mod M, Lvl L, int c, double 
             const int row = ty + 4 * h;
             const int j = j0 + row, m = m0 + tx;
             const int p = (j + k + c) & 1;
-            const Nb s = lds_nb(sA[sm], sA[s0], sA[sp], sB[s0], sB[sm], sB[sp], row + 1, tx + 1, p);
+            const NbT<R> s = lds_nb<R, R>(sA[sm], sA[s0], sA[sp], sB[s0], sB[sm], sB[sp], row + 1,
+                                          tx + 1, p);
             const size_t idx = prow(j, k, L.logn, L.lognh) + m;
-            const double faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
-            const double K = model_term<OP>(M, L, s, h ? d1 : d0, clamp);
-            const double f = (h ? f1 : f0) + fs;
-            out[idx] = (faces - L.h2 * (K + f)) * (1.0 / 6.0);
+            const R faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
+            const R K = model_term<OP, R>(M, L, s, h ? d1 : d0, clamp);
+            const R f = (h ? f1 : f0) + fs;
+            out[idx] = (faces - (R)L.h2 * (K + f)) * (R)(1.0 / 6.0);
         }
         __syncthreads();
     }
@@ -132,14 +133,13 @@ __global__ __launch_bounds__(TPB) void k_pass_tiled(Mod M, Lvl L, int c, double 
 // Residual + restriction (see k_resid_restrict) for a tile of 64 x 4 coarse
 // cells marching over coarse planes: fine planes 2K-1 .. 2K+2 of both colours
 // are staged (ring of 4), two new fine planes per coarse plane.
-template <int OP, bool REDUCE>
-__global__ __launch_bounds__(TPB) void k_resid_restrict_tiled(Mod M, Lvl L, const double *fptr,
-                                                              double fscale, double *ru0,
-                                                              double *ru1, double *rd0,
-                                                              double *rd1, double *partials,
+template <int OP, bool REDUCE, typename R>
+__global__ __launch_bounds__(TPB) void k_resid_restrict_tiled(Mod M, LvlT<R> L, const double *fptr,
+                                                              double fscale, R *ru0, R *ru1,
+                                                              R *rd0, R *rd1, double *partials,
                                                               unsigned long long *clamp,
                                                               TileGeom G) {
-    __shared__ double s0[4][TPLANE], s1[4][TPLANE];
+    __shared__ R s0[4][TPLANE], s1[4][TPLANE];
     const size_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int bx = (int)(blk % G.ntx);
     const int by = (int)((blk / G.ntx) % G.nty);
@@ -149,8 +149,8 @@ __global__ __launch_bounds__(TPB) void k_resid_restrict_tiled(Mod M, Lvl L, cons
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     const int lnc = L.logn - 1;
     // two planes in flight: (a0, a1) and (b0, b1) hold colours 0 and 1
-    double a0[TLOADS], a1[TLOADS], b0[TLOADS], b1[TLOADS];
-    auto fetch = [&](int k, double *x0, double *x1) {
+    R a0[TLOADS], a1[TLOADS], b0[TLOADS], b1[TLOADS];
+    auto fetch = [&](int k, R *x0, R *x1) {
 #pragma unroll
         for (int q = 0; q < TLOADS; ++q) {
             const int e = tid + q * TPB;
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(TPB) void k_resid_restrict_tiled(Mod M, Lvl L, cons
             }
         }
     };
-    auto store = [&](int slot, const double *x0, const double *x1) {
+    auto store = [&](int slot, const R *x0, const R *x1) {
 #pragma unroll
         for (int q = 0; q < TLOADS; ++q) {
             const int e = tid + q * TPB;
@@ -180,9 +180,9 @@ __global__ __launch_bounds__(TPB) void k_resid_restrict_tiled(Mod M, Lvl L, cons
             const int a = qc & 1, b = (qc >> 1) & 1, cc = qc >> 2;
             const int col = (a + b + cc) & 1;
             const size_t idx = prow(2 * J + b, 2 * K + cc, L.logn, L.lognh) + I;
-            dn[qc] = (col ? L.d1 : L.d0)[idx];
-            const double *F = col ? L.f1 : L.f0;
-            fn[qc] = F ? F[idx] : 0.0;
+            dn[qc] = (double)(col ? L.d1 : L.d0)[idx];
+            const R *F = col ? L.f1 : L.f0;
+            fn[qc] = F ? (double)F[idx] : 0.0;
         }
     };
     // slot of fine plane k: (k - 2K0 + 1) & 3
@@ -219,19 +219,19 @@ __global__ __launch_bounds__(TPB) void k_resid_restrict_tiled(Mod M, Lvl L, cons
             const int col = (a + b + cc) & 1;
             const int sm = (k - 1 - 2 * K0 + 1) & 3, sz = (k - 2 * K0 + 1) & 3,
                       sp = (k + 1 - 2 * K0 + 1) & 3;
-            const double *Am = col ? s1[sm] : s0[sm];
-            const double *A0 = col ? s1[sz] : s0[sz];
-            const double *Ap = col ? s1[sp] : s0[sp];
-            const double *Bm = col ? s0[sm] : s1[sm];
-            const double *B0 = col ? s0[sz] : s1[sz];
-            const double *Bp = col ? s0[sp] : s1[sp];
+            const R *Am = col ? s1[sm] : s0[sm];
+            const R *A0 = col ? s1[sz] : s0[sz];
+            const R *Ap = col ? s1[sp] : s0[sp];
+            const R *Bm = col ? s0[sm] : s1[sm];
+            const R *B0 = col ? s0[sz] : s1[sz];
+            const R *Bp = col ? s0[sp] : s1[sp];
             const int r = 2 * ty + b + 1, q = tx + 1;
-            const Nb s = lds_nb(Am, A0, Ap, B0, Bm, Bp, r, q, a);
-            const double u = A0[r * TXH + q];
+            const Nb s = lds_nb<double, R>(Am, A0, Ap, B0, Bm, Bp, r, q, a);
+            const double u = (double)A0[r * TXH + q];
             const double faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
             const double f = fc[qc] + fs;
             (void)j;
-            const double d = (faces - 6.0 * u) * inv_h2 - model_term<OP>(M, L, s, dc[qc], clamp) - f;
+            const double d = (faces - 6.0 * u) * inv_h2 - model_term<OP, double>(M, L, s, dc[qc], clamp) - f;
             sd += d;
             su += u;
             if (REDUCE) {
@@ -241,8 +241,8 @@ __global__ __launch_bounds__(TPB) void k_resid_restrict_tiled(Mod M, Lvl L, cons
         }
         const size_t cidx = ((size_t)K << (2 * lnc - 1)) + ((size_t)J << (lnc - 1)) + (I >> 1);
         const int ccol = (I + J + K) & 1;
-        (ccol ? ru1 : ru0)[cidx] = 0.125 * su;
-        (ccol ? rd1 : rd0)[cidx] = 0.125 * sd;
+        (ccol ? ru1 : ru0)[cidx] = (R)(0.125 * su);
+        (ccol ? rd1 : rd0)[cidx] = (R)(0.125 * sd);
         __syncthreads();
     }
     if (REDUCE) block_sum2(acc1, acc2, partials, blk);
@@ -250,9 +250,9 @@ __global__ __launch_bounds__(TPB) void k_resid_restrict_tiled(Mod M, Lvl L, cons
 
 // u_fine += P(uc - rc) (see k_prolong) with the coarse difference staged in
 // LDS: 66 coarse columns x 6 coarse rows, ring of 3 coarse planes.
-__global__ __launch_bounds__(TPB) void k_prolong_tiled(double *f0, double *f1, int logn,
-                                                       const double *uc0, const double *uc1,
-                                                       const double *rc0, const double *rc1,
+template <typename R>
+__global__ __launch_bounds__(TPB) void k_prolong_tiled(R *f0, R *f1, int logn, const R *uc0,
+                                                       const R *uc1, const R *rc0, const R *rc1,
                                                        TileGeom G) {
     constexpr int CR = TY / 2 + 2;   // coarse rows staged
     constexpr int CPL = TXH * CR;    // 396 values per coarse plane
@@ -276,7 +276,8 @@ __global__ __launch_bounds__(TPB) void k_prolong_tiled(double *f0, double *f1, i
                 const int J = ((j0 >> 1) - 1 + r) & ncm1;
                 const int Kw = K & ncm1;
                 const size_t idx = ((size_t)Kw << (2 * lnc - 1)) + ((size_t)J << (lnc - 1)) + (I >> 1);
-                re[q] = ((I + J + Kw) & 1) ? (uc1[idx] - rc1[idx]) : (uc0[idx] - rc0[idx]);
+                re[q] = ((I + J + Kw) & 1) ? ((double)uc1[idx] - (double)rc1[idx])
+                                           : ((double)uc0[idx] - (double)rc0[idx]);
             }
         }
     };
@@ -315,7 +316,8 @@ __global__ __launch_bounds__(TPB) void k_prolong_tiled(double *f0, double *f1, i
                 acc += w * sE[slot][(lr + b * dj) * TXH + lc + a * di];
             }
             const size_t idx = prow(j, k, logn, lognh) + m;
-            (c ? f1 : f0)[idx] += acc * (1.0 / 64.0);
+            R *f = c ? f1 : f0;
+            f[idx] = (R)((double)f[idx] + acc * (1.0 / 64.0));
         }
         __syncthreads();
     }
@@ -323,11 +325,11 @@ __global__ __launch_bounds__(TPB) void k_prolong_tiled(double *f0, double *f1, i
 
 // FAS source on a coarse level (see k_coarse_source) on an LDS-staged tile:
 // S = L(R u) - (R d - shift) at both colours, written over R d, and u = R u.
-template <int OP>
-__global__ __launch_bounds__(TPB) void k_coarse_source_tiled(Mod M, Lvl Lc, double *s0,
-                                                             double *s1, double *u0, double *u1,
-                                                             const double *shift, TileGeom G) {
-    __shared__ double sA[3][TPLANE], sB[3][TPLANE];   // colour 0 / colour 1 of R u
+template <int OP, typename R>
+__global__ __launch_bounds__(TPB) void k_coarse_source_tiled(Mod M, LvlT<R> Lc, R *s0, R *s1,
+                                                             R *u0, R *u1, const double *shift,
+                                                             TileGeom G) {
+    __shared__ R sA[3][TPLANE], sB[3][TPLANE];   // colour 0 / colour 1 of R u
     const size_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int bx = (int)(blk % G.ntx);
     const int by = (int)((blk / G.ntx) % G.nty);
@@ -335,7 +337,7 @@ __global__ __launch_bounds__(TPB) void k_coarse_source_tiled(Mod M, Lvl Lc, doub
     const int m0 = bx * TX, j0 = by * TY, k0 = bz * G.kz;
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     const double sh = shift ? *shift : 0.0;
-    double ra[TLOADS], rb[TLOADS];
+    R ra[TLOADS], rb[TLOADS];
     auto fetch = [&](int k) {
 #pragma unroll
         for (int q = 0; q < TLOADS; ++q) {
@@ -372,20 +374,21 @@ __global__ __launch_bounds__(TPB) void k_coarse_source_tiled(Mod M, Lvl Lc, doub
             const int row = ty + 4 * (h & 1), c = h >> 1;
             const int j = j0 + row, m = m0 + tx;
             const int p = (j + k + c) & 1;
-            const double *(Am) = c ? sB[sm] : sA[sm];
-            const double *(A0) = c ? sB[sz] : sA[sz];
-            const double *(Ap) = c ? sB[sp] : sA[sp];
-            const double *(Bm) = c ? sA[sm] : sB[sm];
-            const double *(B0) = c ? sA[sz] : sB[sz];
-            const double *(Bp) = c ? sA[sp] : sB[sp];
-            const Nb s = lds_nb(Am, A0, Ap, B0, Bm, Bp, row + 1, tx + 1, p);
+            const R *Am = c ? sB[sm] : sA[sm];
+            const R *A0 = c ? sB[sz] : sA[sz];
+            const R *Ap = c ? sB[sp] : sA[sp];
+            const R *Bm = c ? sA[sm] : sB[sm];
+            const R *B0 = c ? sA[sz] : sB[sz];
+            const R *Bp = c ? sA[sp] : sB[sp];
+            const Nb s = lds_nb<double, R>(Am, A0, Ap, B0, Bm, Bp, row + 1, tx + 1, p);
             const size_t idx = prow(j, k, Lc.logn, Lc.lognh) + m;
-            const double ru = A0[(row + 1) * TXH + tx + 1];
+            const R ru = A0[(row + 1) * TXH + tx + 1];
             const double faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
-            const double delta = (c ? Lc.d1 : Lc.d0)[idx];
-            double *S = c ? s1 : s0;
-            const double rd = S[idx] - sh;
-            S[idx] = (faces - 6.0 * ru) / Lc.h2 - model_term<OP>(M, Lc, s, delta, nullptr) - rd;
+            const double delta = (double)(c ? Lc.d1 : Lc.d0)[idx];
+            R *S = c ? s1 : s0;
+            const double rd = (double)S[idx] - sh;
+            S[idx] = (R)((faces - 6.0 * (double)ru) / Lc.h2
+                         - model_term<OP, double>(M, Lc, s, delta, nullptr) - rd);
             (c ? u1 : u0)[idx] = ru;
         }
         __syncthreads();

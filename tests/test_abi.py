@@ -27,7 +27,10 @@ def test_every_declared_symbol_is_exported(L):
 def test_workspace_sizes(L):
     assert L.mg_workspace_bytes(7, 0, 0, 0) == 0
     assert L.mg_workspace_bytes(4096, 0, 0, 0) == 0
-    assert L.mg_workspace_bytes(32, 1, 0, 0) == 0          # precision not available
+    assert L.mg_workspace_bytes(32, 2, 0, 0) == 0          # unknown precision
+    assert L.mg_workspace_bytes(32, 1, 0, 1) == 0          # the adjoint is FP64 only
+    # mixed keeps an FP32 hierarchy beside the FP64 one
+    assert L.mg_workspace_bytes(64, 1, 0, 0) > L.mg_workspace_bytes(64, 0, 0, 0)
     a = L.mg_workspace_bytes(64, 0, 0, 0)
     b = L.mg_workspace_bytes(64, 0, 0, 1)
     # finest level: 5 half-arrays of FP64 = 20 bytes per cell, coarse levels add < 1/2

@@ -282,3 +282,49 @@ def test_pm_step_parity():
     dp = np.abs(c(gpos) - p_o)
     dp = np.minimum(dp, nm - dp)
     assert dp.max() <= 1e-4
+
+
+# --------------------------------------------------------- mixed precision
+
+@pytest.mark.parametrize("n,h0rc", [(32, 1.0), (128, 1.0), (128, 0.5)])
+def test_mixed_precision_converges_to_fp64_accuracy(n, h0rc):
+    # FP32-storage cycles then FP64 cycles; the returned field meets the FP64
+    # tolerance and matches the FP64 oracle within 1e-6 relative
+    delta = inputs.lognormal_delta(n, 1) if n == 32 else \
+        oracle.cic_density(inputs.za_particles(n // 2, n, 6, amplitude=30.0), n)[1]
+    r = oracle.solve(oracle.dgp_model(1.0, OM, h0rc), delta, tol=1e-10, max_cycles=80)
+    phi, st = mg.solve_dgp(g(delta), h0rc=h0rc, tol=1e-8, precision=mg.MG_MIXED)
+    assert st["status"] == 0 and st["eps"] <= 1e-8
+    assert st["cycles_fp32"] >= 3
+    assert rel(c(phi), r.phi) <= 1e-6
+    for ax in range(3):
+        f_g = np.roll(c(phi), -1, ax) - np.roll(c(phi), 1, ax)
+        f_o = np.roll(r.phi, -1, ax) - np.roll(r.phi, 1, ax)
+        assert rel(f_g, f_o) <= 1e-5
+
+
+@pytest.mark.parametrize("name,n", [("dgp", 64), ("kmo3", 32), ("poisson", 32), ("dgp", 128)])
+def test_fp32_cycles_track_oracle(name, n):
+    # three FP32-storage cycles (tol = 0 and the cycle cap spent in the FP32
+    # phase) agree with three FP64 oracle cycles to FP32 rounding
+    gp, om = models(n)[name]
+    delta = inputs.lognormal_delta(n, 3)
+    r = oracle.solve(om, delta, tol=0.0, max_cycles=3)
+    fn = {"dgp": mg.lib().mg_solve_dgp, "kmo3": mg.lib().mg_solve_kmouflage,
+          "poisson": mg.lib().mg_solve_poisson}[name]
+    model = {"dgp": 0, "kmo3": 1, "poisson": 2}[name]
+    phi, st = mg._solve(fn, gp, model, g(delta), None, None, tol=0.0, max_cycles=3,
+                        precision=mg.MG_MIXED)
+    assert st["cycles_fp32"] == 3 and st["cycles"] == 3
+    assert rel(c(phi), r.phi) <= 2e-5
+
+
+def test_mixed_kmouflage_sphere():
+    n = 32
+    d = inputs.tophat_delta(n, 5000.0, 0.1 * n)
+    d -= d.mean()
+    r = oracle.solve(oracle.kmo_model(n, float(n), 2, 10.0, 0.2), d, tol=1e-10, max_cycles=100)
+    phi, st = mg.solve_kmouflage(g(d), box_mpch=float(n), n_k=2, k0=10.0, beta=0.2, tol=1e-9,
+                                 max_cycles=100, precision=mg.MG_MIXED)
+    assert st["status"] == 0 and st["eps"] <= 1e-9
+    assert rel(c(phi), r.phi) <= 1e-6
