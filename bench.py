@@ -68,12 +68,68 @@ def cpu_baseline(pos_np):
                       "%.1f s" % dt}
 
 
+def vcycle_bytes(n: int) -> int:
+    """Algorithmic HBM bytes of one FP64 V(1,1) cycle: per level 4 colour
+    passes (16 B/cell), residual + restriction (18) and prolongation (18),
+    plus the coarse FAS source (40 B per coarse cell)."""
+    total, m, lev = 0, n, 0
+    while m > 4:
+        total += 100 * m ** 3 + (40 * m ** 3 if lev else 0)
+        m //= 2
+        lev += 1
+    return total
+
+
+def vcycle_time(mg, L, C, delta):
+    """Time per FP64 V-cycle on delta's mesh: difference of 6- and 2-cycle
+    solves (tol = 0), which cancels the set-up and the residual passes."""
+    import torch
+    n = delta.shape[0]
+    ws = mg.workspace(n, mg.MODEL_DGP, False, delta.device)
+    par = mg.dgp_params(A, OMEGA_M, H0RC)
+    phi = torch.zeros_like(delta)
+    times = {}
+    for cyc in (2, 6, 2, 6):
+        opts = mg.make_opts(n, tol=0.0, max_cycles=cyc)
+        st = mg.Stats()
+        phi.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mg._raise(L.mg_solve_dgp(C.byref(opts), C.byref(par), mg._ptr(delta), mg._ptr(phi),
+                                 mg._ptr(ws), ws.numel(), mg._stream(), C.byref(st)))
+        torch.cuda.synchronize()
+        times[cyc] = time.perf_counter() - t0
+    ms = 1e3 * (times[6] - times[2]) / 4
+    bytes_ = vcycle_bytes(n)
+    del ws, phi
+    torch.cuda.empty_cache()
+    return {"n_mesh": n, "ms_per_vcycle": ms, "algorithmic_bytes_per_vcycle": bytes_,
+            "achieved_GBs": bytes_ / (ms * 1e-3) / 1e9,
+            "frac_of_hbm_peak": bytes_ / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
+def vcycle_1024(mg, L, C, dev):
+    """FP64 V-cycle on a 1024^3 mesh: CIC of 512^3 Zel'dovich particles
+    (L = 1 Gpc/h)."""
+    import torch
+
+    import inputs
+    pos = torch.from_numpy(inputs.za_particles(512, 1024, 5)).to(dev)
+    delta = mg.cic_delta(pos, 1024)
+    del pos
+    r = vcycle_time(mg, L, C, delta)
+    del delta
+    torch.cuda.empty_cache()
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-big", action="store_true", help="skip the 1024^3 V-cycle timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solver runs on a single MI355X "
@@ -184,6 +240,11 @@ def main():
                     "eps_fp32": float(mstats[-1].eps_fp32), "eps": float(mstats[-1].eps),
                     "speedup_time_to_tol_vs_fp64": solve_ms / mix_solve_ms,
                     "max_rel_diff_phi_vs_fp64": err}
+    del ws_mix, ws
+    torch.cuda.empty_cache()
+    out["vcycle_512"] = vcycle_time(mg, L, C, delta)
+    if not args.no_big:
+        out["vcycle_1024"] = vcycle_1024(mg, L, C, dev)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(pos_np)
     print(json.dumps(out), flush=True)

@@ -1,0 +1,174 @@
+"""GPU checks at the full sizes of the benchmark configurations.
+
+* 256^3 nDGP (H0 r_c = 0.5, 1, 5) on the CIC density of 256^3 Zel'dovich
+  particles, FP64 and mixed precision: element-wise against the FP64 oracle
+  for H0 r_c = 1, and through the oracle's residual of the GPU field for all.
+* 256^3 Kmouflage (n = 3, K0 = 1, beta = 0.1) on the same density.
+* 256^3 nDGP adjoint: gradient of sum(phi w) against central finite
+  differences on 64 random cells (eps = 1e-4).
+* PM step on a 1024^3 mesh with 512^3 particles: CIC density element-wise,
+  the potentials through their discrete equations on sampled cells, and the
+  kick-drift of sampled particles recomputed by the oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+import inputs
+import oracle
+import paper_2110_00566_amd as mg
+
+pytestmark = pytest.mark.gpu
+OM = 0.3089
+
+
+def g(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def c(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+@pytest.fixture(scope="module")
+def delta256():
+    pos = inputs.za_particles(256, 256, 2)
+    d_gpu = c(mg.cic_delta(g(pos), 256))
+    _, d_or = oracle.cic_density(pos, 256)
+    return d_gpu, d_or
+
+
+def test_config2_cic_matches_oracle(delta256):
+    d_gpu, d_or = delta256
+    assert np.abs(d_gpu - d_or).max() <= 1e-7
+    assert abs(d_gpu.mean()) <= 1e-9
+
+
+@pytest.mark.parametrize("precision", [mg.MG_FP64, mg.MG_MIXED])
+def test_config2_h0rc1_elementwise(delta256, precision):
+    d, _ = delta256
+    ref = oracle.solve(oracle.dgp_model(1.0, OM, 1.0), d, tol=1e-10, max_cycles=60)
+    phi, st = mg.solve_dgp(g(d), h0rc=1.0, tol=1e-8, precision=precision)
+    assert st["status"] == 0 and st["eps"] <= 1e-8
+    assert rel(c(phi), ref.phi) <= 1e-6
+    for ax in range(3):
+        f_g = np.roll(c(phi), -1, ax) - np.roll(c(phi), 1, ax)
+        f_o = np.roll(ref.phi, -1, ax) - np.roll(ref.phi, 1, ax)
+        assert rel(f_g, f_o) <= 1e-6
+
+
+@pytest.mark.parametrize("h0rc", [0.5, 1.0, 5.0])
+@pytest.mark.parametrize("precision", [mg.MG_FP64, mg.MG_MIXED])
+def test_config2_residual_of_gpu_field(delta256, h0rc, precision):
+    # the oracle's operator applied to the GPU field: RMS of the
+    # mean-projected residual <= tol, and mean L(phi) = -lambda
+    d, _ = delta256
+    phi, st = mg.solve_dgp(g(d), h0rc=h0rc, tol=1e-8, precision=precision)
+    assert st["status"] == 0
+    L = oracle.residual(oracle.dgp_model(1.0, OM, h0rc), c(phi), d)
+    eps = np.sqrt(np.mean((L - L.mean()) ** 2))
+    assert eps <= 1.05e-8
+    assert eps == pytest.approx(st["eps"], rel=1e-3)
+    assert L.mean() == pytest.approx(-st["lam"], abs=1e-12)
+
+
+def test_config3_kmouflage(delta256):
+    d, _ = delta256
+    om = oracle.kmo_model(256, 512.0, 3, 1.0, 0.1)
+    ref = oracle.solve(om, d, tol=1e-12, max_cycles=60)
+    for precision in (mg.MG_FP64, mg.MG_MIXED):
+        phi, st = mg.solve_kmouflage(g(d), box_mpch=512.0, n_k=3, k0=1.0, beta=0.1, tol=1e-10,
+                                     precision=precision)
+        assert st["status"] == 0 and st["eps"] <= 1e-10
+        assert rel(c(phi), ref.phi) <= 1e-6
+        L = oracle.residual(om, c(phi), d)
+        assert np.sqrt(np.mean((L - L.mean()) ** 2)) <= 1.05e-10
+
+
+def test_config4_adjoint_finite_differences(delta256):
+    d, _ = delta256
+    n = 256
+    w = g(inputs.gaussian_weights(n, 3))
+    dg = g(d)
+    phi, st = mg.solve_dgp(dg, tol=1e-13, max_cycles=100)
+    assert st["status"] == 0
+    grad, mu, ast = mg.solve_adjoint(mg.MODEL_DGP, mg.dgp_params(), dg, phi, w, tol=1e-11,
+                                     max_cycles=100)
+    assert ast["status"] == 0
+    cells = inputs.random_cells(n, 64, 4)
+    eps = 1e-4
+    fd = []
+    for cidx in cells:
+        vals = []
+        for sgn in (1, -1):
+            d2 = dg.clone().view(-1)
+            d2[int(cidx)] += sgn * eps
+            p2, s2 = mg.solve_dgp(d2.view(dg.shape), phi, tol=1e-13, max_cycles=100)
+            assert s2["status"] == 0
+            vals.append(float((p2 * w).sum()))
+        fd.append((vals[0] - vals[1]) / (2 * eps))
+    fd = np.array(fd)
+    gs = c(grad).reshape(-1)[cells]
+    assert np.abs(gs - fd).max() <= 1e-4 * np.abs(fd).max()
+
+
+def test_config5_pm_step_1024():
+    nm, np_ = 1024, 512
+    pos = inputs.za_particles(np_, nm, 5)
+    mom = np.zeros_like(pos)
+    gpos, gmom = g(pos), g(mom)
+    phi = torch.zeros((nm,) * 3, dtype=torch.float64, device="cuda")
+    phin = torch.zeros_like(phi)
+    a, da = 1.0, 0.0063
+    delta, st = mg.pm_step(gpos, gmom, phi, phin, nm, a, da, tol=1e-8)
+    assert st["status"] == 0 and st["eps"] <= 1e-8
+    d = c(delta)
+    # CIC density element-wise against the oracle's sequential FP64 deposit
+    _, d_or = oracle.cic_density(pos, nm)
+    assert np.abs(d - d_or).max() <= 2e-7
+    del d_or
+    # discrete equations on sampled cells
+    rng = np.random.default_rng(9)
+    idx = rng.integers(0, nm, size=(2000, 3))
+    ph, pn = c(phi), c(phin)
+    dm = d.mean()
+
+    def lap(f, i, j, k):
+        w = lambda q: q % nm
+        return (f[k, j, w(i + 1)] + f[k, j, w(i - 1)] + f[k, w(j + 1), i] + f[k, w(j - 1), i]
+                + f[w(k + 1), j, i] + f[w(k - 1), j, i] - 6 * f[k, j, i])
+
+    src = 1.5 * OM / a
+    res_n = np.array([lap(pn, i, j, k) - src * (d[k, j, i] - dm) for i, j, k in idx])
+    scale = src * np.abs(d).max()
+    assert np.abs(res_n).max() <= 1e-6 * scale
+    m = oracle.dgp_model(a, OM, 1.0)
+    sub = 40
+    i0, j0, k0 = 300, 500, 700
+    win = np.ix_(np.arange(k0 - 2, k0 + sub + 2) % nm, np.arange(j0 - 2, j0 + sub + 2) % nm,
+                 np.arange(i0 - 2, i0 + sub + 2) % nm)
+    # a periodic window is not periodic, so evaluate the operator on the
+    # window interior only
+    L = oracle.residual(m, ph[win], d[win])[2:-2, 2:-2, 2:-2]
+    assert np.abs(L + st["lam"]).max() <= 1e-6
+    # kick-drift of 20000 sampled particles with the GPU potentials
+    sel = rng.choice(np_ ** 3, 20000, replace=False)
+    psi = pn + 0.5 * ph
+    del ph, pn
+    p_s = pos[sel].copy()
+    m_s = mom[sel].copy()
+    ah = a + 0.5 * da
+    kick = da / (a * oracle.expansion_rate(a))
+    drift = da / (ah ** 3 * oracle.expansion_rate(ah))
+    oracle.lib().or_kick_drift(nm, len(sel), np.ascontiguousarray(psi), p_s.reshape(-1),
+                               m_s.reshape(-1), kick, drift)
+    gm = c(gmom)[sel]
+    gp = c(gpos)[sel]
+    assert np.abs(gm - m_s).max() <= 1e-5 * np.abs(m_s).max()
+    dp = np.abs(gp - p_s)
+    dp = np.minimum(dp, nm - dp)
+    assert dp.max() <= 1e-4
