@@ -72,6 +72,7 @@ struct HLevel {
     size_t half = 0;
     R *u[2] = {nullptr, nullptr};
     R *spare = nullptr;
+    R *spare2 = nullptr;   // second output of the fused prolongation + pass (tiled levels)
     R *d[2] = {nullptr, nullptr};
     R *f[2] = {nullptr, nullptr};
     R *ru[2] = {nullptr, nullptr};
@@ -122,6 +123,7 @@ void layout_hier(Hier<R> &Hh, Carve &cv, int n, bool adjoint) {
         H.u[0] = cv.take<R>(H.half);
         H.u[1] = cv.take<R>(H.half);
         H.spare = cv.take<R>(H.half);
+        if (!adjoint && m >= 128) H.spare2 = cv.take<R>(H.half);
         H.d[0] = cv.take<R>(H.half);
         H.d[1] = cv.take<R>(H.half);
         if (L > 0 || adjoint) {
@@ -402,6 +404,20 @@ struct Solver {
         launch_prolong<R>(H.u[0], H.u[1], H.logn, Hc.u[0], Hc.u[1], Hc.ru[0], Hc.ru[1], C.st);
     }
 
+    // prolongation fused with the colour-0 pass of the first post-sweep
+    bool fused_prolong(int l) const {
+        return OP != OP_ADJ && C.nu2 >= 1 && Hh.lv[l].spare2 && tiled_level(Hh.lv[l].n);
+    }
+    void prolong_pass0(int l) {
+        HLevel<R> &H = Hh.lv[l], &Hc = Hh.lv[l + 1];
+        const TileGeom G = tile_geom(H.n, H.n);
+        k_prolong_pass_tiled<fwd_op(OP), R><<<tile_blocks(G, H.n), TPB, 0, C.st>>>(
+            C.M, view(H, l > 0), H.spare, H.spare2, Hc.u[0], Hc.u[1], Hc.ru[0], Hc.ru[1],
+            l == 0 ? C.scal + S_MU : nullptr, 1.0, C.clamp, G);
+        std::swap(H.u[0], H.spare);
+        std::swap(H.u[1], H.spare2);
+    }
+
     template <int NL>
     void launch_tail(const TailArgs<R> &A, size_t lds) {
         static bool attr_set = false;   // per instantiation, process-wide
@@ -454,8 +470,14 @@ struct Solver {
         resid_restrict(l);
         coarse_source(l + 1);
         vcycle(l + 1);
-        prolong(l);
-        for (int s = 0; s < C.nu2; ++s) sweep(l);
+        if (fused_prolong(l)) {
+            prolong_pass0(l);
+            pass(l, 1);
+            for (int s = 1; s < C.nu2; ++s) sweep(l);
+        } else {
+            prolong(l);
+            for (int s = 0; s < C.nu2; ++s) sweep(l);
+        }
     }
 
     mg_status read_scal(double *hs) {

@@ -323,6 +323,197 @@ __global__ __launch_bounds__(TPB) void k_prolong_tiled(R *f0, R *f1, int logn, c
     }
 }
 
+// Prolongation of the coarse correction fused with the first post-smoothing
+// pass (colour 0).  Every staged fine value is corrected on the fly,
+// u + P(uc - rc), colour-0 cells get the closed-form update from the corrected
+// neighbourhood (out0) and colour-1 cells are written corrected (out1).  Both
+// outputs are separate arrays: neighbouring tiles still read the old values.
+//
+// The 27/9/3/1 weights factor into a z part (3/4 own coarse plane, 1/4 the
+// plane on the fine cell's side) times an x-y bilinear part (9, 3, 3, 1 over
+// 16).  A thread keeps the x-y part of the two coarse planes the next staged
+// fine planes need, at its staged positions and for both x parities, in
+// registers; one coarse plane of 68 x 6 values around the tile passes through
+// LDS every second fine plane.  kz (fine planes per block) is even.
+template <int OP, typename R>
+__global__ __launch_bounds__(TPB) void k_prolong_pass_tiled(Mod M, LvlT<R> L, R *__restrict__ out0,
+                                                            R *__restrict__ out1, const R *uc0,
+                                                            const R *uc1, const R *rc0,
+                                                            const R *rc1, const double *fptr,
+                                                            double fscale,
+                                                            unsigned long long *clamp, TileGeom G) {
+    constexpr int CW = TX + 4;           // coarse columns m0-2 .. m0+65
+    constexpr int CH = TY / 2 + 2;       // coarse rows j0/2-1 .. j0/2+4
+    constexpr int CPL = CW * CH;
+    constexpr int CLOADS = (CPL + TPB - 1) / TPB;
+    __shared__ R sA[3][TPLANE], sB[3][TPLANE];
+    __shared__ double sC[CPL];
+    const size_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int bx = (int)(blk % G.ntx);
+    const int by = (int)((blk / G.ntx) % G.nty);
+    const int bz = (int)(blk / ((size_t)G.ntx * G.nty));
+    const int m0 = bx * TX, j0 = by * TY, k0 = bz * G.kz, K0 = k0 >> 1;
+    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+    const int lnc = L.logn - 1, ncm1 = (1 << lnc) - 1;
+    const R fs = (R)(fptr ? fscale * (*fptr) : 0.0);
+
+    // coarse difference uc - rc of one coarse plane, via registers into sC
+    double cu[CLOADS], cr[CLOADS];
+    auto cfetch = [&](int Z) {
+        const int Zw = Z & ncm1;
+#pragma unroll
+        for (int q = 0; q < CLOADS; ++q) {
+            const int e = tid + q * TPB;
+            if (e < CPL) {
+                const int r = e / CW, cI = e - r * CW;
+                const int X = (m0 - 2 + cI) & ncm1;
+                const int Y = ((j0 >> 1) - 1 + r) & ncm1;
+                const size_t idx =
+                    ((size_t)Zw << (2 * lnc - 1)) + ((size_t)Y << (lnc - 1)) + (X >> 1);
+                const bool odd = (X + Y + Zw) & 1;
+                cu[q] = (double)(odd ? uc1 : uc0)[idx];
+                cr[q] = (double)(odd ? rc1 : rc0)[idx];
+            }
+        }
+    };
+    auto cstore = [&]() {
+#pragma unroll
+        for (int q = 0; q < CLOADS; ++q) {
+            const int e = tid + q * TPB;
+            if (e < CPL) sC[e] = cu[q] - cr[q];
+        }
+    };
+    // x-y bilinear part of the coarse plane in sC at the thread's staged
+    // positions, for fine x = 2m (index 0, coarse neighbour m-1) and
+    // x = 2m+1 (index 1, coarse neighbour m+1)
+    double xlo[TLOADS][2], xhi[TLOADS][2], xnx[TLOADS][2];
+    auto interp = [&](double (&x)[TLOADS][2]) {
+#pragma unroll
+        for (int q = 0; q < TLOADS; ++q) {
+            const int e = tid + q * TPB;
+            if (e < TPLANE) {
+                const int r = e / TXH, cI = e - r * TXH;
+                const int lr = (r + 1) >> 1, lc = cI + 1;
+                const int ly = (r & 1) ? lr - 1 : lr + 1;   // fine row odd: coarse row above
+                const double c0 = sC[lr * CW + lc], cm = sC[lr * CW + lc - 1],
+                             cp = sC[lr * CW + lc + 1];
+                const double d0 = sC[ly * CW + lc], dm = sC[ly * CW + lc - 1],
+                             dp = sC[ly * CW + lc + 1];
+                x[q][0] = (9.0 / 16.0) * c0 + (3.0 / 16.0) * cm + (3.0 / 16.0) * d0 +
+                          (1.0 / 16.0) * dm;
+                x[q][1] = (9.0 / 16.0) * c0 + (3.0 / 16.0) * cp + (3.0 / 16.0) * d0 +
+                          (1.0 / 16.0) * dp;
+            }
+        }
+    };
+
+    // raw fine values of the next plane, and own cells' delta and f
+    R ra[TLOADS], rb[TLOADS];
+    auto fetch = [&](int k) {
+#pragma unroll
+        for (int q = 0; q < TLOADS; ++q) {
+            const int e = tid + q * TPB;
+            if (e < TPLANE) {
+                const size_t g = tile_gidx(e, j0, m0, k, L.logn, L.lognh);
+                ra[q] = L.u0[g];
+                rb[q] = L.u1[g];
+            }
+        }
+    };
+    // corrected plane k into ring slot; the coarse pair (lo, hi) holds the
+    // plane's own coarse plane (hi for even k, lo for odd k) and its neighbour
+    auto stage = [&](int slot, int k, bool kodd) {
+        const double wl = kodd ? 0.75 : 0.25, wh = kodd ? 0.25 : 0.75;
+#pragma unroll
+        for (int q = 0; q < TLOADS; ++q) {
+            const int e = tid + q * TPB;
+            if (e < TPLANE) {
+                const int r = e / TXH;
+                const bool p0 = (j0 - 1 + r + k) & 1;   // x parity of the colour-0 value
+                const double l0 = p0 ? xlo[q][1] : xlo[q][0], l1 = p0 ? xlo[q][0] : xlo[q][1];
+                const double h0 = p0 ? xhi[q][1] : xhi[q][0], h1 = p0 ? xhi[q][0] : xhi[q][1];
+                sA[slot][e] = (R)((double)ra[q] + (wl * l0 + wh * h0));
+                sB[slot][e] = (R)((double)rb[q] + (wl * l1 + wh * h1));
+            }
+        }
+    };
+    R dn[2], fn[2];
+    auto fetch_cells = [&](int k) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const size_t idx = prow(j0 + ty + 4 * h, k, L.logn, L.lognh) + m0 + tx;
+            dn[h] = L.d0[idx];
+            fn[h] = L.f0 ? L.f0[idx] : (R)0;
+        }
+    };
+
+    // coarse planes K0-1, K0 (pair for fine planes k0-1, k0) and K0+1
+    cfetch(K0 - 1);
+    cstore();
+    __syncthreads();
+    interp(xlo);
+    __syncthreads();
+    cfetch(K0);
+    cstore();
+    __syncthreads();
+    interp(xhi);
+    __syncthreads();
+    cfetch(K0 + 1);
+    cstore();
+    __syncthreads();
+    interp(xnx);
+    // slot of fine plane k: (k - k0 + 1) mod 3
+    fetch(k0 - 1);
+    stage(0, k0 - 1, true);
+    fetch(k0);
+    stage(1, k0, false);
+    fetch(k0 + 1);
+    fetch_cells(k0);
+
+    auto step = [&](int k, bool odd) {
+        if (!odd) {
+#pragma unroll
+            for (int q = 0; q < TLOADS; ++q) {
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    xlo[q][b] = xhi[q][b];
+                    xhi[q][b] = xnx[q][b];
+                }
+            }
+        }
+        const int sm = (k - k0) % 3, s0 = (k - k0 + 1) % 3, sp = (k - k0 + 2) % 3;
+        stage(sp, k + 1, !odd);
+        // a new coarse plane (k >> 1) + 2 is needed for fine planes beyond k + 2
+        const bool cnew = odd && (k + 3 <= k0 + G.kz);
+        if (cnew) cstore();
+        const R d0 = dn[0], d1 = dn[1], f0 = fn[0], f1 = fn[1];
+        __syncthreads();
+        if (k + 2 <= k0 + G.kz) fetch(k + 2);
+        if (k + 1 < k0 + G.kz) fetch_cells(k + 1);
+        if (!odd && k + 4 <= k0 + G.kz) cfetch((k >> 1) + 2);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int row = ty + 4 * h;
+            const int j = j0 + row, m = m0 + tx;
+            const int p = (j + k) & 1;
+            const NbT<R> s = lds_nb<R, R>(sA[sm], sA[s0], sA[sp], sB[s0], sB[sm], sB[sp], row + 1,
+                                          tx + 1, p);
+            const size_t idx = prow(j, k, L.logn, L.lognh) + m;
+            const R faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
+            const R K = model_term<OP, R>(M, L, s, h ? d1 : d0, clamp);
+            const R f = (h ? f1 : f0) + fs;
+            out0[idx] = (faces - (R)L.h2 * (K + f)) * (R)(1.0 / 6.0);
+            out1[idx] = sB[s0][(row + 1) * TXH + tx + 1];
+        }
+        if (cnew) interp(xnx);
+        __syncthreads();
+    };
+    for (int k = k0; k < k0 + G.kz; k += 2) {
+        step(k, false);
+        step(k + 1, true);
+    }
+}
+
 // FAS source on a coarse level (see k_coarse_source) on an LDS-staged tile:
 // S = L(R u) - (R d - shift) at both colours, written over R d, and u = R u.
 template <int OP, typename R>

@@ -104,16 +104,22 @@ def test_transpose_jacobian_parity(n, name):
 
 # ------------------------------------------------------------- whole solves
 
-@pytest.mark.parametrize("name,n,cycles", [("dgp", 128, 2), ("kmo3", 128, 2), ("dgp_h05", 256, 1)])
-def test_tiled_levels_fixed_cycles_parity(name, n, cycles):
+@pytest.mark.parametrize("name,n,cycles,nu1,nu2", [("dgp", 128, 2, 1, 1), ("kmo3", 128, 2, 1, 1),
+                                                   ("poisson", 128, 2, 1, 1),
+                                                   ("dgp_h05", 256, 1, 1, 1), ("dgp", 128, 1, 2, 2),
+                                                   ("dgp", 128, 2, 1, 0)])
+def test_tiled_levels_fixed_cycles_parity(name, n, cycles, nu1, nu2):
     # levels >= 128^3 run the LDS-tiled kernels (pass, residual + restriction
-    # with the residual reduction, prolongation)
+    # with the residual reduction, and the prolongation fused with the first
+    # colour pass of the post-smoothing; nu2 = 0 takes the plain prolongation)
     gp, om = models(n)[name]
     delta = inputs.lognormal_delta(n, 3)
-    r = oracle.solve(om, delta, tol=0.0, max_cycles=cycles)
-    fn = mg.lib().mg_solve_kmouflage if name.startswith("kmo") else mg.lib().mg_solve_dgp
-    phi, st = mg._solve(fn, gp, 1 if name.startswith("kmo") else 0, g(delta), None, None,
-                        tol=0.0, max_cycles=cycles)
+    r = oracle.solve(om, delta, tol=0.0, max_cycles=cycles, nu1=nu1, nu2=nu2)
+    fn = {"dgp": mg.lib().mg_solve_dgp, "dgp_h05": mg.lib().mg_solve_dgp,
+          "kmo3": mg.lib().mg_solve_kmouflage, "poisson": mg.lib().mg_solve_poisson}[name]
+    model = {"dgp": 0, "dgp_h05": 0, "kmo3": 1, "poisson": 2}[name]
+    phi, st = mg._solve(fn, gp, model, g(delta), None, None, tol=0.0, max_cycles=cycles,
+                        nu_pre=nu1, nu_post=nu2)
     assert rel(c(phi), r.phi) <= 1e-11
     assert st["eps0"] == pytest.approx(r.eps0, rel=1e-10)
     assert np.allclose(st["eps_hist"], r.hist[:cycles], rtol=1e-8, atol=1e-300)
