@@ -329,7 +329,7 @@ struct Solver {
     explicit Solver(Ctx &c) : C(c), Hh(hier<R>(c)) {}
 
     void mean_of(R *a0, R *a1, size_t half) {
-        const unsigned nb = nblocks(2 * half);
+        const unsigned nb = (unsigned)std::min<size_t>(nblocks(half), 2048);
         k_sum<R><<<nb, TPB, 0, C.st>>>(a0, a1, half, C.partials);
         k_finalize<<<1, 1024, 0, C.st>>>(C.partials, nb, (double)(2 * half), C.scal, 1, 0.0);
     }

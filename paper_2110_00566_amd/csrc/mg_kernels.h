@@ -316,12 +316,22 @@ __global__ __launch_bounds__(TPB) void k_convert(const Rin *a, Rout *b, size_t n
 template <typename R>
 __global__ __launch_bounds__(TPB) void k_sum(const R *a0, const R *a1, size_t nhalf,
                                              double *partials) {
-    const size_t blk = blockIdx.x;
-    const size_t t = blk * TPB + threadIdx.x;
-    double v = 0.0;
-    if (t < nhalf) v = (double)a0[t];
-    else if (a1 && t < 2 * nhalf) v = (double)a1[t - nhalf];
-    block_sum2(v, v * v, partials, blk);
+    // grid-stride: a fixed grid for a given size keeps the order deterministic
+    const size_t stride = (size_t)gridDim.x * TPB;
+    double v = 0.0, v2 = 0.0;
+    for (size_t t = (size_t)blockIdx.x * TPB + threadIdx.x; t < nhalf; t += stride) {
+        const double x = (double)a0[t];
+        v += x;
+        v2 += x * x;
+    }
+    if (a1) {
+        for (size_t t = (size_t)blockIdx.x * TPB + threadIdx.x; t < nhalf; t += stride) {
+            const double x = (double)a1[t];
+            v += x;
+            v2 += x * x;
+        }
+    }
+    block_sum2(v, v2, partials, blockIdx.x);
 }
 
 // Finalise a reduction.  mode 0: residual of the finest level with lagged mu

@@ -124,7 +124,8 @@ __global__ __launch_bounds__(TPB) void k_pass_tiled(Mod M, LvlT<R> L, int c, R *
             const R faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
             const R K = model_term<OP, R>(M, L, s, h ? d1 : d0, clamp);
             const R f = (h ? f1 : f0) + fs;
-            out[idx] = (faces - (R)L.h2 * (K + f)) * (R)(1.0 / 6.0);
+            // streamed: the next reader is a later launch
+            __builtin_nontemporal_store((faces - (R)L.h2 * (K + f)) * (R)(1.0 / 6.0), out + idx);
         }
         __syncthreads();
     }
@@ -502,8 +503,8 @@ __global__ __launch_bounds__(TPB) void k_prolong_pass_tiled(Mod M, LvlT<R> L, R 
             const R faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
             const R K = model_term<OP, R>(M, L, s, h ? d1 : d0, clamp);
             const R f = (h ? f1 : f0) + fs;
-            out0[idx] = (faces - (R)L.h2 * (K + f)) * (R)(1.0 / 6.0);
-            out1[idx] = sB[s0][(row + 1) * TXH + tx + 1];
+            __builtin_nontemporal_store((faces - (R)L.h2 * (K + f)) * (R)(1.0 / 6.0), out0 + idx);
+            __builtin_nontemporal_store(sB[s0][(row + 1) * TXH + tx + 1], out1 + idx);
         }
         if (cnew) interp(xnx);
         __syncthreads();
