@@ -232,8 +232,12 @@ unsigned launch_resid_restrict(const Mod &M, const LvlT<R> &L, const Coefs &Cf, 
     if (OP != OP_ADJ && tiled_level(L.n)) {
         const TileGeom G = tile_geom(L.n, L.n / 2);
         const unsigned nb = tile_blocks(G, L.n / 2);
-        k_resid_restrict_tiled<fwd_op(OP), REDUCE, R><<<nb, TPB, 0, st>>>(
-            M, L, fptr, fs, ru0, ru1, rd0, rd1, partials, clamp, G);
+        if (L.f0)
+            k_resid_restrict_tiled<fwd_op(OP), REDUCE, true, R><<<nb, TPB, 0, st>>>(
+                M, L, fptr, fs, ru0, ru1, rd0, rd1, partials, clamp, G);
+        else
+            k_resid_restrict_tiled<fwd_op(OP), REDUCE, false, R><<<nb, TPB, 0, st>>>(
+                M, L, fptr, fs, ru0, ru1, rd0, rd1, partials, clamp, G);
         return nb;
     }
     const size_t ncoarse = (size_t)L.n * L.n * L.n / 8;

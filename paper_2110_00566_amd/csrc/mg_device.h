@@ -94,9 +94,11 @@ __device__ __forceinline__ NbT<T> load_nb(const R *__restrict__ A, const R *__re
 // A_x = phi(i+1)+phi(i-1) etc. and the cross differences N_xy,
 //   hat(H):hat(H) = [(A_x-A_y)^2 + (A_x-A_z)^2 + (A_y-A_z)^2]/(3h^4)
 //                   + (N_xy^2 + N_xz^2 + N_yz^2)/(8h^4),
-// and the root of eq:DGP, (3/4)[-alpha + sign(alpha) sqrt(alpha^2+8 Sigma/3)],
-// is evaluated as 2 Sigma / (alpha + sign(alpha) sqrt(D)), which does not
-// cancel when Sigma << alpha^2.  D < 0 is clamped (Sigma raised to -3 alpha^2/8).
+// and K is the root of eq:DGP, (3/4)[-alpha + sign(alpha) sqrt(D)] with
+// D = alpha^2 + 8 Sigma/3, in that form.  Its cancellation for Sigma << alpha^2
+// costs an absolute error of about one ulp of alpha (~1e-15 here), far below
+// any residual tolerance, and saves the division of the cancellation-free
+// 2 Sigma / (alpha + sign(alpha) sqrt(D)).  D < 0 is clamped to 0 (K = -3 alpha/4).
 template <int MODEL, typename T, typename L_>
 __device__ __forceinline__ T model_term(const Mod &M, const L_ &L, const NbT<T> &s, T delta,
                                         unsigned long long *clamp) {
@@ -106,14 +108,13 @@ __device__ __forceinline__ T model_term(const Mod &M, const L_ &L, const NbT<T> 
         const T dxy = ax - ay, dxz = ax - az, dyz = ay - az;
         const T t3 = dxy * dxy + dxz * dxz + dyz * dyz;
         const T t8 = s.nxy * s.nxy + s.nxz * s.nxz + s.nyz * s.nyz;
-        double sig = (double)t3 * L.c3h4 + (double)t8 * L.c8h4 + M.s * (double)delta;
+        const double sig = (double)t3 * L.c3h4 + (double)t8 * L.c8h4 + M.s * (double)delta;
         double disc = M.alpha * M.alpha + (8.0 / 3.0) * sig;
         if (disc < 0.0) {
-            sig = -0.375 * M.alpha * M.alpha;
             disc = 0.0;
             if (clamp) atomicAdd(clamp, 1ull);
         }
-        return (T)(2.0 * sig / (M.alpha + M.sgn * sqrt(disc)));
+        return (T)(0.75 * (M.sgn * sqrt(disc) - M.alpha));
     }
     // Kmouflage split form eq:kmf_eqn_codeunit_final: with e = 2h grad phi,
     //   g = |e|^2/(4h^2),  Q = hat(H)_ij G_i G_j

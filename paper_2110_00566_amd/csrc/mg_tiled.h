@@ -22,11 +22,31 @@ struct TileGeom {
     int ntx, nty, kz;   // tiles in x, tiles in y, planes per block
 };
 
-__device__ __forceinline__ size_t tile_gidx(int e, int j0, int m0, int k, int logn, int lognh) {
+// Byte offsets for the marching kernels: a thread's positions inside a z-plane
+// are fixed for the whole march, so their offsets are computed once (32 bit)
+// and each plane adds one uniform (scalar) base.
+template <typename R>
+__device__ __forceinline__ unsigned stage_off(int e, int j0, int m0, int logn, int lognh) {
     const int r = e / TXH, q = e - r * TXH;
-    const int nm1 = (1 << logn) - 1, hm1 = (1 << lognh) - 1;
-    const int j = (j0 - 1 + r) & nm1, m = (m0 - 1 + q) & hm1;
-    return prow(j, k & nm1, logn, lognh) + m;
+    const unsigned j = (unsigned)(j0 - 1 + r) & ((1u << logn) - 1);
+    const unsigned m = (unsigned)(m0 - 1 + q) & ((1u << lognh) - 1);
+    return ((j << lognh) + m) * (unsigned)sizeof(R);
+}
+template <typename R>
+__device__ __forceinline__ unsigned cell_off(int j, int m, int lognh) {
+    return (((unsigned)j << lognh) + (unsigned)m) * (unsigned)sizeof(R);
+}
+template <typename R>
+__device__ __forceinline__ size_t plane_off(int k, int logn, int lognh) {
+    return ((size_t)((unsigned)k & ((1u << logn) - 1)) << (logn + lognh)) * sizeof(R);
+}
+template <typename R>
+__device__ __forceinline__ R ld(const R *base, size_t plane, unsigned off) {
+    return *reinterpret_cast<const R *>(reinterpret_cast<const char *>(base) + plane + off);
+}
+template <typename R>
+__device__ __forceinline__ R *ptr(R *base, size_t plane, unsigned off) {
+    return reinterpret_cast<R *>(reinterpret_cast<char *>(base) + plane + off);
 }
 
 // Stencil of the cell at local (r, q) (halo-shifted tile coordinates) with
@@ -67,15 +87,19 @@ __global__ __launch_bounds__(TPB) void k_pass_tiled(Mod M, LvlT<R> L, int c, R *
     const R *F = c ? L.f1 : L.f0;
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     const R fs = (R)(fptr ? fscale * (*fptr) : 0.0);
+    unsigned soff[TLOADS], coff[2];
+#pragma unroll
+    for (int q = 0; q < TLOADS; ++q) soff[q] = stage_off<R>(tid + q * TPB, j0, m0, L.logn, L.lognh);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) coff[h] = cell_off<R>(j0 + ty + 4 * h, m0 + tx, L.lognh);
     R ra[TLOADS], rb[TLOADS];
     auto fetch = [&](int k) {
+        const size_t pl = plane_off<R>(k, L.logn, L.lognh);
 #pragma unroll
         for (int q = 0; q < TLOADS; ++q) {
-            const int e = tid + q * TPB;
-            if (e < TPLANE) {
-                const size_t g = tile_gidx(e, j0, m0, k, L.logn, L.lognh);
-                ra[q] = A[g];
-                rb[q] = B[g];
+            if (tid + q * TPB < TPLANE) {
+                ra[q] = ld(A, pl, soff[q]);
+                rb[q] = ld(B, pl, soff[q]);
             }
         }
     };
@@ -92,11 +116,11 @@ __global__ __launch_bounds__(TPB) void k_pass_tiled(Mod M, LvlT<R> L, int c, R *
     // own cells' delta and f, one plane ahead
     R dn[2], fn[2];
     auto fetch_cells = [&](int k) {
+        const size_t pl = plane_off<R>(k, L.logn, L.lognh);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const size_t idx = prow(j0 + ty + 4 * h, k, L.logn, L.lognh) + m0 + tx;
-            dn[h] = D[idx];
-            fn[h] = F ? F[idx] : (R)0;
+            dn[h] = ld(D, pl, coff[h]);
+            fn[h] = F ? ld(F, pl, coff[h]) : (R)0;
         }
     };
     // slot of plane k: (k - k0 + 1) mod 3
@@ -116,134 +140,141 @@ __global__ __launch_bounds__(TPB) void k_pass_tiled(Mod M, LvlT<R> L, int c, R *
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int row = ty + 4 * h;
-            const int j = j0 + row, m = m0 + tx;
+            const int j = j0 + row;
             const int p = (j + k + c) & 1;
             const NbT<R> s = lds_nb<R, R>(sA[sm], sA[s0], sA[sp], sB[s0], sB[sm], sB[sp], row + 1,
                                           tx + 1, p);
-            const size_t idx = prow(j, k, L.logn, L.lognh) + m;
             const R faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
             const R K = model_term<OP, R>(M, L, s, h ? d1 : d0, clamp);
             const R f = (h ? f1 : f0) + fs;
             // streamed: the next reader is a later launch
-            __builtin_nontemporal_store((faces - (R)L.h2 * (K + f)) * (R)(1.0 / 6.0), out + idx);
+            __builtin_nontemporal_store((faces - (R)L.h2 * (K + f)) * (R)(1.0 / 6.0),
+                                        ptr(out, plane_off<R>(k, L.logn, L.lognh), coff[h]));
         }
         __syncthreads();
     }
 }
 
 // Residual + restriction (see k_resid_restrict) for a tile of 64 x 4 coarse
-// cells marching over coarse planes: fine planes 2K-1 .. 2K+2 of both colours
-// are staged (ring of 4), two new fine planes per coarse plane.
-template <int OP, bool REDUCE, typename R>
+// cells.  The block marches over the fine planes of its coarse z-chunk with a
+// ring of 3 staged planes of both colours, like the pass; a thread owns one
+// coarse cell and computes its 4 children in each fine plane (rows 2ty,
+// 2ty+1, both colours), summing over the two fine planes of the coarse
+// plane.  kz counts coarse planes.  HASF: the level has a right-hand side f
+// (every level but the finest).
+template <int OP, bool REDUCE, bool HASF, typename R>
 __global__ __launch_bounds__(TPB) void k_resid_restrict_tiled(Mod M, LvlT<R> L, const double *fptr,
                                                               double fscale, R *ru0, R *ru1,
                                                               R *rd0, R *rd1, double *partials,
                                                               unsigned long long *clamp,
                                                               TileGeom G) {
-    __shared__ R s0[4][TPLANE], s1[4][TPLANE];
+    __shared__ R s0[3][TPLANE], s1[3][TPLANE];
     const size_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int bx = (int)(blk % G.ntx);
     const int by = (int)((blk / G.ntx) % G.nty);
     const int bz = (int)(blk / ((size_t)G.ntx * G.nty));
     // fine tile: packed columns m0.., fine rows j0 .. j0+7 (coarse rows j0/2 ..)
-    const int m0 = bx * TX, j0 = by * TY, K0 = bz * G.kz;
+    const int m0 = bx * TX, j0 = by * TY, k0 = 2 * bz * G.kz, k1 = k0 + 2 * G.kz;
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     const int lnc = L.logn - 1;
-    // two planes in flight: (a0, a1) and (b0, b1) hold colours 0 and 1
-    R a0[TLOADS], a1[TLOADS], b0[TLOADS], b1[TLOADS];
-    auto fetch = [&](int k, R *x0, R *x1) {
+    unsigned soff[TLOADS], coff[2];
+#pragma unroll
+    for (int q = 0; q < TLOADS; ++q) soff[q] = stage_off<R>(tid + q * TPB, j0, m0, L.logn, L.lognh);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) coff[b] = cell_off<R>(j0 + 2 * ty + b, m0 + tx, L.lognh);
+    R ra[TLOADS], rb[TLOADS];
+    auto fetch = [&](int k) {
+        const size_t pl = plane_off<R>(k, L.logn, L.lognh);
+#pragma unroll
+        for (int q = 0; q < TLOADS; ++q) {
+            if (tid + q * TPB < TPLANE) {
+                ra[q] = ld(L.u0, pl, soff[q]);
+                rb[q] = ld(L.u1, pl, soff[q]);
+            }
+        }
+    };
+    auto store = [&](int slot) {
 #pragma unroll
         for (int q = 0; q < TLOADS; ++q) {
             const int e = tid + q * TPB;
             if (e < TPLANE) {
-                const size_t g = tile_gidx(e, j0, m0, k, L.logn, L.lognh);
-                x0[q] = L.u0[g];
-                x1[q] = L.u1[g];
+                s0[slot][e] = ra[q];
+                s1[slot][e] = rb[q];
             }
         }
     };
-    auto store = [&](int slot, const R *x0, const R *x1) {
+    // delta (and f) of the 4 children in a fine plane, one plane ahead
+    R dn[4], fn[4];
+    auto fetch_cells = [&](int k) {
+        const size_t pl = plane_off<R>(k, L.logn, L.lognh);
 #pragma unroll
-        for (int q = 0; q < TLOADS; ++q) {
-            const int e = tid + q * TPB;
-            if (e < TPLANE) {
-                s0[slot][e] = x0[q];
-                s1[slot][e] = x1[q];
+        for (int b = 0; b < 2; ++b) {
+            dn[2 * b] = ld(L.d0, pl, coff[b]);
+            dn[2 * b + 1] = ld(L.d1, pl, coff[b]);
+            if (HASF) {
+                fn[2 * b] = ld(L.f0, pl, coff[b]);
+                fn[2 * b + 1] = ld(L.f1, pl, coff[b]);
             }
         }
     };
-    const int I = m0 + tx, J = (j0 >> 1) + ty;
-    // the 8 children's delta and f, one coarse plane ahead
-    double dn[8], fn[8];
-    auto fetch_cells = [&](int K) {
-#pragma unroll
-        for (int qc = 0; qc < 8; ++qc) {
-            const int a = qc & 1, b = (qc >> 1) & 1, cc = qc >> 2;
-            const int col = (a + b + cc) & 1;
-            const size_t idx = prow(2 * J + b, 2 * K + cc, L.logn, L.lognh) + I;
-            dn[qc] = (double)(col ? L.d1 : L.d0)[idx];
-            const R *F = col ? L.f1 : L.f0;
-            fn[qc] = F ? (double)F[idx] : 0.0;
-        }
-    };
-    // slot of fine plane k: (k - 2K0 + 1) & 3
-    fetch(2 * K0 - 1, a0, a1);
-    fetch(2 * K0, b0, b1);
-    store(0, a0, a1);
-    store(1, b0, b1);
-    fetch(2 * K0 + 1, a0, a1);
-    fetch(2 * K0 + 2, b0, b1);
-    fetch_cells(K0);
-    double acc1 = 0.0, acc2 = 0.0;
+    // slot of fine plane k: (k - k0 + 1) mod 3
+    fetch(k0 - 1);
+    store(0);
+    fetch(k0);
+    store(1);
+    fetch(k0 + 1);
+    fetch_cells(k0);
+    double su = 0.0, sd = 0.0, acc1 = 0.0, acc2 = 0.0;
     const double fs = fptr ? fscale * (*fptr) : 0.0;
     const double inv_h2 = 1.0 / L.h2;
-    for (int K = K0; K < K0 + G.kz; ++K) {
-        store((2 * K + 1 - 2 * K0 + 1) & 3, a0, a1);
-        store((2 * K + 2 - 2 * K0 + 1) & 3, b0, b1);
-        double dc[8], fc[8];
+    for (int k = k0; k < k1; ++k) {
+        const int sm = (k - k0) % 3, sz = (k - k0 + 1) % 3, sp = (k - k0 + 2) % 3;
+        store(sp);
+        R dc[4], fc[4];
 #pragma unroll
-        for (int qc = 0; qc < 8; ++qc) {
-            dc[qc] = dn[qc];
-            fc[qc] = fn[qc];
+        for (int q = 0; q < 4; ++q) {
+            dc[q] = dn[q];
+            if (HASF) fc[q] = fn[q];
         }
         __syncthreads();
-        if (K + 1 < K0 + G.kz) {
-            fetch(2 * K + 3, a0, a1);
-            fetch(2 * K + 4, b0, b1);
-            fetch_cells(K + 1);
-        }
-        double sd = 0.0, su = 0.0;
+        if (k + 2 <= k1) fetch(k + 2);
+        if (k + 1 < k1) fetch_cells(k + 1);
 #pragma unroll
-        for (int qc = 0; qc < 8; ++qc) {
-            const int a = qc & 1, b = (qc >> 1) & 1, cc = qc >> 2;
-            const int k = 2 * K + cc, j = 2 * J + b;
-            const int col = (a + b + cc) & 1;
-            const int sm = (k - 1 - 2 * K0 + 1) & 3, sz = (k - 2 * K0 + 1) & 3,
-                      sp = (k + 1 - 2 * K0 + 1) & 3;
-            const R *Am = col ? s1[sm] : s0[sm];
-            const R *A0 = col ? s1[sz] : s0[sz];
-            const R *Ap = col ? s1[sp] : s0[sp];
-            const R *Bm = col ? s0[sm] : s1[sm];
-            const R *B0 = col ? s0[sz] : s1[sz];
-            const R *Bp = col ? s0[sp] : s1[sp];
-            const int r = 2 * ty + b + 1, q = tx + 1;
-            const Nb s = lds_nb<double, R>(Am, A0, Ap, B0, Bm, Bp, r, q, a);
-            const double u = (double)A0[r * TXH + q];
-            const double faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
-            const double f = fc[qc] + fs;
-            (void)j;
-            const double d = (faces - 6.0 * u) * inv_h2 - model_term<OP, double>(M, L, s, dc[qc], clamp) - f;
-            sd += d;
-            su += u;
-            if (REDUCE) {
-                acc1 += d;
-                acc2 += d * d;
+        for (int b = 0; b < 2; ++b) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int row = 2 * ty + b;
+                const int p = (j0 + row + k + c) & 1;
+                const R *Am = c ? s1[sm] : s0[sm];
+                const R *A0 = c ? s1[sz] : s0[sz];
+                const R *Ap = c ? s1[sp] : s0[sp];
+                const R *Bm = c ? s0[sm] : s1[sm];
+                const R *B0 = c ? s0[sz] : s1[sz];
+                const R *Bp = c ? s0[sp] : s1[sp];
+                const int r = row + 1, q = tx + 1;
+                const Nb s = lds_nb<double, R>(Am, A0, Ap, B0, Bm, Bp, r, q, p);
+                const double u = (double)A0[r * TXH + q];
+                const double faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
+                const double f = (HASF ? (double)fc[2 * b + c] : 0.0) + fs;
+                const double d = (faces - 6.0 * u) * inv_h2 -
+                                 model_term<OP, double>(M, L, s, (double)dc[2 * b + c], clamp) - f;
+                sd += d;
+                su += u;
+                if (REDUCE) {
+                    acc1 += d;
+                    acc2 += d * d;
+                }
             }
         }
-        const size_t cidx = ((size_t)K << (2 * lnc - 1)) + ((size_t)J << (lnc - 1)) + (I >> 1);
-        const int ccol = (I + J + K) & 1;
-        (ccol ? ru1 : ru0)[cidx] = (R)(0.125 * su);
-        (ccol ? rd1 : rd0)[cidx] = (R)(0.125 * sd);
+        if (k & 1) {
+            const int K = k >> 1, I = m0 + tx, J = (j0 >> 1) + ty;
+            const size_t cidx = ((size_t)K << (2 * lnc - 1)) + ((size_t)J << (lnc - 1)) + (I >> 1);
+            const int ccol = (I + J + K) & 1;
+            (ccol ? ru1 : ru0)[cidx] = (R)(0.125 * su);
+            (ccol ? rd1 : rd0)[cidx] = (R)(0.125 * sd);
+            su = 0.0;
+            sd = 0.0;
+        }
         __syncthreads();
     }
     if (REDUCE) block_sum2(acc1, acc2, partials, blk);
@@ -409,15 +440,19 @@ __global__ __launch_bounds__(TPB) void k_prolong_pass_tiled(Mod M, LvlT<R> L, R 
     };
 
     // raw fine values of the next plane, and own cells' delta and f
+    unsigned soff[TLOADS], coff[2];
+#pragma unroll
+    for (int q = 0; q < TLOADS; ++q) soff[q] = stage_off<R>(tid + q * TPB, j0, m0, L.logn, L.lognh);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) coff[h] = cell_off<R>(j0 + ty + 4 * h, m0 + tx, L.lognh);
     R ra[TLOADS], rb[TLOADS];
     auto fetch = [&](int k) {
+        const size_t pl = plane_off<R>(k, L.logn, L.lognh);
 #pragma unroll
         for (int q = 0; q < TLOADS; ++q) {
-            const int e = tid + q * TPB;
-            if (e < TPLANE) {
-                const size_t g = tile_gidx(e, j0, m0, k, L.logn, L.lognh);
-                ra[q] = L.u0[g];
-                rb[q] = L.u1[g];
+            if (tid + q * TPB < TPLANE) {
+                ra[q] = ld(L.u0, pl, soff[q]);
+                rb[q] = ld(L.u1, pl, soff[q]);
             }
         }
     };
@@ -440,11 +475,11 @@ __global__ __launch_bounds__(TPB) void k_prolong_pass_tiled(Mod M, LvlT<R> L, R 
     };
     R dn[2], fn[2];
     auto fetch_cells = [&](int k) {
+        const size_t pl = plane_off<R>(k, L.logn, L.lognh);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const size_t idx = prow(j0 + ty + 4 * h, k, L.logn, L.lognh) + m0 + tx;
-            dn[h] = L.d0[idx];
-            fn[h] = L.f0 ? L.f0[idx] : (R)0;
+            dn[h] = ld(L.d0, pl, coff[h]);
+            fn[h] = L.f0 ? ld(L.f0, pl, coff[h]) : (R)0;
         }
     };
 
@@ -495,16 +530,17 @@ __global__ __launch_bounds__(TPB) void k_prolong_pass_tiled(Mod M, LvlT<R> L, R 
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int row = ty + 4 * h;
-            const int j = j0 + row, m = m0 + tx;
+            const int j = j0 + row;
             const int p = (j + k) & 1;
             const NbT<R> s = lds_nb<R, R>(sA[sm], sA[s0], sA[sp], sB[s0], sB[sm], sB[sp], row + 1,
                                           tx + 1, p);
-            const size_t idx = prow(j, k, L.logn, L.lognh) + m;
+            const size_t pl = plane_off<R>(k, L.logn, L.lognh);
             const R faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
             const R K = model_term<OP, R>(M, L, s, h ? d1 : d0, clamp);
             const R f = (h ? f1 : f0) + fs;
-            __builtin_nontemporal_store((faces - (R)L.h2 * (K + f)) * (R)(1.0 / 6.0), out0 + idx);
-            __builtin_nontemporal_store(sB[s0][(row + 1) * TXH + tx + 1], out1 + idx);
+            __builtin_nontemporal_store((faces - (R)L.h2 * (K + f)) * (R)(1.0 / 6.0),
+                                        ptr(out0, pl, coff[h]));
+            __builtin_nontemporal_store(sB[s0][(row + 1) * TXH + tx + 1], ptr(out1, pl, coff[h]));
         }
         if (cnew) interp(xnx);
         __syncthreads();
@@ -529,15 +565,20 @@ __global__ __launch_bounds__(TPB) void k_coarse_source_tiled(Mod M, LvlT<R> Lc, 
     const int m0 = bx * TX, j0 = by * TY, k0 = bz * G.kz;
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     const double sh = shift ? *shift : 0.0;
+    unsigned soff[TLOADS], coff[2];
+#pragma unroll
+    for (int q = 0; q < TLOADS; ++q)
+        soff[q] = stage_off<R>(tid + q * TPB, j0, m0, Lc.logn, Lc.lognh);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) coff[h] = cell_off<R>(j0 + ty + 4 * h, m0 + tx, Lc.lognh);
     R ra[TLOADS], rb[TLOADS];
     auto fetch = [&](int k) {
+        const size_t pl = plane_off<R>(k, Lc.logn, Lc.lognh);
 #pragma unroll
         for (int q = 0; q < TLOADS; ++q) {
-            const int e = tid + q * TPB;
-            if (e < TPLANE) {
-                const size_t g = tile_gidx(e, j0, m0, k, Lc.logn, Lc.lognh);
-                ra[q] = Lc.u0[g];
-                rb[q] = Lc.u1[g];
+            if (tid + q * TPB < TPLANE) {
+                ra[q] = ld(Lc.u0, pl, soff[q]);
+                rb[q] = ld(Lc.u1, pl, soff[q]);
             }
         }
     };
@@ -564,7 +605,7 @@ __global__ __launch_bounds__(TPB) void k_coarse_source_tiled(Mod M, LvlT<R> Lc, 
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
             const int row = ty + 4 * (h & 1), c = h >> 1;
-            const int j = j0 + row, m = m0 + tx;
+            const int j = j0 + row;
             const int p = (j + k + c) & 1;
             const R *Am = c ? sB[sm] : sA[sm];
             const R *A0 = c ? sB[sz] : sA[sz];
@@ -573,15 +614,16 @@ __global__ __launch_bounds__(TPB) void k_coarse_source_tiled(Mod M, LvlT<R> Lc, 
             const R *B0 = c ? sA[sz] : sB[sz];
             const R *Bp = c ? sA[sp] : sB[sp];
             const Nb s = lds_nb<double, R>(Am, A0, Ap, B0, Bm, Bp, row + 1, tx + 1, p);
-            const size_t idx = prow(j, k, Lc.logn, Lc.lognh) + m;
+            const size_t pl = plane_off<R>(k, Lc.logn, Lc.lognh);
+            const unsigned o = coff[h & 1];
             const R ru = A0[(row + 1) * TXH + tx + 1];
             const double faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
-            const double delta = (double)(c ? Lc.d1 : Lc.d0)[idx];
-            R *S = c ? s1 : s0;
-            const double rd = (double)S[idx] - sh;
-            S[idx] = (R)((faces - 6.0 * (double)ru) / Lc.h2
-                         - model_term<OP, double>(M, Lc, s, delta, nullptr) - rd);
-            (c ? u1 : u0)[idx] = ru;
+            const double delta = (double)ld(c ? Lc.d1 : Lc.d0, pl, o);
+            R *S = ptr(c ? s1 : s0, pl, o);
+            const double rd = (double)*S - sh;
+            *S = (R)((faces - 6.0 * (double)ru) / Lc.h2
+                     - model_term<OP, double>(M, Lc, s, delta, nullptr) - rd);
+            *ptr(c ? u1 : u0, pl, o) = ru;
         }
         __syncthreads();
     }
