@@ -73,6 +73,9 @@ def lib():
         L.or_mean.restype = C.c_double
         L.or_solve.argtypes = [_MP, C.c_int, C.c_double, _D, _D, C.c_int, C.c_double, C.c_int, C.c_int,
                                C.c_int, C.POINTER(Stats)]
+        L.or_solve_cycle.argtypes = [_MP, C.c_int, C.c_double, _D, _D, C.c_int, C.c_double,
+                                     C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_int,
+                                     C.POINTER(C.c_int), C.POINTER(Stats)]
         L.or_sweep.argtypes = [_MP, _D, _D, C.c_void_p, C.c_double, C.c_int, C.c_double, _D]
         L.or_jac_rows.argtypes = [_MP, _D, _D, C.c_int, C.c_double, _D]
         L.or_jac_apply.argtypes = [_D, _D, C.c_int, C.c_double, _D]
@@ -182,17 +185,41 @@ class SolveResult:
     nclamp: int = 0
 
 
+CYCLE_V, CYCLE_F, CYCLE_W = 0, 1, 2
+
+
 def solve(m: Model, delta, phi0=None, max_cycles: int = 50, tol: float = 1e-8,
-          nu1: int = 1, nu2: int = 1, nuc: int = 32, h0: float = 1.0) -> SolveResult:
-    """FAS V(nu1,nu2) solve from phi0 (default 0) on a mesh of spacing h0;
-    returns the zero-mean phi."""
+          nu1: int = 1, nu2: int = 1, nuc: int = 32, h0: float = 1.0,
+          cycle: int = CYCLE_V) -> SolveResult:
+    """FAS solve with V(nu1,nu2), F or W cycles (Sec. 3.2.1) from phi0
+    (default 0) on a mesh of spacing h0; returns the zero-mean phi."""
     delta = _c(delta)
     n = delta.shape[0]
     phi = np.zeros_like(delta) if phi0 is None else _c(phi0).copy()
     st = Stats()
-    lib().or_solve(C.byref(m), n, h0, delta, phi, max_cycles, tol, nu1, nu2, nuc, C.byref(st))
+    lib().or_solve_cycle(C.byref(m), n, h0, delta, phi, max_cycles, tol, nu1, nu2, nuc, cycle,
+                         None, 0, None, C.byref(st))
     return SolveResult(phi, st.status, st.cycles, st.eps0, st.eps, st.mu,
                        list(st.hist[:min(st.cycles, 256)]), st.nclamp)
+
+
+def cycle_trace(n: int, cycle: int) -> list:
+    """Levels (0 = finest) of the smoothing visits of one cycle on an n^3
+    mesh, consecutive visits of the same level merged: the walk drawn in
+    fig:multigrid_cycles."""
+    delta = np.zeros((n, n, n))
+    phi = np.zeros_like(delta)
+    cap = 1 << 16
+    buf = (C.c_int * cap)()
+    cnt = C.c_int(0)
+    st = Stats()
+    lib().or_solve_cycle(C.byref(linear_model(1.0)), n, 1.0, delta, phi, 1, -1.0, 1, 1, 1, cycle,
+                         C.cast(buf, C.c_void_p), cap, C.byref(cnt), C.byref(st))
+    walk = []
+    for q in range(min(cnt.value, cap)):
+        if not walk or walk[-1] != buf[q]:
+            walk.append(buf[q])
+    return walk
 
 
 def jac_rows(m: Model, phi, delta, h: float = 1.0):

@@ -14,6 +14,10 @@
  *   - Multigrid: relaxation eq:relaxation_iteration, FAS coarse equation
  *     eq:general_pde_numerical_coarse, 8-cell mean restriction, 27/9/3/1
  *     prolongation with eq:solution_correction, coarsest level 4^3 (Sec. 3.2.1).
+ *   - Cycle arrangements of Sec. 3.2.1 and fig:multigrid_cycles, as the
+ *     textbook recursions: V = one coarse cycle per level, W = two, F = an
+ *     F-cycle followed by a V-cycle on the coarse problem; every visit of the
+ *     coarsest level is nu_c sweeps.
  *
  * Readings where the paper is silent (all shared with the GPU path by
  * specification, never by code):
@@ -334,6 +338,8 @@ typedef struct {
     double mu;                      /* finest right-hand side (lagged mean L) */
     int nu1, nu2, nuc;
     long long nclamp;
+    int *trace;                     /* optional: level of every smoothing visit */
+    int ntrace, trace_cap;
 } or_hier;
 
 static int hier_init(or_hier *H, int n, double h0, const double *delta, double *phi)
@@ -403,10 +409,18 @@ static void finest_stats(const or_model *m, or_hier *H, double *mu, double *eps)
     *eps = sqrt(s2 / (double)n3);
 }
 
-static void vcycle(const or_model *m, or_hier *H, int l, double *eps_mid)
+static void visit(or_hier *H, int l)
+{
+    if (H->trace && H->ntrace < H->trace_cap) H->trace[H->ntrace] = l;
+    if (H->trace) ++H->ntrace;
+}
+
+/* One cycle of type 0 (V), 1 (F) or 2 (W) on level l. */
+static void mgcycle(const or_model *m, or_hier *H, int l, int type, double *eps_mid)
 {
     int n = H->n[l];
     size_t c = (size_t)n * n * n;
+    visit(H, l);
     if (l == H->nlev - 1) {
         for (int s = 0; s < H->nuc; ++s) sweep(m, H, l);
         return;
@@ -431,8 +445,17 @@ static void vcycle(const or_model *m, or_hier *H, int l, double *eps_mid)
     or_residual(m, H->ru[lc], H->delta[lc], NULL, 0.0, ncs, H->h[lc], H->f[lc], &H->nclamp);
     for (size_t q = 0; q < cc; ++q) H->f[lc][q] -= H->tmp[lc][q];
     memcpy(H->u[lc], H->ru[lc], sizeof(double) * cc);  /* initial guess R u */
-    vcycle(m, H, lc, NULL);
+    if (type == 2) {               /* W: two coarse W-cycles */
+        mgcycle(m, H, lc, 2, NULL);
+        mgcycle(m, H, lc, 2, NULL);
+    } else if (type == 1) {        /* F: a coarse F-cycle, then a coarse V-cycle */
+        mgcycle(m, H, lc, 1, NULL);
+        mgcycle(m, H, lc, 0, NULL);
+    } else {
+        mgcycle(m, H, lc, 0, NULL);
+    }
     or_prolong_add(H->u[l], n, H->u[lc], H->ru[lc]);
+    visit(H, l);
     for (int s = 0; s < H->nu2; ++s) sweep(m, H, l);
     (void)c;
 }
@@ -440,15 +463,23 @@ static void vcycle(const or_model *m, or_hier *H, int l, double *eps_mid)
 /* Solve the model equation for phi (in: initial guess, out: zero-mean
  * solution) on an n^3 mesh of spacing h0 (1 in code units).  tol is the absolute RMS of the mean-projected finest residual.
  * Returns the status code stored in st->status. */
-int or_solve(const or_model *m, int n, double h0, const double *delta, double *phi,
-             int max_cycles, double tol, int nu1, int nu2, int nuc, or_stats *st)
+/* Solve with cycles of the given type (0 V, 1 F, 2 W).  trace (may be NULL)
+ * receives the level of every smoothing visit, at most trace_cap entries;
+ * *ntrace the number of visits. */
+int or_solve_cycle(const or_model *m, int n, double h0, const double *delta, double *phi,
+                   int max_cycles, double tol, int nu1, int nu2, int nuc, int cycle,
+                   int *trace, int trace_cap, int *ntrace, or_stats *st)
 {
     or_hier H;
     memset(st, 0, sizeof(*st));
+    if (cycle < 0 || cycle > 2) return -1;
     if (hier_init(&H, n, h0, delta, phi)) return -1;
     H.nu1 = nu1;
     H.nu2 = nu2;
     H.nuc = nuc;
+    H.trace = trace;
+    H.trace_cap = trace_cap;
+    H.ntrace = 0;
     double mu, eps;
     finest_stats(m, &H, &mu, &eps);
     H.mu = mu;
@@ -460,7 +491,7 @@ int or_solve(const or_model *m, int n, double h0, const double *delta, double *p
     else {
         for (cyc = 1; cyc <= max_cycles; ++cyc) {
             double eps_mid = 0.0;
-            vcycle(m, &H, 0, &eps_mid);
+            mgcycle(m, &H, 0, cycle, &eps_mid);
             if (cyc - 1 < OR_HIST) st->hist[cyc - 1] = eps_mid;
             if (!isfinite(eps_mid)) { st->status = -3; break; }
             if (eps_mid > 1e3 * best) { st->status = -4; break; }
@@ -480,8 +511,16 @@ int or_solve(const or_model *m, int n, double h0, const double *delta, double *p
     long n3 = (long)n * n * n;
     for (long q = 0; q < n3; ++q) phi[q] -= mean;
     st->nclamp = H.nclamp;
+    if (ntrace) *ntrace = H.ntrace;
     hier_free(&H);
     return st->status;
+}
+
+int or_solve(const or_model *m, int n, double h0, const double *delta, double *phi,
+             int max_cycles, double tol, int nu1, int nu2, int nuc, or_stats *st)
+{
+    return or_solve_cycle(m, n, h0, delta, phi, max_cycles, tol, nu1, nu2, nuc, 0, NULL, 0, NULL,
+                          st);
 }
 
 /* Exposed single V-cycle building blocks for tests: one sweep on one level
