@@ -68,13 +68,16 @@ def cpu_baseline(pos_np):
                       "%.1f s" % dt}
 
 
-def vcycle_bytes(n: int) -> int:
+def vcycle_bytes(n: int, fused: bool = False) -> int:
     """Algorithmic HBM bytes of one FP64 V(1,1) cycle: per level 4 colour
     passes (16 B/cell), residual + restriction (18) and prolongation (18),
-    plus the coarse FAS source (40 B per coarse cell)."""
+    plus the coarse FAS source (40 B per coarse cell).  fused: the bytes the
+    executed kernels must move, where levels >= 128^3 fuse the prolongation
+    with the first post-smoothing pass (22 B/cell instead of 18 + 16)."""
     total, m, lev = 0, n, 0
     while m > 4:
-        total += 100 * m ** 3 + (40 * m ** 3 if lev else 0)
+        per = 88 if (fused and m >= 128) else 100
+        total += per * m ** 3 + (40 * m ** 3 if lev else 0)
         m //= 2
         lev += 1
     return total
@@ -101,11 +104,40 @@ def vcycle_time(mg, L, C, delta):
         times[cyc] = time.perf_counter() - t0
     ms = 1e3 * (times[6] - times[2]) / 4
     bytes_ = vcycle_bytes(n)
+    fbytes = vcycle_bytes(n, fused=True)
     del ws, phi
     torch.cuda.empty_cache()
     return {"n_mesh": n, "ms_per_vcycle": ms, "algorithmic_bytes_per_vcycle": bytes_,
             "achieved_GBs": bytes_ / (ms * 1e-3) / 1e9,
-            "frac_of_hbm_peak": bytes_ / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            "frac_of_hbm_peak": bytes_ / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "executed_min_bytes_per_vcycle": fbytes,
+            "executed_frac_of_hbm_peak": fbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
+def cycle_types(mg, L, C, delta, ws, par, phi_ref):
+    """Time to tol from phi = 0 with V(1,1), F(1,1) and W(1,1) cycles on the
+    same density (the arrangements of Sec. 3.2.1): cycles, ms, and the largest
+    relative difference from the V-cycle solution."""
+    import numpy as np
+    import torch
+    n = delta.shape[0]
+    phi = torch.zeros_like(delta)
+    res = {}
+    for name, cyc in (("V", mg.CYCLE_V), ("F", mg.CYCLE_F), ("W", mg.CYCLE_W)):
+        opts = mg.make_opts(n, tol=TOL, max_cycles=60, cycle=cyc)
+        secs, st = [], None
+        for rep in range(4):
+            phi.zero_()
+            st = mg.Stats()
+            mg._raise(L.mg_solve_dgp(C.byref(opts), C.byref(par), mg._ptr(delta), mg._ptr(phi),
+                                     mg._ptr(ws), ws.numel(), mg._stream(), C.byref(st)))
+            if rep:
+                secs.append(st.seconds)
+        assert st.status == 0 and st.eps <= TOL, (name, st.status)
+        err = float((phi - phi_ref).abs().max() / phi_ref.abs().max())
+        res[name] = {"cycles": int(st.cycles), "time_to_tol_ms": 1e3 * float(np.mean(secs)),
+                     "eps": float(st.eps), "max_rel_diff_phi_vs_V": err}
+    return res
 
 
 def vcycle_1024(mg, L, C, dev):
@@ -240,6 +272,7 @@ def main():
                     "eps_fp32": float(mstats[-1].eps_fp32), "eps": float(mstats[-1].eps),
                     "speedup_time_to_tol_vs_fp64": solve_ms / mix_solve_ms,
                     "max_rel_diff_phi_vs_fp64": err}
+    out["cycle_types"] = cycle_types(mg, L, C, delta, ws, par, phi64)
     del ws_mix, ws
     torch.cuda.empty_cache()
     out["vcycle_512"] = vcycle_time(mg, L, C, delta)

@@ -14,7 +14,7 @@
  *  - The caller owns every array and the workspace; the library never
  *    allocates, frees or keeps them.  Work is enqueued on the caller's
  *    stream.  Solver calls return after that stream has reached the end of
- *    the solve (the stopping test reads one residual per V-cycle).
+ *    the solve (the stopping test reads one residual per cycle).
  *  - Arguments are validated before the first GPU call; invalid ones give
  *    MG_ERR_ARG and mg_last_error() says which.  Positive status codes mean
  *    the outputs are valid (see the stats); negative codes leave outputs
@@ -45,12 +45,18 @@ typedef enum {
 typedef enum { MG_FP64 = 0, MG_MIXED = 1 } mg_precision;
 typedef enum { MG_MODEL_DGP = 0, MG_MODEL_KMOUFLAGE = 1, MG_MODEL_POISSON = 2 } mg_model;
 
-/* Solver options.  Sec. 3.2.1: FAS V-cycle with nonlinear red-black
+/* Multigrid cycle arrangements of Sec. 3.2.1 (fig:multigrid_cycles), as the
+ * textbook recursions: V = one coarse cycle per level, W = two coarse
+ * W-cycles, F = a coarse F-cycle followed by a coarse V-cycle.  Every visit
+ * of the 4^3 level runs nu_coarse sweeps. */
+typedef enum { MG_CYCLE_V = 0, MG_CYCLE_F = 1, MG_CYCLE_W = 2 } mg_cycle;
+
+/* Solver options.  Sec. 3.2.1: FAS cycles with nonlinear red-black
  * Gauss-Seidel smoothing, 8-cell mean restriction, 27/9/3/1 prolongation,
  * coarsest level 4^3. */
 typedef struct {
     int n;            /* cells per side of the finest mesh (power of two, 8..2048) */
-    int max_cycles;   /* cap on V-cycles (0..100000); default 50 */
+    int max_cycles;   /* cap on cycles (0..100000); default 50 */
     double tol;       /* stop when the RMS of the mean-projected finest residual
                          is <= tol (code units); 0 runs exactly max_cycles */
     int nu_pre;       /* smoothing sweeps before restriction (one sweep = colour 0
@@ -62,14 +68,15 @@ typedef struct {
                          residual stops falling, then FP64 cycles from that field to
                          tol; the final residual is always the FP64 one (forward
                          solves only; the adjoint is FP64) */
-    int cycle;        /* 0 = V-cycle (the only schedule in this version) */
+    int cycle;        /* mg_cycle: MG_CYCLE_V (default), MG_CYCLE_F or MG_CYCLE_W;
+                         mg_solve_adjoint accepts MG_CYCLE_V only */
     int profile;      /* 1: time every finest-level colour pass with HIP events
                          on the caller's stream (stats.pass_ms_avg) */
 } mg_opts;
 
 #define MG_HIST 64
 typedef struct {
-    int cycles;                 /* V-cycles run */
+    int cycles;                 /* cycles run */
     int status;                 /* same as the return value */
     double eps0;                /* residual of the initial guess */
     double eps;                 /* residual of the returned field */
@@ -80,7 +87,7 @@ typedef struct {
     double seconds;             /* host wall clock of the call */
     double pass_ms_avg;         /* mean finest colour-pass duration (profile=1) */
     int pass_count;             /* number of timed finest colour passes */
-    int cycles_fp32;            /* MG_MIXED: V-cycles of the FP32 phase (included in cycles) */
+    int cycles_fp32;            /* MG_MIXED: cycles of the FP32 phase (included in cycles) */
     double eps_fp32;            /* MG_MIXED: residual at the end of the FP32 phase */
 } mg_stats;
 

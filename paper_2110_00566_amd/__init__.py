@@ -32,6 +32,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "mgglam.h")
 MG_OK, MG_NOT_CONVERGED, MG_WARN_CLAMPED = 0, 1, 2
 MG_ERR_ARG, MG_ERR_HIP, MG_ERR_NONFINITE, MG_ERR_DIVERGED, MG_ERR_WORKSPACE = -1, -2, -3, -4, -5
 MODEL_DGP, MODEL_KMOUFLAGE, MODEL_POISSON = 0, 1, 2
+CYCLE_V, CYCLE_F, CYCLE_W = 0, 1, 2
 OMEGA_M = 0.3089
 HIST = 64
 
@@ -180,8 +181,8 @@ def workspace(n: int, model: int = MODEL_DGP, adjoint: bool = False, device=None
 
 
 def make_opts(n, tol=1e-8, max_cycles=50, nu_pre=1, nu_post=1, nu_coarse=32, profile=False,
-              precision=MG_FP64):
-    return Opts(n, max_cycles, tol, nu_pre, nu_post, nu_coarse, precision, 0, int(profile))
+              precision=MG_FP64, cycle=CYCLE_V):
+    return Opts(n, max_cycles, tol, nu_pre, nu_post, nu_coarse, precision, cycle, int(profile))
 
 
 def dgp_params(a=1.0, omega_m=OMEGA_M, h0rc=1.0):
@@ -212,7 +213,7 @@ def _solve(fn, par, model, delta, phi0, ws, **kw):
 def solve_dgp(delta, phi0=None, a=1.0, omega_m=OMEGA_M, h0rc=1.0, ws=None, **kw):
     """nDGP field (eq:dgp_eom_code); returns (zero-mean phi, stats).
     Keywords: tol, max_cycles, nu_pre, nu_post, nu_coarse, profile,
-    precision (MG_FP64 or MG_MIXED)."""
+    precision (MG_FP64 or MG_MIXED), cycle (CYCLE_V, CYCLE_F or CYCLE_W)."""
     return _solve(lib().mg_solve_dgp, dgp_params(a, omega_m, h0rc), MODEL_DGP, delta, phi0, ws, **kw)
 
 

@@ -96,6 +96,7 @@ struct Ctx {
     hipStream_t st = nullptr;
     Mod M{};
     int nu1 = 1, nu2 = 1, nuc = 32;
+    int cycle = 0;   // 0 V, 1 F, 2 W
     double kappa = 6.0;
     bool profile = false;
     std::vector<hipEvent_t> ev;
@@ -314,7 +315,8 @@ mg_status check_opts(const mg_opts *o) {
         return fail(MG_ERR_ARG, "sweep counts out of range");
     if (o->precision != MG_FP64 && o->precision != MG_MIXED)
         return fail(MG_ERR_ARG, "opts.precision must be MG_FP64 or MG_MIXED");
-    if (o->cycle != 0) return fail(MG_ERR_ARG, "only the V-cycle (cycle = 0) is available");
+    if (o->cycle < MG_CYCLE_V || o->cycle > MG_CYCLE_W)
+        return fail(MG_ERR_ARG, "opts.cycle must be MG_CYCLE_V, MG_CYCLE_F or MG_CYCLE_W");
     return MG_OK;
 }
 
@@ -433,13 +435,15 @@ struct Solver {
         k_tail<OP, NL, R><<<1, TAIL_THREADS, lds, C.st>>>(C.M, A);
     }
 
-    // Levels l.. (all <= 16^3, l >= 1) in one single-workgroup launch.
-    void tail(int l) {
+    // Levels l.. (all <= 16^3, l >= 1) in one single-workgroup launch that
+    // runs a cycle of the given type on them.
+    void tail(int l, int type) {
         TailArgs<R> A;
         A.nlev = Hh.nlev - l;
         A.nu1 = C.nu1;
         A.nu2 = C.nu2;
         A.nuc = C.nuc;
+        A.cycle = type;
         for (int q = 0; q < A.nlev; ++q) {
             HLevel<R> &H = Hh.lv[l + q];
             A.lv[q].L = view(H, true);
@@ -461,9 +465,11 @@ struct Solver {
         return Hh.nlev;
     }
 
-    void vcycle(int l) {
+    // One cycle of type 0 (V), 1 (F: a coarse F-cycle then a coarse V-cycle)
+    // or 2 (W: two coarse W-cycles) on level l (Sec. 3.2.1).
+    void cycle(int l, int type) {
         if (l > 0 && l == tail_start()) {
-            tail(l);
+            tail(l, type);
             return;
         }
         if (l == Hh.nlev - 1) {
@@ -473,7 +479,15 @@ struct Solver {
         for (int s = 0; s < C.nu1; ++s) sweep(l);
         resid_restrict(l);
         coarse_source(l + 1);
-        vcycle(l + 1);
+        if (type == 2) {
+            cycle(l + 1, 2);
+            cycle(l + 1, 2);
+        } else if (type == 1) {
+            cycle(l + 1, 1);
+            cycle(l + 1, 0);
+        } else {
+            cycle(l + 1, 0);
+        }
         if (fused_prolong(l)) {
             prolong_pass0(l);
             pass(l, 1);
@@ -524,7 +538,7 @@ struct Solver {
         int cyc = 0;
         if (status != MG_OK) {
             for (cyc = 1; cyc <= max_cycles; ++cyc) {
-                vcycle(0);
+                cycle(0, C.cycle);
                 if ((rc = read_scal(hs)) != MG_OK) return rc;
                 const double em = std::sqrt(hs[S_EPS2]);
                 if (hist0 + cyc - 1 < MG_HIST) st->eps_hist[hist0 + cyc - 1] = em;
@@ -610,6 +624,7 @@ mg_status forward_solve(const mg_opts *o, const Mod &M, const double *delta, dou
     C.nu1 = o->nu_pre;
     C.nu2 = o->nu_post;
     C.nuc = o->nu_coarse;
+    C.cycle = o->cycle;
     Profiler prof(C, o->profile != 0, 2 * (o->nu_pre + o->nu_post) + 2);
     reset_scalars(C);
     HLevel<double> &F = C.h64.lv[0];
@@ -887,6 +902,7 @@ mg_status mg_solve_adjoint(const mg_opts *opts, int model, const void *params,
     mg_status rc = common_checks(opts, delta, phi, ws, stats);
     if (rc != MG_OK) return rc;
     if (opts->precision != MG_FP64) return fail(MG_ERR_ARG, "the adjoint solve is FP64 only");
+    if (opts->cycle != MG_CYCLE_V) return fail(MG_ERR_ARG, "the adjoint solve uses V-cycles only");
     if (!w || !grad_delta || !mu) return fail(MG_ERR_ARG, "w, grad_delta and mu must be device pointers");
     Mod M;
     if (!model_mod(model, params, opts->n, M)) return fail(MG_ERR_ARG, "invalid model or parameters");

@@ -428,6 +428,7 @@ struct TailLv {
 template <typename R>
 struct TailArgs {
     int nlev, nu1, nu2, nuc;
+    int cycle;   // 0 V, 1 F, 2 W
     TailLv<R> lv[TAIL_MAX_LEVELS];
     Coefs cf[TAIL_MAX_LEVELS];
 };
@@ -474,43 +475,52 @@ __host__ __device__ inline int tail_lds_elems(int logn0, int nl) {
     return tot;
 }
 
+// FAS transfer from tail level l to l+1: residual, R u and R d, coarse source.
 template <int OP, int NL, typename R>
-__device__ __forceinline__ void tail_down(const Mod &M, TailLv<R> (&T)[NL],
-                                          const Coefs (&Cf)[NL], int nu1) {
-#pragma unroll
-    for (int l = 0; l < NL - 1; ++l) {
-        tail_sweeps<OP, R>(M, T[l], Cf[l], nu1);
-        TailLv<R> &Tc = T[l + 1];
-        double s1 = 0.0, s2 = 0.0;
-        const int ncoarse = 1 << (3 * Tc.L.logn);
-        for (int t = threadIdx.x; t < ncoarse; t += TAIL_THREADS)
-            dev_resid_restrict<OP, false, R>(M, T[l].L, Cf[l], nullptr, 0.0, Tc.ru0, Tc.ru1,
-                                             const_cast<R *>(Tc.L.f0), const_cast<R *>(Tc.L.f1),
-                                             nullptr, (size_t)t, s1, s2);
-        __syncthreads();
-        LvlT<R> Lr = Tc.L;
-        Lr.u0 = Tc.ru0;
-        Lr.u1 = Tc.ru1;
-        for (int t = threadIdx.x; t < ncoarse; t += TAIL_THREADS)
-            dev_coarse_source<OP, R>(M, Lr, Cf[l + 1], const_cast<R *>(Tc.L.f0),
-                                     const_cast<R *>(Tc.L.f1), Tc.L.u0, Tc.L.u1, nullptr,
-                                     (size_t)t);
-        __syncthreads();
-    }
+__device__ __forceinline__ void tail_restrict(const Mod &M, TailLv<R> (&T)[NL],
+                                              const Coefs (&Cf)[NL], int l) {
+    TailLv<R> &Tc = T[l + 1];
+    double s1 = 0.0, s2 = 0.0;
+    const int ncoarse = 1 << (3 * Tc.L.logn);
+    for (int t = threadIdx.x; t < ncoarse; t += TAIL_THREADS)
+        dev_resid_restrict<OP, false, R>(M, T[l].L, Cf[l], nullptr, 0.0, Tc.ru0, Tc.ru1,
+                                         const_cast<R *>(Tc.L.f0), const_cast<R *>(Tc.L.f1),
+                                         nullptr, (size_t)t, s1, s2);
+    __syncthreads();
+    LvlT<R> Lr = Tc.L;
+    Lr.u0 = Tc.ru0;
+    Lr.u1 = Tc.ru1;
+    for (int t = threadIdx.x; t < ncoarse; t += TAIL_THREADS)
+        dev_coarse_source<OP, R>(M, Lr, Cf[l + 1], const_cast<R *>(Tc.L.f0),
+                                 const_cast<R *>(Tc.L.f1), Tc.L.u0, Tc.L.u1, nullptr, (size_t)t);
+    __syncthreads();
 }
 
-template <int OP, int NL, typename R>
-__device__ __forceinline__ void tail_up(const Mod &M, TailLv<R> (&T)[NL], const Coefs (&Cf)[NL],
-                                        int nu2) {
-#pragma unroll
-    for (int l = NL - 2; l >= 0; --l) {
-        const TailLv<R> &Tf = T[l], &Tc = T[l + 1];
+// One cycle (0 V, 1 F, 2 W) on tail level LV, recursing at compile time.
+template <int OP, int NL, int LV, typename R>
+__device__ __forceinline__ void tail_cycle(const Mod &M, TailLv<R> (&T)[NL], const Coefs (&Cf)[NL],
+                           const TailArgs<R> &A, int type) {
+    if constexpr (LV == NL - 1) {
+        tail_sweeps<OP, R>(M, T[LV], Cf[LV], A.nuc);
+    } else {
+        tail_sweeps<OP, R>(M, T[LV], Cf[LV], A.nu1);
+        tail_restrict<OP, NL, R>(M, T, Cf, LV);
+        if (type == 2) {
+            tail_cycle<OP, NL, LV + 1, R>(M, T, Cf, A, 2);
+            tail_cycle<OP, NL, LV + 1, R>(M, T, Cf, A, 2);
+        } else if (type == 1) {
+            tail_cycle<OP, NL, LV + 1, R>(M, T, Cf, A, 1);
+            tail_cycle<OP, NL, LV + 1, R>(M, T, Cf, A, 0);
+        } else {
+            tail_cycle<OP, NL, LV + 1, R>(M, T, Cf, A, 0);
+        }
+        const TailLv<R> &Tf = T[LV], &Tc = T[LV + 1];
         const int nfine = 1 << (3 * Tf.L.logn);
         for (int t = threadIdx.x; t < nfine; t += TAIL_THREADS)
             dev_prolong<R>(Tf.L.u0, Tf.L.u1, Tf.L.logn, Tc.L.u0, Tc.L.u1, Tc.ru0, Tc.ru1,
                            (size_t)t);
         __syncthreads();
-        tail_sweeps<OP, R>(M, Tf, Cf[l], nu2);
+        tail_sweeps<OP, R>(M, Tf, Cf[LV], A.nu2);
     }
 }
 
@@ -557,9 +567,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Mod M, TailArgs<R> A) {
         }
     }
     __syncthreads();
-    tail_down<OP, NL, R>(M, T, Cf, A.nu1);
-    tail_sweeps<OP, R>(M, T[NL - 1], Cf[NL - 1], A.nuc);
-    tail_up<OP, NL, R>(M, T, Cf, A.nu2);
+    tail_cycle<OP, NL, 0, R>(M, T, Cf, A, A.cycle);
     const int half0 = 1 << (3 * A.lv[0].L.logn - 1);
     lds_copy<R>(A.lv[0].L.u0, T[0].L.u0, half0);
     lds_copy<R>(A.lv[0].L.u1, T[0].L.u1, half0);

@@ -53,7 +53,8 @@ def _bad_solve(L, **over):
 
 @pytest.mark.parametrize("field,value", [("n", 24), ("n", 4), ("n", 4096), ("tol", -1.0),
                                          ("tol", float("nan")), ("max_cycles", -1),
-                                         ("nu_coarse", 0), ("precision", 7), ("cycle", 2)])
+                                         ("nu_coarse", 0), ("precision", 7), ("cycle", 3),
+                                         ("cycle", -1)])
 def test_invalid_options_rejected_before_gpu(L, field, value):
     assert _bad_solve(L, **{field: value}) == mg.MG_ERR_ARG
     assert len(L.mg_last_error()) > 0
@@ -79,6 +80,17 @@ def test_null_pointers_and_workspace(L):
     assert L.mg_solve_dgp(C.byref(o), C.byref(par), d, d, None, 1 << 30, None, C.byref(st)) == mg.MG_ERR_WORKSPACE
     assert L.mg_solve_dgp(C.byref(o), C.byref(par), d, d, d, 16, None, C.byref(st)) == mg.MG_ERR_WORKSPACE
     assert L.mg_solve_dgp(None, C.byref(par), d, d, d, 1 << 30, None, C.byref(st)) == mg.MG_ERR_ARG
+
+
+def test_adjoint_accepts_v_cycles_only(L):
+    o = mg.make_opts(32, cycle=mg.CYCLE_W)
+    st = mg.Stats()
+    d = C.c_void_p(0x1000)
+    par = mg.dgp_params()
+    rc = L.mg_solve_adjoint(C.byref(o), mg.MODEL_DGP, C.byref(par), d, d, d, d, d, d, 1 << 30,
+                            None, C.byref(st))
+    assert rc == mg.MG_ERR_ARG
+    assert b"V-cycles" in L.mg_last_error()
 
 
 def test_status_strings(L):

@@ -125,6 +125,35 @@ def test_tiled_levels_fixed_cycles_parity(name, n, cycles, nu1, nu2):
     assert np.allclose(st["eps_hist"], r.hist[:cycles], rtol=1e-8, atol=1e-300)
 
 
+@pytest.mark.parametrize("cycle", [mg.CYCLE_F, mg.CYCLE_W])
+@pytest.mark.parametrize("name,n", [("dgp", 32), ("kmo3", 32), ("dgp", 128), ("dgp_h05", 64)])
+def test_f_and_w_cycles_fixed_cycles_parity(name, n, cycle):
+    # F- and W-cycle arrangements (Sec. 3.2.1): the host recursion on the
+    # per-level kernels and the recursion inside the single-workgroup tail
+    gp, om = models(n)[name]
+    delta = inputs.lognormal_delta(n, 3)
+    r = oracle.solve(om, delta, tol=0.0, max_cycles=2, cycle=cycle)
+    fn = mg.lib().mg_solve_kmouflage if name.startswith("kmo") else mg.lib().mg_solve_dgp
+    phi, st = mg._solve(fn, gp, 1 if name.startswith("kmo") else 0, g(delta), None, None,
+                        tol=0.0, max_cycles=2, cycle=cycle)
+    assert st["cycles"] == 2
+    assert rel(c(phi), r.phi) <= 1e-11
+    assert np.allclose(st["eps_hist"], r.hist[:2], rtol=1e-8, atol=1e-300)
+
+
+@pytest.mark.parametrize("cycle", [mg.CYCLE_F, mg.CYCLE_W])
+def test_f_and_w_cycles_converge_to_the_v_solution(cycle):
+    n = 64
+    delta = inputs.lognormal_delta(n, 1)
+    ref = oracle.solve(oracle.dgp_model(1.0, OM, 1.0), delta, tol=1e-12, max_cycles=60)
+    phi, st = mg.solve_dgp(g(delta), tol=1e-12, max_cycles=60, cycle=cycle)
+    assert st["status"] == 0 and st["eps"] <= 1e-12
+    assert rel(c(phi), ref.phi) <= 1e-9
+    rv = oracle.solve(oracle.dgp_model(1.0, OM, 1.0), delta, tol=1e-12, max_cycles=60,
+                      cycle=cycle)
+    assert st["cycles"] == rv.cycles
+
+
 def test_config1_fixed_cycles_parity():
     # 32^3 lognormal (sigma = 1), nDGP H0 r_c = 1, a = 1: three V(1,1) cycles
     n = 32
