@@ -103,6 +103,46 @@ typedef struct {
     double k0, beta, lambda, a, omega_m, box_mpch, phibar, dphibar_dtau_over_h0;
 } mg_kmo_params;
 
+/* Kmouflage background cosmology (Sec. 3.2.5), computed on the host.
+ * K(X) = -1 + X + K0 X^n, A = exp(beta phi); flat, matter + radiation.
+ * The background field phibar(N), N = ln a, is integrated from z_init with
+ * phibar = dphibar/dN = 1e-30, solving the modified Friedmann equation for
+ * (aH)^2 at every step, and lambda is shot until H(a = 1) = H0 within
+ * htol (relative).  Units H0 = 1. */
+typedef struct {
+    int n_k;          /* n >= 2 (2..8) */
+    double k0;        /* K0 >= 0 */
+    double beta;      /* beta_Kmo */
+    double omega_m;   /* matter density today */
+    double omega_r;   /* radiation density today (see mg_omega_radiation) */
+    double z_init;    /* start of the integration, e.g. 1e5 */
+    double htol;      /* relative tolerance on H(a=1)/H0, in (0, 1e-2) */
+} mg_kmo_bg_params;
+
+typedef struct {
+    double lambda;    /* Lambda^4 / (M_Pl^2 H0^2) = lambda^2 of the model */
+    double h_miss;    /* H(a=1)/H0 - 1 reached */
+    int shots;        /* integrations run by the shooting */
+    int steps;        /* Runge-Kutta steps of the tabulating integration */
+} mg_kmo_bg_info;
+
+/* Omega_r of photons at t_cmb (K) plus n_eff massless neutrinos for the
+ * dimensionless Hubble constant h (Sec. 3.2.5: 2.7255 K, 3.046).  Returns a
+ * negative value for invalid arguments. */
+double mg_omega_radiation(double h, double t_cmb, double n_eff);
+
+/* Solve the background and tabulate it at the n_table scale factors of
+ * a_table (HOST array, strictly increasing within (1/(1+z_init), 1]): hubble
+ * = H/H0, hubble_dot = (dH/dt)/H0^2, phibar, dphibar_dtau = (d phibar/d tau)/H0
+ * (conformal time; the value mg_kmo_params.dphibar_dtau_over_h0 takes).
+ * Outputs are caller-owned HOST arrays of n_table values (n_table may be 0
+ * to get lambda only).  No GPU is used.  Errors: MG_ERR_ARG (invalid input,
+ * no root of the Friedmann equation, or the shooting did not converge; see
+ * mg_last_error). */
+mg_status mg_kmo_background(const mg_kmo_bg_params *par, int n_table, const double *a_table,
+                            double *hubble, double *hubble_dot, double *phibar,
+                            double *dphibar_dtau, mg_kmo_bg_info *info);
+
 /* Linear Poisson model lap(phi) = s * delta (used for the Newtonian
  * potential, eq:GR_poisson_codeunit with s = 1.5 Omega_m / a). */
 typedef struct { double s; } mg_poisson_params;

@@ -77,6 +77,17 @@ class KmoParams(C.Structure):
                 ("dphibar_dtau_over_h0", C.c_double)]
 
 
+class KmoBgParams(C.Structure):
+    _fields_ = [("n_k", C.c_int), ("k0", C.c_double), ("beta", C.c_double),
+                ("omega_m", C.c_double), ("omega_r", C.c_double), ("z_init", C.c_double),
+                ("htol", C.c_double)]
+
+
+class KmoBgInfo(C.Structure):
+    _fields_ = [("lambda_", C.c_double), ("h_miss", C.c_double), ("shots", C.c_int),
+                ("steps", C.c_int)]
+
+
 class PoissonParams(C.Structure):
     _fields_ = [("s", C.c_double)]
 
@@ -131,6 +142,11 @@ def lib():
         L.mg_op_jt_apply.argtypes = [C.c_int, _P, C.c_int, C.c_double, _P, _P, _P, _P, _P,
                                      C.c_size_t, _P]
         L.mg_op_jt_apply.restype = st
+        L.mg_omega_radiation.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.mg_omega_radiation.restype = C.c_double
+        L.mg_kmo_background.argtypes = [C.POINTER(KmoBgParams), C.c_int, _P, _P, _P, _P, _P,
+                                        C.POINTER(KmoBgInfo)]
+        L.mg_kmo_background.restype = st
         L.mg_status_string.argtypes = [C.c_int]
         L.mg_status_string.restype = C.c_char_p
         L.mg_last_error.argtypes = []
@@ -194,6 +210,43 @@ def kmo_params(n_mesh, box_mpch, n_k=3, k0=1.0, beta=0.1, lam=None, a=1.0, omega
     if lam is None:
         lam = (3.0 * (1.0 - omega_m)) ** 0.5
     return KmoParams(n_k, k0, beta, lam, a, omega_m, box_mpch, phibar, dphibar_dtau_over_h0)
+
+
+H_PLANCK = 0.6774      # dimensionless Hubble constant paired with OMEGA_M
+
+
+def omega_radiation(h=H_PLANCK, t_cmb=2.7255, n_eff=3.046):
+    """Radiation density today: photons at t_cmb plus n_eff massless neutrinos."""
+    return lib().mg_omega_radiation(h, t_cmb, n_eff)
+
+
+def kmo_background(n_k, k0, beta, a, omega_m=OMEGA_M, omega_r=None, z_init=1e5, htol=1e-10):
+    """Kmouflage background (Sec. 3.2.5) at the scale factors a (increasing):
+    dict with lambda, hubble (H/H0), hubble_dot ((dH/dt)/H0^2), phibar and
+    dphibar_dtau ((d phibar/d tau)/H0).  Host computation in the library."""
+    import numpy as np
+    a = np.ascontiguousarray(np.atleast_1d(np.asarray(a, dtype=np.float64)))
+    if omega_r is None:
+        omega_r = omega_radiation()
+    par = KmoBgParams(n_k, k0, beta, omega_m, omega_r, z_init, htol)
+    out = {k: np.empty_like(a) for k in ("hubble", "hubble_dot", "phibar", "dphibar_dtau")}
+    info = KmoBgInfo()
+    ptr = lambda x: x.ctypes.data_as(C.c_void_p)
+    _raise(lib().mg_kmo_background(C.byref(par), a.size, ptr(a), ptr(out["hubble"]),
+                                   ptr(out["hubble_dot"]), ptr(out["phibar"]),
+                                   ptr(out["dphibar_dtau"]), C.byref(info)))
+    out.update(a=a, **{"lambda": info.lambda_, "h_miss": info.h_miss, "shots": info.shots,
+                       "steps": info.steps})
+    return out
+
+
+def kmo_params_from_background(n_mesh, box_mpch, n_k, k0, beta, a, omega_m=OMEGA_M,
+                               omega_r=None):
+    """mg_kmo_params at scale factor a with lambda, phibar and phibar' from the
+    background solver."""
+    bg = kmo_background(n_k, k0, beta, [a], omega_m, omega_r)
+    return KmoParams(n_k, k0, beta, bg["lambda"], a, omega_m, box_mpch, float(bg["phibar"][0]),
+                     float(bg["dphibar_dtau"][0]))
 
 
 def _solve(fn, par, model, delta, phi0, ws, **kw):

@@ -850,6 +850,10 @@ mg_status common_checks(const mg_opts *o, const void *delta, const void *phi, vo
 
 }  // namespace
 
+namespace mgglam_internal {
+void set_error(const char *msg) { g_err = msg; }
+}  // namespace mgglam_internal
+
 // ===================================================================== C ABI
 
 extern "C" {
