@@ -203,6 +203,28 @@ mg_status mg_pm_step(const mg_pm_params *par, float *pos, float *mom, double *ph
                      double *phi_newton, double *delta_out, void *ws, size_t ws_bytes,
                      hipStream_t stream, mg_stats *stats);
 
+/* One Kmouflage particle-mesh step (Sec. 3.2.4): CIC density, Newtonian
+ * potential with the rescaled mass, lap Phi_N = 1.5 A(phibar) Omega_m delta / a
+ * (eq:kmf_Poission_eqn_codeunit), the scalar field of eq:kmf_eqn_codeunit_final
+ * (warm start from phi), and eq:force_Kmo1/2: kick
+ * p <- (1 - beta (d phibar/da) da) p - (da / (a E(a))) grad(Phi_N + beta c~ phi)
+ * at a, drift x += da / (a_h^3 E(a_h)) p at a_h = a + da/2.  The background
+ * values (E at a and a_h, d phibar/da, and kmo.lambda / phibar /
+ * dphibar_dtau_over_h0 at a) come from mg_kmo_background.  Same arrays and
+ * workspace as mg_pm_step. */
+typedef struct {
+    int n_mesh, n_part;
+    double a, da;
+    mg_kmo_params kmo;   /* field parameters at a (kmo.a == a) */
+    double e_a;          /* H/H0 of the Kmouflage background at a */
+    double e_half;       /* H/H0 at a + da/2 */
+    double dphibar_da;   /* d phibar / d a at a */
+    mg_opts mg;          /* options of both field solves; mg.n must equal n_mesh */
+} mg_pm_kmo_params;
+mg_status mg_pm_step_kmouflage(const mg_pm_kmo_params *par, float *pos, float *mom, double *phi,
+                               double *phi_newton, double *delta_out, void *ws, size_t ws_bytes,
+                               hipStream_t stream, mg_stats *stats);
+
 /* CIC density contrast of n_part^3 unit-mass particles on an n_mesh^3
  * mesh (cell i has centre i + 1/2): delta = rho / rho_bar - 1.  Deterministic:
  * weights accumulate as 64-bit fixed point (2^-32 per unit mass).  ws needs

@@ -84,6 +84,8 @@ def lib():
                                  C.c_int, C.c_int, C.c_int, C.POINTER(Stats)]
         L.or_cic_deposit.argtypes = [C.c_int, C.c_long, _F, _D]
         L.or_kick_drift.argtypes = [C.c_int, C.c_long, _D, _F, _F, C.c_double, C.c_double]
+        L.or_kick_drift_damped.argtypes = [C.c_int, C.c_long, _D, _F, _F, C.c_double,
+                                           C.c_double, C.c_double]
         _lib = L
     return _lib
 
@@ -318,4 +320,43 @@ def pm_step(pos, mom, n_mesh: int, a: float, da: float, h0rc: float = 1.0,
     drift = da / (ah ** 3 * expansion_rate(ah, omega_m))
     lib().or_kick_drift(n_mesh, pos.shape[0], _c(psi), pos.reshape(-1), mom.reshape(-1), kick,
                         drift)
+    return pos, mom, res.phi, delta, phin
+
+
+def kmo_background_values(bg, a: float, da: float) -> dict:
+    """Background inputs of a Kmouflage PM step from an oracle background
+    (oracle.background.solve): E at a and a + da/2, phibar, phibar' and
+    d phibar/da at a."""
+    ah = a + 0.5 * da
+    one = lambda x: float(np.asarray(x).reshape(-1)[0])
+    e_a = one(bg.hubble(a))
+    dtau = one(bg.dphibar_dtau_over_h0(a))
+    return dict(lam=bg.lam, e_a=e_a, e_half=one(bg.hubble(ah)), phibar=one(bg.phibar(a)),
+                dphibar_dtau=dtau, dphibar_da=dtau / (a * a * e_a))
+
+
+def pm_step_kmouflage(pos, mom, n_mesh: int, a: float, da: float, box: float, nk: int,
+                      k0: float, beta: float, bgv: dict, omega_m: float = OMEGA_M, phi0=None,
+                      max_cycles: int = 50, tol: float = 1e-8):
+    """One Kmouflage particle-mesh step (Sec. 3.2.4): CIC density, Newtonian
+    potential with the rescaled mass 1.5 A(phibar) Omega_m delta / a by FFT
+    (eq:kmf_Poission_eqn_codeunit), the field of eq:kmf_eqn_codeunit_final by
+    multigrid, total potential Phi_N + beta c~ phi, and eq:force_Kmo1/2:
+    p <- (1 - beta dphibar/da da) p - da/(a E(a)) grad, then the drift with
+    da/(a_h^3 E(a_h)).  bgv: kmo_background_values.  Returns new (pos, mom,
+    phi, delta, Phi_N)."""
+    pos = np.ascontiguousarray(pos, dtype=np.float32).copy()
+    mom = np.ascontiguousarray(mom, dtype=np.float32).copy()
+    _, delta = cic_density(pos, n_mesh)
+    A = np.exp(beta * bgv["phibar"])
+    phin = fft_poisson(1.5 * A * omega_m / a * delta)
+    m = kmo_model(n_mesh, box, nk, k0, beta, bgv["lam"], a, omega_m, bgv["phibar"],
+                  bgv["dphibar_dtau"])
+    res = solve(m, delta, phi0, max_cycles=max_cycles, tol=tol)
+    ctil = n_mesh / box * 2997.92458
+    psi = phin + beta * ctil * res.phi
+    ah = a + 0.5 * da
+    damp = 1.0 - beta * bgv["dphibar_da"] * da
+    lib().or_kick_drift_damped(n_mesh, pos.shape[0], _c(psi), pos.reshape(-1), mom.reshape(-1),
+                               damp, da / (a * bgv["e_a"]), da / (ah ** 3 * bgv["e_half"]))
     return pos, mom, res.phi, delta, phin

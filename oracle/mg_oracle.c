@@ -914,8 +914,11 @@ void or_cic_deposit(int n, long npart, const float *pos, double *rho)
  * mesh: g = -grad psi by 3-point central differences at cell centres,
  * interpolated with the CIC weights (the scheme of Sec. 3.1), then
  * p += g * kick, x += p * drift (wrapped to [0, n)). */
-void or_kick_drift(int n, long npart, const double *psi, float *pos, float *mom,
-                   double kick, double drift)
+/* p <- damp p - kick grad(psi) (3-point differences at the 8 CIC cells,
+ * CIC-weighted), then x <- x + drift p, periodic.  damp = 1 for nDGP;
+ * 1 - beta (d phibar/da) da for the velocity term of eq:force_Kmo2. */
+void or_kick_drift_damped(int n, long npart, const double *psi, float *pos, float *mom,
+                          double damp, double kick, double drift)
 {
 #pragma omp parallel for schedule(static)
     for (long p = 0; p < npart; ++p) {
@@ -937,7 +940,7 @@ void or_kick_drift(int n, long npart, const double *psi, float *pos, float *mom,
                     g[2] -= wgt * (psi[IX(n, i, j, k + 1)] - psi[IX(n, i, j, k - 1)]) / 2.0;
                 }
         for (int a = 0; a < 3; ++a) {
-            double pn = (double)mom[3 * p + a] + g[a] * kick;
+            double pn = damp * (double)mom[3 * p + a] + g[a] * kick;
             double xn = (double)pos[3 * p + a] + pn * drift;
             xn = fmod(xn, (double)n);
             if (xn < 0.0) xn += n;
@@ -946,4 +949,10 @@ void or_kick_drift(int n, long npart, const double *psi, float *pos, float *mom,
             if (pos[3 * p + a] >= (float)n) pos[3 * p + a] = 0.0f;
         }
     }
+}
+
+void or_kick_drift(int n, long npart, const double *psi, float *pos, float *mom,
+                   double kick, double drift)
+{
+    or_kick_drift_damped(n, npart, psi, pos, mom, 1.0, kick, drift);
 }

@@ -97,6 +97,12 @@ class PmParams(C.Structure):
                 ("h0rc", C.c_double), ("a", C.c_double), ("da", C.c_double), ("mg", Opts)]
 
 
+class PmKmoParams(C.Structure):
+    _fields_ = [("n_mesh", C.c_int), ("n_part", C.c_int), ("a", C.c_double), ("da", C.c_double),
+                ("kmo", KmoParams), ("e_a", C.c_double), ("e_half", C.c_double),
+                ("dphibar_da", C.c_double), ("mg", Opts)]
+
+
 _lib = None
 _P = C.c_void_p
 
@@ -127,6 +133,9 @@ def lib():
         L.mg_pm_step.argtypes = [C.POINTER(PmParams), _P, _P, _P, _P, _P, _P, C.c_size_t, _P,
                                  C.POINTER(Stats)]
         L.mg_pm_step.restype = st
+        L.mg_pm_step_kmouflage.argtypes = [C.POINTER(PmKmoParams), _P, _P, _P, _P, _P, _P,
+                                           C.c_size_t, _P, C.POINTER(Stats)]
+        L.mg_pm_step_kmouflage.restype = st
         L.mg_cic_delta.argtypes = [C.c_int, C.c_int, _P, _P, _P, C.c_size_t, _P]
         L.mg_cic_delta.restype = st
         L.mg_op_residual.argtypes = [C.c_int, _P, C.c_int, C.c_double, _P, _P, _P, C.c_double,
@@ -355,6 +364,38 @@ def pm_step(pos, mom, phi, phi_newton, n_mesh, a, da, h0rc=1.0, omega_m=OMEGA_M,
     st = Stats()
     _raise(lib().mg_pm_step(C.byref(par), _ptr(pos), _ptr(mom), _ptr(phi), _ptr(phi_newton),
                             _ptr(delta), _ptr(ws), ws.numel(), _stream(), C.byref(st)))
+    return delta, st.as_dict()
+
+
+def kmo_pm_background(n_k, k0, beta, a, da, omega_m=OMEGA_M):
+    """Background inputs of a Kmouflage PM step from the library's background
+    solver: lambda, E at a and a + da/2, phibar, phibar' and d phibar/da at a."""
+    bg = kmo_background(n_k, k0, beta, [a, a + 0.5 * da], omega_m)
+    e_a = float(bg["hubble"][0])
+    dtau = float(bg["dphibar_dtau"][0])
+    return dict(lam=bg["lambda"], e_a=e_a, e_half=float(bg["hubble"][1]),
+                phibar=float(bg["phibar"][0]), dphibar_dtau=dtau, dphibar_da=dtau / (a * a * e_a))
+
+
+def pm_step_kmouflage(pos, mom, phi, phi_newton, n_mesh, a, da, box_mpch, n_k=2, k0=1.0,
+                      beta=0.2, omega_m=OMEGA_M, bgv=None, ws=None, **kw):
+    """One Kmouflage PM step in place on pos/mom (float32 [n^3,3]), phi and
+    phi_newton (float64 warm starts, updated); bgv: kmo_pm_background (computed
+    when None).  Returns (delta, stats)."""
+    if bgv is None:
+        bgv = kmo_pm_background(n_k, k0, beta, a, da, omega_m)
+    n_part = round(pos.shape[0] ** (1.0 / 3.0))
+    delta = torch.empty((n_mesh,) * 3, dtype=torch.float64, device=pos.device)
+    if ws is None:
+        ws = torch.empty(lib().mg_pm_workspace_bytes(n_mesh), dtype=torch.uint8, device=pos.device)
+    kmo = KmoParams(n_k, k0, beta, bgv["lam"], a, omega_m, box_mpch, bgv["phibar"],
+                    bgv["dphibar_dtau"])
+    par = PmKmoParams(n_mesh, n_part, a, da, kmo, bgv["e_a"], bgv["e_half"], bgv["dphibar_da"],
+                      make_opts(n_mesh, **kw))
+    st = Stats()
+    _raise(lib().mg_pm_step_kmouflage(C.byref(par), _ptr(pos), _ptr(mom), _ptr(phi),
+                                      _ptr(phi_newton), _ptr(delta), _ptr(ws), ws.numel(),
+                                      _stream(), C.byref(st)))
     return delta, st.as_dict()
 
 

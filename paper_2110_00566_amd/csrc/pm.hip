@@ -57,13 +57,15 @@ __global__ void k_zero_u64(unsigned long long *a, size_t n) {
     if (t < n) a[t] = 0ull;
 }
 
-// g = -grad(Phi_N + phi/2) by 3-point differences at the 8 CIC cells,
-// interpolated with the CIC weights; p += g*kick; x += p*drift (periodic).
+// g = -grad(Phi_N + cphi phi) by 3-point differences at the 8 CIC cells,
+// interpolated with the CIC weights; p = damp p + g kick; x += p drift
+// (periodic).  nDGP: cphi = 1/2, damp = 1; Kmouflage: cphi = beta c~ and
+// damp = 1 - beta (d phibar/da) da (the velocity term of eq:force_Kmo2).
 __global__ __launch_bounds__(PTPB) void k_kick_drift(float *__restrict__ pos,
                                                       float *__restrict__ mom, size_t np, int logn,
                                                       const double *__restrict__ phin,
-                                                      const double *__restrict__ phi, double kick,
-                                                      double drift) {
+                                                      const double *__restrict__ phi, double cphi,
+                                                      double damp, double kick, double drift) {
     const size_t t = (size_t)blockIdx.x * PTPB + threadIdx.x;
     if (t >= np) return;
     const int n = 1 << logn, nm1 = n - 1;
@@ -73,7 +75,7 @@ __global__ __launch_bounds__(PTPB) void k_kick_drift(float *__restrict__ pos,
     double g[3] = {0.0, 0.0, 0.0};
     auto psi = [&](int i, int j, int k) {
         const size_t idx = ((size_t)(k & nm1) << (2 * logn)) + ((size_t)(j & nm1) << logn) + (i & nm1);
-        return phin[idx] + 0.5 * phi[idx];
+        return phin[idx] + cphi * phi[idx];
     };
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -86,7 +88,7 @@ __global__ __launch_bounds__(PTPB) void k_kick_drift(float *__restrict__ pos,
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const double pn = (double)mom[3 * t + a] + g[a] * kick;
+        const double pn = damp * (double)mom[3 * t + a] + g[a] * kick;
         double xn = fmod((double)pos[3 * t + a] + pn * drift, (double)n);
         if (xn < 0.0) xn += n;
         float xf = (float)xn;
@@ -177,7 +179,53 @@ mg_status mg_pm_step(const mg_pm_params *par, float *pos, float *mom, double *ph
     const double kick = par->da / (a * E);
     const double drift = par->da / (ah * ah * ah * Eh);
     const size_t np = (size_t)par->n_part * par->n_part * par->n_part;
-    k_kick_drift<<<nb(np), PTPB, 0, stream>>>(pos, mom, np, ilog2(n), phi_newton, phi, kick, drift);
+    k_kick_drift<<<nb(np), PTPB, 0, stream>>>(pos, mom, np, ilog2(n), phi_newton, phi, 0.5, 1.0,
+                                              kick, drift);
+    if (hipGetLastError() != hipSuccess) return MG_ERR_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return MG_ERR_HIP;
+    if (pst.status == MG_NOT_CONVERGED && rc == MG_OK) rc = MG_NOT_CONVERGED;
+    return rc;
+}
+
+mg_status mg_pm_step_kmouflage(const mg_pm_kmo_params *par, float *pos, float *mom, double *phi,
+                               double *phi_newton, double *delta_out, void *ws, size_t ws_bytes,
+                               hipStream_t stream, mg_stats *stats) {
+    if (!par || !pos || !mom || !phi || !phi_newton || !delta_out || !stats) return MG_ERR_ARG;
+    const int n = par->n_mesh;
+    const mg_kmo_params &K = par->kmo;
+    if (!pow2(n) || n < 8 || n > 2048 || par->mg.n != n || par->n_part < 1 || par->n_part > 2048 ||
+        !(par->a > 0.0) || !std::isfinite(par->da) || K.a != par->a || !(par->e_a > 0.0) ||
+        !(par->e_half > 0.0) || !std::isfinite(par->dphibar_da) || !(K.box_mpch > 0.0) ||
+        !(K.omega_m > 0.0) || !(K.omega_m < 1.0))
+        return MG_ERR_ARG;
+    const size_t need = mg_pm_workspace_bytes(n);
+    if (!ws || ws_bytes < need) return MG_ERR_WORKSPACE;
+    const size_t ncell = (size_t)n * n * n;
+    unsigned long long *counts = (unsigned long long *)ws;
+    char *solver_ws = (char *)ws + align256(ncell * sizeof(unsigned long long));
+    const size_t solver_bytes = ws_bytes - align256(ncell * sizeof(unsigned long long));
+
+    mg_status rc = cic(n, par->n_part, pos, delta_out, counts, stream);
+    if (rc != MG_OK) return rc;
+    // Newtonian potential with the rescaled particle mass, eq:kmf_Poission_eqn_codeunit
+    const double A = std::exp(K.beta * K.phibar);
+    mg_poisson_params pp{1.5 * A * K.omega_m / par->a};
+    mg_stats pst;
+    rc = mg_solve_poisson(&par->mg, &pp, delta_out, phi_newton, solver_ws, solver_bytes, stream, &pst);
+    if (rc < 0) return rc;
+    // scalar field, eq:kmf_eqn_codeunit_final
+    rc = mg_solve_kmouflage(&par->mg, &K, delta_out, phi, solver_ws, solver_bytes, stream, stats);
+    if (rc < 0) return rc;
+    // eq:force_Kmo1/2: kick with H0/adot = 1/(a E(a)) and the velocity term
+    // at a, drift with H0/(a^2 adot) at a + da/2; E from the background
+    const double ctil = (double)n / K.box_mpch * 2997.92458;
+    const double a = par->a, ah = a + 0.5 * par->da;
+    const double kick = par->da / (a * par->e_a);
+    const double drift = par->da / (ah * ah * ah * par->e_half);
+    const double damp = 1.0 - K.beta * par->dphibar_da * par->da;
+    const size_t np = (size_t)par->n_part * par->n_part * par->n_part;
+    k_kick_drift<<<nb(np), PTPB, 0, stream>>>(pos, mom, np, ilog2(n), phi_newton, phi,
+                                              K.beta * ctil, damp, kick, drift);
     if (hipGetLastError() != hipSuccess) return MG_ERR_HIP;
     if (hipStreamSynchronize(stream) != hipSuccess) return MG_ERR_HIP;
     if (pst.status == MG_NOT_CONVERGED && rc == MG_OK) rc = MG_NOT_CONVERGED;
