@@ -370,11 +370,14 @@ def pm_step(pos, mom, phi, phi_newton, n_mesh, a, da, h0rc=1.0, omega_m=OMEGA_M,
 def kmo_pm_background(n_k, k0, beta, a, da, omega_m=OMEGA_M):
     """Background inputs of a Kmouflage PM step from the library's background
     solver: lambda, E at a and a + da/2, phibar, phibar' and d phibar/da at a."""
-    bg = kmo_background(n_k, k0, beta, [a, a + 0.5 * da], omega_m)
-    e_a = float(bg["hubble"][0])
-    dtau = float(bg["dphibar_dtau"][0])
-    return dict(lam=bg["lambda"], e_a=e_a, e_half=float(bg["hubble"][1]),
-                phibar=float(bg["phibar"][0]), dphibar_dtau=dtau, dphibar_da=dtau / (a * a * e_a))
+    ah = a + 0.5 * da
+    pts = sorted({a, ah})          # the table must increase strictly
+    bg = kmo_background(n_k, k0, beta, pts, omega_m)
+    ia, ih = pts.index(a), pts.index(ah)
+    e_a = float(bg["hubble"][ia])
+    dtau = float(bg["dphibar_dtau"][ia])
+    return dict(lam=bg["lambda"], e_a=e_a, e_half=float(bg["hubble"][ih]),
+                phibar=float(bg["phibar"][ia]), dphibar_dtau=dtau, dphibar_da=dtau / (a * a * e_a))
 
 
 def pm_step_kmouflage(pos, mom, phi, phi_newton, n_mesh, a, da, box_mpch, n_k=2, k0=1.0,
