@@ -140,6 +140,43 @@ def cycle_types(mg, L, C, delta, ws, par, phi_ref):
     return res
 
 
+def pm_steps(mg, pos0, dev, steps=3):
+    """Particle-mesh steps of both models on the bench workload (512^3 mesh,
+    256^3 particles, L = 512 Mpc/h) from a = 0.5, da = 0.01: CIC, Newtonian
+    potential, scalar field to 1e-8 (warm-started), kick and drift."""
+    import numpy as np
+    import torch
+    res = {}
+    for model in ("dgp", "kmouflage"):
+        pos = pos0.clone()
+        mom = torch.zeros_like(pos)
+        phi = torch.zeros((N_MESH,) * 3, dtype=torch.float64, device=dev)
+        phin = torch.zeros_like(phi)
+        ws = torch.empty(mg.lib().mg_pm_workspace_bytes(N_MESH), dtype=torch.uint8, device=dev)
+        a, da, times, cycles = 0.5, 0.01, [], []
+        for s in range(steps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if model == "dgp":
+                _, st = mg.pm_step(pos, mom, phi, phin, N_MESH, a, da, h0rc=H0RC, ws=ws, tol=TOL)
+            else:
+                _, st = mg.pm_step_kmouflage(pos, mom, phi, phin, N_MESH, a, da, BOX, 2, 1.0, 0.2,
+                                             ws=ws, tol=TOL)
+            torch.cuda.synchronize()
+            assert st["status"] >= 0
+            if s:
+                times.append(time.perf_counter() - t0)
+                cycles.append(st["cycles"])
+            a += da
+        res[model] = {"ms_per_step": 1e3 * float(np.mean(times)),
+                      "scalar_cycles_per_step": float(np.mean(cycles))}
+        del ws, phi, phin
+        torch.cuda.empty_cache()
+    res["config"] = "512^3 mesh, 256^3 particles, L=512 Mpc/h, a=0.5, da=0.01, tol=1e-8; " \
+                    "Kmouflage n=2, K0=1, beta=0.2 with its background"
+    return res
+
+
 def vcycle_1024(mg, L, C, dev):
     """FP64 V-cycle on a 1024^3 mesh: CIC of 512^3 Zel'dovich particles
     (L = 1 Gpc/h)."""
@@ -276,6 +313,7 @@ def main():
     del ws_mix, ws
     torch.cuda.empty_cache()
     out["vcycle_512"] = vcycle_time(mg, L, C, delta)
+    out["pm_steps"] = pm_steps(mg, pos, dev)
     if not args.no_big:
         out["vcycle_1024"] = vcycle_1024(mg, L, C, dev)
     if not args.no_cpu:

@@ -44,6 +44,77 @@ __global__ __launch_bounds__(PTPB) void k_cic(const float *__restrict__ pos, siz
     }
 }
 
+// Gather form of the same deposit (for n_part^3 <= n_mesh^3): every particle
+// is linked into the list of its lower CIC corner cell (one 32-bit atomic
+// exchange per particle instead of eight 64-bit adds), then every cell sums
+// the fixed-point weights of the particles in the 8 lists whose clouds reach
+// it.  Integer sums are exact in any order, so delta is bit-identical to the
+// scatter form whatever order the lists are built in.
+__global__ __launch_bounds__(PTPB) void k_cic_link(const float *__restrict__ pos, int np, int logn,
+                                                    int *__restrict__ head, int *__restrict__ next) {
+    const int t = blockIdx.x * PTPB + threadIdx.x;
+    if (t >= np) return;
+    const int nm1 = (1 << logn) - 1;
+    double f[3];
+    int i0[3];
+    cic_weights(pos + 3 * (size_t)t, f, i0);
+    const size_t c = ((size_t)(i0[2] & nm1) << (2 * logn)) + ((size_t)(i0[1] & nm1) << logn) +
+                     (size_t)(i0[0] & nm1);
+    next[t] = atomicExch(head + c, t);
+}
+
+// A block owns a tile of CGX x CGY x CGZ cells and walks, once, the lists
+// of every corner cell whose particles reach the tile (the tile and one cell
+// below it in each axis), adding the fixed-point weights that land inside
+// the tile into LDS; then it writes the tile's delta.
+constexpr int CGX = 32, CGY = 4, CGZ = 4;
+constexpr int CG_CELLS = CGX * CGY * CGZ;                      // 512
+constexpr int CG_LISTS = (CGX + 1) * (CGY + 1) * (CGZ + 1);    // 825
+
+__global__ __launch_bounds__(PTPB) void k_cic_gather(const float *__restrict__ pos, int logn,
+                                                      const int *__restrict__ head,
+                                                      const int *__restrict__ next, double scale,
+                                                      double *__restrict__ delta) {
+    __shared__ unsigned long long acc[CG_CELLS];
+    const int nm1 = (1 << logn) - 1;
+    const int ntx = (1 << logn) / CGX, nty = (1 << logn) / CGY;
+    const int bx = blockIdx.x % ntx, by = (blockIdx.x / ntx) % nty, bz = blockIdx.x / (ntx * nty);
+    const int x0 = bx * CGX, y0 = by * CGY, z0 = bz * CGZ;
+    for (int q = threadIdx.x; q < CG_CELLS; q += PTPB) acc[q] = 0ull;
+    __syncthreads();
+    for (int q = threadIdx.x; q < CG_LISTS; q += PTPB) {
+        const int lx = q % (CGX + 1) - 1, ly = (q / (CGX + 1)) % (CGY + 1) - 1,
+                  lz = q / ((CGX + 1) * (CGY + 1)) - 1;   // corner in tile coordinates
+        const size_t L = ((size_t)((z0 + lz) & nm1) << (2 * logn)) +
+                         ((size_t)((y0 + ly) & nm1) << logn) + (size_t)((x0 + lx) & nm1);
+        for (int p = head[L]; p >= 0; p = next[p]) {
+            double f[3];
+            int i0[3];
+            cic_weights(pos + 3 * (size_t)p, f, i0);
+#pragma unroll
+            for (int o = 0; o < 8; ++o) {
+                const int a = o & 1, b = (o >> 1) & 1, c = o >> 2;
+                const int tx = lx + a, ty = ly + b, tz = lz + c;
+                if (tx < 0 || tx >= CGX || ty < 0 || ty >= CGY || tz < 0 || tz >= CGZ) continue;
+                const double w =
+                    ((a ? f[0] : 1.0 - f[0]) * (b ? f[1] : 1.0 - f[1])) * (c ? f[2] : 1.0 - f[2]);
+                atomicAdd(acc + (tz * CGY + ty) * CGX + tx, __double2ull_rn(w * FIX_SCALE));
+            }
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < CG_CELLS; q += PTPB) {
+        const int tx = q % CGX, ty = (q / CGX) % CGY, tz = q / (CGX * CGY);
+        const size_t t = ((size_t)(z0 + tz) << (2 * logn)) + ((size_t)(y0 + ty) << logn) + (x0 + tx);
+        delta[t] = (double)acc[q] * scale - 1.0;
+    }
+}
+
+__global__ void k_fill_i32(int *a, size_t n, int v) {
+    const size_t t = (size_t)blockIdx.x * PTPB + threadIdx.x;
+    if (t < n) a[t] = v;
+}
+
 __global__ __launch_bounds__(PTPB) void k_counts_to_delta(const unsigned long long *counts,
                                                            size_t ncell, double scale,
                                                            double *delta) {
@@ -107,14 +178,25 @@ int ilog2(int n) {
     return l;
 }
 
+// counts: workspace of ncell 64-bit words
 mg_status cic(int n_mesh, int n_part, const float *pos, double *delta, unsigned long long *counts,
               hipStream_t s) {
     const size_t ncell = (size_t)n_mesh * n_mesh * n_mesh;
     const size_t np = (size_t)n_part * n_part * n_part;
     const int logn = ilog2(n_mesh);
+    const double scale = (1.0 / FIX_SCALE) * ((double)ncell / (double)np);
+    if (np <= ncell && np < ((size_t)1 << 31) && n_mesh >= CGX) {
+        // gather form: heads and links fit in the ncell 64-bit words
+        int *head = reinterpret_cast<int *>(counts);
+        int *next = head + ncell;
+        k_fill_i32<<<nb(ncell), PTPB, 0, s>>>(head, ncell, -1);
+        k_cic_link<<<nb(np), PTPB, 0, s>>>(pos, (int)np, logn, head, next);
+        k_cic_gather<<<(unsigned)(ncell / CG_CELLS), PTPB, 0, s>>>(pos, logn, head, next, scale,
+                                                                  delta);
+        return hipGetLastError() == hipSuccess ? MG_OK : MG_ERR_HIP;
+    }
     k_zero_u64<<<nb(ncell), PTPB, 0, s>>>(counts, ncell);
     k_cic<<<nb(np), PTPB, 0, s>>>(pos, np, logn, counts);
-    const double scale = (1.0 / FIX_SCALE) * ((double)ncell / (double)np);
     k_counts_to_delta<<<nb(ncell), PTPB, 0, s>>>(counts, ncell, scale, delta);
     return hipGetLastError() == hipSuccess ? MG_OK : MG_ERR_HIP;
 }
