@@ -43,7 +43,12 @@ typedef enum {
 } mg_status;
 
 typedef enum { MG_FP64 = 0, MG_MIXED = 1 } mg_precision;
-typedef enum { MG_MODEL_DGP = 0, MG_MODEL_KMOUFLAGE = 1, MG_MODEL_POISSON = 2 } mg_model;
+typedef enum {
+    MG_MODEL_DGP = 0,
+    MG_MODEL_KMOUFLAGE = 1,
+    MG_MODEL_POISSON = 2,
+    MG_MODEL_DGP_NEWTON = 3   /* comparator: see mg_solve_dgp_newton (single ops and sizing) */
+} mg_model;
 
 /* Multigrid cycle arrangements of Sec. 3.2.1 (fig:multigrid_cycles), as the
  * textbook recursions: V = one coarse cycle per level, W = two coarse
@@ -161,6 +166,20 @@ size_t mg_workspace_bytes(int n, int precision, int model, int adjoint);
 mg_status mg_solve_dgp(const mg_opts *opts, const mg_dgp_params *par, const double *delta,
                        double *phi, void *ws, size_t ws_bytes, hipStream_t stream,
                        mg_stats *stats);
+
+/* Comparator for the closed-form relaxation: the same nDGP problem written in
+ * its quadratic form eq:dgp_quadratic_eom (divided by alpha),
+ *   L_N = D + 2 D^2 / (3 alpha) - Sigma / alpha = 0,  D = 7-point Laplacian
+ * (centre included), smoothed by the generic Newton-Gauss-Seidel step of
+ * eq:relaxation_iteration, u <- u - (L_N - f) / (dL_N/du), with
+ * dL_N/du = -(6/h^2)(1 + 4 D / (3 alpha)) -- the iteration Sec. 3.2.3
+ * replaces.  Same FAS cycles, transfers, bordering and gauge as mg_solve_dgp;
+ * stats.eps is the RMS of the mean-projected L_N residual (equal to the
+ * mg_solve_dgp residual to first order in Sigma/alpha^2).  FP64 only, untiled
+ * kernels at every level; same arguments as mg_solve_dgp. */
+mg_status mg_solve_dgp_newton(const mg_opts *opts, const mg_dgp_params *par, const double *delta,
+                              double *phi, void *ws, size_t ws_bytes, hipStream_t stream,
+                              mg_stats *stats);
 
 /* Solve the Kmouflage equation in the split form eq:kmf_eqn_codeunit_final:
  * c~ lap(phi) = (3 beta A Omega_m delta / a + Sigma_2) / Sigma_1.

@@ -61,6 +61,7 @@ def lib():
         L.or_kmo_setup.argtypes = [C.c_int, C.c_double, C.c_int, C.c_double, C.c_double,
                                    C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, _MP]
         L.or_linear_setup.argtypes = [C.c_double, _MP]
+        L.or_dgp_newton_setup.argtypes = [C.c_double, C.c_double, C.c_double, _MP]
         L.or_op_cell.argtypes = [_MP, _D, _D, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int]
         L.or_op_cell.restype = C.c_double
         L.or_residual.argtypes = [_MP, _D, _D, C.c_void_p, C.c_double, C.c_int, C.c_double, _D,
@@ -114,6 +115,13 @@ def kmo_model(n_mesh: int, box: float, nk: int = 3, k0: float = 1.0, beta: float
     m = Model()
     lib().or_kmo_setup(n_mesh, box, nk, k0, beta, lam, a, omega_m, phibar, dphibar_over_h0,
                        C.byref(m))
+    return m
+
+
+def dgp_newton_model(a: float = 1.0, omega_m: float = OMEGA_M, h0rc: float = 1.0) -> Model:
+    """Comparator: the nDGP quadratic form relaxed by Newton-Gauss-Seidel."""
+    m = Model()
+    lib().or_dgp_newton_setup(a, omega_m, h0rc, C.byref(m))
     return m
 
 

@@ -105,6 +105,16 @@ void or_kmo_setup(int n_mesh, double box_mpch, int nk, double k0, double beta,
     m->src = 3.0 * beta * exp(beta * phibar) * omega_m / a;
 }
 
+/* Comparator: the nDGP problem in the quadratic form eq:dgp_quadratic_eom,
+ * divided by alpha, relaxed by the generic Newton-Gauss-Seidel step of
+ * eq:relaxation_iteration (model 3): L = lap(phi) - K with
+ * K = Sigma/alpha - 2 (lap phi)^2 / (3 alpha), which depends on the centre. */
+void or_dgp_newton_setup(double a, double omega_m, double h0rc, or_model *m)
+{
+    or_dgp_setup(a, omega_m, h0rc, m, NULL);
+    m->model = 3;
+}
+
 void or_linear_setup(double s, or_model *m)
 {
     memset(m, 0, sizeof(*m));
@@ -141,7 +151,7 @@ static double model_term(const or_model *m, const double *phi, const double *del
     double h4 = h * h * h * h;
     if (m->model == 2)
         return m->s * d;
-    if (m->model == 0) {
+    if (m->model == 0 || m->model == 3) {
         /* Sigma_ijk exactly as printed (Sec. 3.2.3) */
         double dxx = xp + xm - 2.0 * c;
         double dyy = yp + ym - 2.0 * c;
@@ -160,6 +170,10 @@ static double model_term(const or_model *m, const double *phi, const double *del
                      + 1.0 / (8.0 * h4) * nxz * nxz
                      + 1.0 / (8.0 * h4) * nyz * nyz
                      + m->s * d;
+        if (m->model == 3) {
+            double D = (xp + xm + yp + ym + zp + zm - 6.0 * c) / (h * h);
+            return sigma / m->alpha - 2.0 * D * D / (3.0 * m->alpha);
+        }
         double disc = m->alpha * m->alpha + 8.0 / 3.0 * sigma;
         if (disc < 0.0) {
             disc = 0.0;
@@ -240,9 +254,12 @@ void or_colour_pass(const or_model *m, const double *phi_in, const double *delta
             for (int i = 0; i < n; ++i) {
                 if (((i + j + k) & 1) != colour) continue;
                 long c = IX(n, i, j, k);
-                double L = lap(phi_in, n, h, i, j, k)
-                         - model_term(m, phi_in, delta, n, h, i, j, k, &nc);
+                double D = lap(phi_in, n, h, i, j, k);
+                double L = D - model_term(m, phi_in, delta, n, h, i, j, k, &nc);
+                /* dL/dphi at the cell: the closed-form models do not depend on
+                 * the centre through K; the quadratic form does through D */
                 double dLdphi = -6.0 / (h * h);
+                if (m->model == 3) dLdphi *= 1.0 + 4.0 * D / (3.0 * m->alpha);
                 phi_out[c] = phi_in[c] - (L - (f ? f[c] : fs)) / dLdphi;
             }
     if (nclamp) *nclamp += nc;

@@ -31,7 +31,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "mgglam.h")
 
 MG_OK, MG_NOT_CONVERGED, MG_WARN_CLAMPED = 0, 1, 2
 MG_ERR_ARG, MG_ERR_HIP, MG_ERR_NONFINITE, MG_ERR_DIVERGED, MG_ERR_WORKSPACE = -1, -2, -3, -4, -5
-MODEL_DGP, MODEL_KMOUFLAGE, MODEL_POISSON = 0, 1, 2
+MODEL_DGP, MODEL_KMOUFLAGE, MODEL_POISSON, MODEL_DGP_NEWTON = 0, 1, 2, 3
 CYCLE_V, CYCLE_F, CYCLE_W = 0, 1, 2
 OMEGA_M = 0.3089
 HIST = 64
@@ -122,7 +122,7 @@ def lib():
         L.mg_op_workspace_bytes.argtypes = [C.c_int]
         L.mg_op_workspace_bytes.restype = C.c_size_t
         for name, par in (("mg_solve_dgp", DgpParams), ("mg_solve_kmouflage", KmoParams),
-                          ("mg_solve_poisson", PoissonParams)):
+                          ("mg_solve_poisson", PoissonParams), ("mg_solve_dgp_newton", DgpParams)):
             f = getattr(L, name)
             f.argtypes = [C.POINTER(Opts), C.POINTER(par), _P, _P, _P, C.c_size_t, _P,
                           C.POINTER(Stats)]
@@ -277,6 +277,13 @@ def solve_dgp(delta, phi0=None, a=1.0, omega_m=OMEGA_M, h0rc=1.0, ws=None, **kw)
     Keywords: tol, max_cycles, nu_pre, nu_post, nu_coarse, profile,
     precision (MG_FP64 or MG_MIXED), cycle (CYCLE_V, CYCLE_F or CYCLE_W)."""
     return _solve(lib().mg_solve_dgp, dgp_params(a, omega_m, h0rc), MODEL_DGP, delta, phi0, ws, **kw)
+
+
+def solve_dgp_newton(delta, phi0=None, a=1.0, omega_m=OMEGA_M, h0rc=1.0, ws=None, **kw):
+    """Comparator: the nDGP problem in its quadratic form relaxed by
+    Newton-Gauss-Seidel (see mg_solve_dgp_newton); returns (phi, stats)."""
+    return _solve(lib().mg_solve_dgp_newton, dgp_params(a, omega_m, h0rc), MODEL_DGP_NEWTON, delta,
+                  phi0, ws, **kw)
 
 
 def solve_kmouflage(delta, phi0=None, box_mpch=512.0, n_k=3, k0=1.0, beta=0.1, lam=None, a=1.0,

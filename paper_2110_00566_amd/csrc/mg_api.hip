@@ -194,6 +194,9 @@ unsigned nblocks(size_t threads) { return (unsigned)((threads + TPB - 1) / TPB);
 
 bool tiled_level(int n) { return n >= 128; }
 
+// The tiled kernels implement the closed-form update only.
+constexpr bool tiled_op(int OP) { return OP != OP_ADJ && OP != OP_NEWTON; }
+
 // z-planes per block so that a launch has ~4096 blocks (at least 4 planes).
 TileGeom tile_geom(int n, int planes) {
     TileGeom G;
@@ -216,7 +219,7 @@ constexpr int fwd_op(int OP) { return OP == OP_ADJ ? OP_DGP : OP; }
 template <int OP, typename R>
 void launch_pass(const Mod &M, const LvlT<R> &L, const Coefs &Cf, int c, R *out, const double *fptr,
                  double fs, unsigned long long *clamp, hipStream_t st) {
-    if (OP != OP_ADJ && tiled_level(L.n)) {
+    if (tiled_op(OP) && tiled_level(L.n)) {
         const TileGeom G = tile_geom(L.n, L.n);
         k_pass_tiled<fwd_op(OP), R><<<tile_blocks(G, L.n), TPB, 0, st>>>(M, L, c, out, fptr, fs,
                                                                          clamp, G);
@@ -230,7 +233,7 @@ template <int OP, bool REDUCE, typename R>
 unsigned launch_resid_restrict(const Mod &M, const LvlT<R> &L, const Coefs &Cf, const double *fptr,
                                double fs, R *ru0, R *ru1, R *rd0, R *rd1, double *partials,
                                unsigned long long *clamp, hipStream_t st) {
-    if (OP != OP_ADJ && tiled_level(L.n)) {
+    if (tiled_op(OP) && tiled_level(L.n)) {
         const TileGeom G = tile_geom(L.n, L.n / 2);
         const unsigned nb = tile_blocks(G, L.n / 2);
         if (L.f0)
@@ -395,7 +398,7 @@ struct Solver {
         L.u0 = Hc.ru[0];
         L.u1 = Hc.ru[1];
         const double *shift = (lc == 1 && OP != OP_ADJ) ? C.scal + S_SHIFT : nullptr;
-        if (OP != OP_ADJ && tiled_level(Hc.n)) {
+        if (tiled_op(OP) && tiled_level(Hc.n)) {
             const TileGeom G = tile_geom(Hc.n, Hc.n);
             k_coarse_source_tiled<fwd_op(OP), R><<<tile_blocks(G, Hc.n), TPB, 0, C.st>>>(
                 C.M, L, Hc.f[0], Hc.f[1], Hc.u[0], Hc.u[1], shift, G);
@@ -412,7 +415,7 @@ struct Solver {
 
     // prolongation fused with the colour-0 pass of the first post-sweep
     bool fused_prolong(int l) const {
-        return OP != OP_ADJ && C.nu2 >= 1 && Hh.lv[l].spare2 && tiled_level(Hh.lv[l].n);
+        return tiled_op(OP) && C.nu2 >= 1 && Hh.lv[l].spare2 && tiled_level(Hh.lv[l].n);
     }
     void prolong_pass0(int l) {
         HLevel<R> &H = Hh.lv[l], &Hc = Hh.lv[l + 1];
@@ -826,7 +829,8 @@ void pack_f(OpWs &W, const double *f, double fs, hipStream_t s) {
 
 bool model_mod(int model, const void *params, int n, Mod &M) {
     if (!params) return false;
-    if (model == MG_MODEL_DGP) return setup_dgp((const mg_dgp_params *)params, M);
+    if (model == MG_MODEL_DGP || model == MG_MODEL_DGP_NEWTON)
+        return setup_dgp((const mg_dgp_params *)params, M);
     if (model == MG_MODEL_KMOUFLAGE) return setup_kmo((const mg_kmo_params *)params, n, M);
     if (model == MG_MODEL_POISSON) {
         M = Mod{};
@@ -859,7 +863,8 @@ void set_error(const char *msg) { g_err = msg; }
 extern "C" {
 
 size_t mg_workspace_bytes(int n, int precision, int model, int adjoint) {
-    if (!is_pow2(n) || n < 8 || n > 2048 || model < 0 || model > 2) return 0;
+    if (!is_pow2(n) || n < 8 || n > 2048 || model < 0 || model > 3) return 0;
+    if (model == MG_MODEL_DGP_NEWTON && (adjoint || precision != MG_FP64)) return 0;
     if (precision != MG_FP64 && precision != MG_MIXED) return 0;
     if (adjoint && precision != MG_FP64) return 0;
     Ctx C;
@@ -876,6 +881,17 @@ mg_status mg_solve_dgp(const mg_opts *opts, const mg_dgp_params *par, const doub
     Mod M;
     if (!par || !setup_dgp(par, M)) return fail(MG_ERR_ARG, "invalid nDGP parameters");
     return forward_solve<OP_DGP>(opts, M, delta, phi, ws, ws_bytes, stream, stats);
+}
+
+mg_status mg_solve_dgp_newton(const mg_opts *opts, const mg_dgp_params *par, const double *delta,
+                              double *phi, void *ws, size_t ws_bytes, hipStream_t stream,
+                              mg_stats *stats) {
+    mg_status rc = common_checks(opts, delta, phi, ws, stats);
+    if (rc != MG_OK) return rc;
+    if (opts->precision != MG_FP64) return fail(MG_ERR_ARG, "the Newton-GS comparator is FP64 only");
+    Mod M;
+    if (!par || !setup_dgp(par, M)) return fail(MG_ERR_ARG, "invalid nDGP parameters");
+    return forward_solve<OP_NEWTON>(opts, M, delta, phi, ws, ws_bytes, stream, stats);
 }
 
 mg_status mg_solve_kmouflage(const mg_opts *opts, const mg_kmo_params *par, const double *delta,
@@ -907,6 +923,7 @@ mg_status mg_solve_adjoint(const mg_opts *opts, int model, const void *params,
     if (rc != MG_OK) return rc;
     if (opts->precision != MG_FP64) return fail(MG_ERR_ARG, "the adjoint solve is FP64 only");
     if (opts->cycle != MG_CYCLE_V) return fail(MG_ERR_ARG, "the adjoint solve uses V-cycles only");
+    if (model == MG_MODEL_DGP_NEWTON) return fail(MG_ERR_ARG, "no adjoint for the Newton-GS comparator");
     if (!w || !grad_delta || !mu) return fail(MG_ERR_ARG, "w, grad_delta and mu must be device pointers");
     Mod M;
     if (!model_mod(model, params, opts->n, M)) return fail(MG_ERR_ARG, "invalid model or parameters");
@@ -941,6 +958,7 @@ mg_status mg_op_residual(int model, const void *params, int n, double h, const d
     pack_f(W, f, fs, stream);
     switch (model) {
         case MG_MODEL_DGP: op_residual_launch<OP_DGP>(M, W, stream, true); break;
+        case MG_MODEL_DGP_NEWTON: op_residual_launch<OP_NEWTON>(M, W, stream, true); break;
         case MG_MODEL_KMOUFLAGE: op_residual_launch<OP_KMO>(M, W, stream, true); break;
         default: op_residual_launch<OP_POISSON>(M, W, stream, true); break;
     }
@@ -968,6 +986,7 @@ mg_status mg_op_colour_pass(int model, const void *params, int n, double h, int 
     pack_f(W, f, fs, stream);
     switch (model) {
         case MG_MODEL_DGP: op_pass_launch<OP_DGP>(M, W, colour, stream); break;
+        case MG_MODEL_DGP_NEWTON: op_pass_launch<OP_NEWTON>(M, W, colour, stream); break;
         case MG_MODEL_KMOUFLAGE: op_pass_launch<OP_KMO>(M, W, colour, stream); break;
         default: op_pass_launch<OP_POISSON>(M, W, colour, stream); break;
     }

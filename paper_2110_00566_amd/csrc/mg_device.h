@@ -99,6 +99,18 @@ __device__ __forceinline__ NbT<T> load_nb(const R *__restrict__ A, const R *__re
 // costs an absolute error of about one ulp of alpha (~1e-15 here), far below
 // any residual tolerance, and saves the division of the cancellation-free
 // 2 Sigma / (alpha + sign(alpha) sqrt(D)).  D < 0 is clamped to 0 (K = -3 alpha/4).
+// Sigma / alpha of the nDGP operator at one cell (no centre dependence).
+template <typename T, typename L_>
+__device__ __forceinline__ T dgp_sigma_over_alpha(const Mod &M, const L_ &L, const NbT<T> &s,
+                                                  T delta) {
+    const T ax = s.xp + s.xm, ay = s.yp + s.ym, az = s.zp + s.zm;
+    const T dxy = ax - ay, dxz = ax - az, dyz = ay - az;
+    const T t3 = dxy * dxy + dxz * dxz + dyz * dyz;
+    const T t8 = s.nxy * s.nxy + s.nxz * s.nxz + s.nyz * s.nyz;
+    const double sig = (double)t3 * L.c3h4 + (double)t8 * L.c8h4 + M.s * (double)delta;
+    return (T)(sig / M.alpha);
+}
+
 template <int MODEL, typename T, typename L_>
 __device__ __forceinline__ T model_term(const Mod &M, const L_ &L, const NbT<T> &s, T delta,
                                         unsigned long long *clamp) {

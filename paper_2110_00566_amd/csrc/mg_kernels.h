@@ -20,7 +20,27 @@ enum {
     S_NSCAL = 16
 };
 
-enum { OP_DGP = MODEL_DGP, OP_KMO = MODEL_KMO, OP_POISSON = MODEL_POISSON, OP_ADJ = 3 };
+enum { OP_DGP = MODEL_DGP, OP_KMO = MODEL_KMO, OP_POISSON = MODEL_POISSON, OP_ADJ = 3,
+       OP_NEWTON = 4 };
+
+// OP_NEWTON: the nDGP equation in its quadratic form eq:dgp_quadratic_eom,
+// divided by alpha, L_N = D + 2 D^2 / (3 alpha) - Sigma / alpha with D the
+// 7-point Laplacian (centre included), relaxed by the generic Newton-Gauss-
+// Seidel step of eq:relaxation_iteration,
+//   u <- u - (L_N - f) / (dL_N/du),  dL_N/du = -(6/h^2)(1 + 4 D / (3 alpha)).
+// A comparator for the closed-form update: same fixed point on the physical
+// branch.  cell_term returns Sigma / alpha; newton_term adds the D part.
+template <typename T>
+__device__ __forceinline__ T newton_term(const Mod &M, T sigma_over_alpha, T D) {
+    return sigma_over_alpha - (T)(2.0 / (3.0 * M.alpha)) * D * D;
+}
+template <typename T>
+__device__ __forceinline__ T newton_update(const Mod &M, T u, T faces, T sig, T f, T h2) {
+    const T D = (faces - (T)6 * u) / h2;
+    const T r = D - newton_term<T>(M, sig, D) - f;
+    const T dL = -((T)6 / h2) * ((T)1 + (T)(4.0 / (3.0 * M.alpha)) * D);
+    return u - r / dL;
+}
 
 // Blocks are dispatched round-robin over the 8 XCDs; hand XCD x the x-th
 // contiguous eighth of the logical tiles.
@@ -44,7 +64,14 @@ __device__ __forceinline__ T cell_term(const Mod &M, const LvlT<R> &L, const Coe
                                        int m, int j, int k, T &faces, unsigned long long *clamp) {
     const R *A = c ? L.u1 : L.u0;
     const R *B = c ? L.u0 : L.u1;
-    if (OP != OP_ADJ) {
+    if (OP == OP_NEWTON) {
+        const NbT<T> s = load_nb<T, R>(A, B, c, m, j, k, L.n, L.logn, L.lognh);
+        faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
+        const R *D = c ? L.d1 : L.d0;
+        const T delta = (T)D[prow(j, k, L.logn, L.lognh) + m];
+        (void)clamp;
+        return dgp_sigma_over_alpha<T>(M, L, s, delta);
+    } else if (OP != OP_ADJ) {
         const NbT<T> s = load_nb<T, R>(A, B, c, m, j, k, L.n, L.logn, L.lognh);
         faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
         const R *D = c ? L.d1 : L.d0;
@@ -110,7 +137,10 @@ __global__ __launch_bounds__(TPB) void k_pass(Mod M, LvlT<R> L, Coefs Cf, int c,
     R faces;
     const R K = cell_term<OP, R, R>(M, L, Cf, c, m, j, k, faces, clamp);
     const R f = rhs_at<R, R>(L, c, t, fptr, fscale);
-    out[t] = (faces - (R)L.h2 * (K + f)) * (R)(1.0 / 6.0);
+    if constexpr (OP == OP_NEWTON)
+        out[t] = newton_update<R>(M, (c ? L.u1 : L.u0)[t], faces, K, f, (R)L.h2);
+    else
+        out[t] = (faces - (R)L.h2 * (K + f)) * (R)(1.0 / 6.0);
 }
 
 // Deterministic block sum of two values into partials[2*blk .. 2*blk+1].
@@ -160,9 +190,10 @@ __device__ __forceinline__ void dev_resid_restrict(const Mod &M, const LvlT<R> &
             const int j = 2 * J + b, k = 2 * K + cc;
             const int col = (a + b + cc) & 1;
             double faces;
-            const double term = cell_term<OP, double, R>(M, L, Cf, col, I, j, k, faces, clamp);
+            double term = cell_term<OP, double, R>(M, L, Cf, col, I, j, k, faces, clamp);
             const size_t idx = prow(j, k, L.logn, L.lognh) + I;
             const double u = (double)(col ? L.u1 : L.u0)[idx];
+            if constexpr (OP == OP_NEWTON) term = newton_term(M, term, (faces - 6.0 * u) * inv_h2);
             const double d = (faces - 6.0 * u) * inv_h2 - term
                            - rhs_at<double, R>(L, col, idx, fptr, fscale);
             sd += d;
@@ -205,8 +236,9 @@ __device__ __forceinline__ void dev_coarse_source(const Mod &M, const LvlT<R> &L
     const int j = (int)((tt >> Lc.lognh) & (Lc.n - 1));
     const int k = (int)(tt >> (Lc.lognh + Lc.logn));
     double faces;
-    const double term = cell_term<OP, double, R>(M, Lc, Cf, c, m, j, k, faces, nullptr);
+    double term = cell_term<OP, double, R>(M, Lc, Cf, c, m, j, k, faces, nullptr);
     const R ru = (c ? Lc.u1 : Lc.u0)[tt];
+    if constexpr (OP == OP_NEWTON) term = newton_term(M, term, (faces - 6.0 * (double)ru) / Lc.h2);
     R *S = c ? s1 : s0;
     const double rd = (double)S[tt] - (shift ? *shift : 0.0);
     S[tt] = (R)((faces - 6.0 * (double)ru) / Lc.h2 - term - rd);
@@ -403,8 +435,9 @@ __global__ __launch_bounds__(TPB) void k_residual(Mod M, Lvl L, Coefs Cf, const 
     const int j = (int)((tt >> L.lognh) & (L.n - 1));
     const int k = (int)(tt >> (L.lognh + L.logn));
     double faces;
-    const double term = cell_term<OP, double, double>(M, L, Cf, c, m, j, k, faces, clamp);
+    double term = cell_term<OP, double, double>(M, L, Cf, c, m, j, k, faces, clamp);
     const double u = (c ? L.u1 : L.u0)[tt];
+    if constexpr (OP == OP_NEWTON) term = newton_term(M, term, (faces - 6.0 * u) / L.h2);
     (c ? r1 : r0)[tt] = (faces - 6.0 * u) / L.h2 - term
                       - rhs_at<double, double>(L, c, tt, fptr, fscale);
 }
@@ -447,7 +480,11 @@ __device__ void tail_pass(const Mod &M, const TailLv<R> &T, const Coefs &Cf, int
             const int k = t >> (L.lognh + L.logn);
             R faces;
             const R K = cell_term<OP, R, R>(M, L, Cf, c, m, j, k, faces, nullptr);
-            nv[q] = (faces - (R)L.h2 * (K + (c ? L.f1 : L.f0)[t])) * (R)(1.0 / 6.0);
+            const R f = (c ? L.f1 : L.f0)[t];
+            if constexpr (OP == OP_NEWTON)
+                nv[q] = newton_update<R>(M, (c ? L.u1 : L.u0)[t], faces, K, f, (R)L.h2);
+            else
+                nv[q] = (faces - (R)L.h2 * (K + f)) * (R)(1.0 / 6.0);
         }
     }
     __syncthreads();

@@ -82,3 +82,53 @@ def test_f_and_w_contract_faster_per_cycle():
          for c in (oracle.CYCLE_V, oracle.CYCLE_F, oracle.CYCLE_W)}
     assert h[oracle.CYCLE_F][2] < h[oracle.CYCLE_V][2]
     assert h[oracle.CYCLE_W][2] < h[oracle.CYCLE_V][2]
+
+
+# ------------------------------------------- Newton-Gauss-Seidel comparator
+# The nDGP equation in its quadratic form eq:dgp_eom_code, relaxed by the
+# generic Newton step of eq:relaxation_iteration (the iteration the closed
+# form of Sec. 3.2.3 replaces).
+
+
+def test_newton_operator_is_the_printed_equation():
+    # L_N = lap + [(lap)^2 - H:H] / alpha - s delta / alpha with the full
+    # discrete Hessian H, evaluated independently with NumPy
+    from oracle import pins
+    n, h = 16, 2.0
+    phi = 3.0 * inputs.gaussian_field(n, 4, lambda k: k ** -3.0)
+    delta = inputs.lognormal_delta(n, 2)
+    beta, alpha, s = pins.dgp_params(0.8, OM, 1.0)
+    H = pins.hessian(phi, h)
+    D = pins.laplacian(phi, h)
+    HH = sum(H[a][b] * H[a][b] for a in range(3) for b in range(3))
+    ref = D + (D * D - HH) / alpha - s * delta / alpha
+    got = oracle.residual(oracle.dgp_newton_model(0.8, OM, 1.0), phi, delta, h=h)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("amp", [None, 20.0])
+def test_newton_comparator_reaches_the_exact_sine_solution(amp):
+    # in 1D the traceless part vanishes and mean(L) = 0, so the quadratic form
+    # and the closed form share the exact discrete solution
+    from oracle import pins
+    n = 32
+    m = oracle.dgp_newton_model(1.0, OM, 1.0)
+    phi = pins.dgp_sine_phi_discrete(n) if amp is None else pins.sine_1d(n, amp, 1, 0)
+    beta = oracle.dgp_model(1.0, OM, 1.0).beta
+    delta = pins.dgp_sine_delta_discrete(phi, beta)
+    r = oracle.solve(m, delta, tol=1e-13, max_cycles=100)
+    phi = phi - phi.mean()
+    assert r.status == 0
+    assert np.abs(r.phi - phi).max() <= 1e-10 * np.abs(phi).max()
+
+
+def test_newton_comparator_fixed_point_matches_closed_form_to_the_border():
+    # on a periodic 3D field the two forms differ only through the bordering
+    # constant (the mean of L enters the quadratic form multiplied by
+    # (2/(3 alpha))(D - r_minus)): the solutions agree to about mu / alpha
+    n = 32
+    delta = inputs.lognormal_delta(n, 1)
+    rc = oracle.solve(oracle.dgp_model(1.0, OM, 1.0), delta, tol=1e-12, max_cycles=80)
+    rn = oracle.solve(oracle.dgp_newton_model(1.0, OM, 1.0), delta, tol=1e-12, max_cycles=200)
+    assert rc.status == 0 and rn.status == 0
+    assert np.abs(rn.phi - rc.phi).max() <= 1e-3 * np.abs(rc.phi).max()
