@@ -131,6 +131,29 @@ def linear_model(s: float) -> Model:
     return m
 
 
+def linearised_dgp_model(a: float = 1.0, omega_m: float = OMEGA_M, h0rc: float = 1.0) -> Model:
+    """Comparator: eq:dgp_linear.  At linear order the fifth-force potential
+    phi/2 is Phi_N / (3 beta_DGP), and Phi_N obeys lap Phi_N = (3/2) Omega_m
+    delta / a (eq:GR_poisson_codeunit), so lap phi = Omega_m delta / (a beta)."""
+    beta = dgp_model(a, omega_m, h0rc).beta
+    return linear_model(omega_m / (a * beta))
+
+
+def linearised_kmo_model(n_mesh: int, box: float, nk: int = 3, k0: float = 1.0,
+                         beta: float = 0.1, lam: float | None = None, a: float = 1.0,
+                         omega_m: float = OMEGA_M, phibar: float = 0.0,
+                         dphibar_over_h0: float = 0.0) -> Model:
+    """Comparator: eq:linearised_Kmo in code units.  The source of
+    eq:kmf_eqn_codeunit_final, 3 beta A(phibar) Omega_m delta / a, divided by
+    c~ and by the background K_X = 1 + n K0 (phibar'^2 / (2 lambda^2 a^2))^(n-1)
+    (the bracket of eq:linearised_Kmo)."""
+    if lam is None:
+        lam = float(np.sqrt(3.0 * (1.0 - omega_m)))
+    ctil = n_mesh / box * 2997.92458
+    kx = 1.0 + nk * k0 * (dphibar_over_h0 ** 2 / (2.0 * lam ** 2 * a ** 2)) ** (nk - 1)
+    return linear_model(3.0 * beta * np.exp(beta * phibar) * omega_m / (a * ctil * kx))
+
+
 def _c(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
