@@ -140,6 +140,57 @@ def cycle_types(mg, L, C, delta, ws, par, phi_ref):
     return res
 
 
+def comparators(mg, L, C, delta, ws, par, phi_ref):
+    """The baselines the closed-form FAS solve is compared with, from phi = 0:
+    Newton-Gauss-Seidel on the quadratic form (on the bench density, and on a
+    tenth of it beside the closed form on the same tenth), the linearised
+    equation (eq:dgp_linear) by the same multigrid, and the all-FP32 variant
+    (stops at its floor).  Status, cycles, ms, final residual and the largest
+    and RMS relative differences from the FP64 closed-form solution."""
+    import numpy as np
+    import torch
+    n = delta.shape[0]
+    s_lin = mg.linear_source(mg.MODEL_DGP, par)
+    ws32 = mg.workspace(n, mg.MODEL_DGP, False, delta.device, mg.MG_FP32)
+    mild = 0.1 * delta
+    phi = torch.zeros_like(delta)
+
+    def run(fn, p, d, w, prec, ref):
+        opts = mg.make_opts(n, tol=TOL, max_cycles=60, precision=prec)
+        secs, st, rc = [], None, 0
+        for rep in range(3):
+            phi.zero_()
+            st = mg.Stats()
+            rc = fn(C.byref(opts), C.byref(p), mg._ptr(d), mg._ptr(phi), mg._ptr(w), w.numel(),
+                    mg._stream(), C.byref(st))
+            if rc < 0 and rc not in (mg.MG_ERR_DIVERGED, mg.MG_ERR_NONFINITE):
+                mg._raise(rc)
+            if rep:
+                secs.append(st.seconds)
+        out = {"status": L.mg_status_string(rc).decode(), "cycles": int(st.cycles),
+               "time_ms": 1e3 * float(np.mean(secs)) if rc >= 0 else None,
+               "eps": float(st.eps)}
+        if rc >= 0 and ref is not None:
+            diff = phi - ref
+            out["max_rel_diff_phi_vs_fp64"] = float(diff.abs().max() / ref.abs().max())
+            out["rms_rel_diff_phi_vs_fp64"] = float(diff.norm() / ref.norm())
+        return out
+
+    res = {"newton_gs": run(L.mg_solve_dgp_newton, par, delta, ws, mg.MG_FP64, phi_ref)}
+    closed_mild = run(L.mg_solve_dgp, par, mild, ws, mg.MG_FP64, None)
+    ref_mild = phi.clone()
+    res["delta_x0.1"] = {"closed_form": closed_mild,
+                         "newton_gs": run(L.mg_solve_dgp_newton, par, mild, ws, mg.MG_FP64,
+                                          ref_mild)}
+    del ref_mild
+    res["linearised"] = run(L.mg_solve_poisson, mg.PoissonParams(s_lin), delta, ws, mg.MG_FP64,
+                            phi_ref)
+    res["linearised"]["s"] = s_lin
+    res["fp32"] = run(L.mg_solve_dgp, par, delta, ws32, mg.MG_FP32, phi_ref)
+    del ws32, mild
+    return res
+
+
 def pm_steps(mg, pos0, dev, steps=3):
     """Particle-mesh steps of both models on the bench workload (512^3 mesh,
     256^3 particles, L = 512 Mpc/h) from a = 0.5, da = 0.01: CIC, Newtonian
@@ -199,6 +250,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-big", action="store_true", help="skip the 1024^3 V-cycle timing")
+    ap.add_argument("--main-only", action="store_true",
+                    help="only the FP64 steps and the JSON line's core fields (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solver runs on a single MI355X "
@@ -277,6 +330,9 @@ def main():
                      "traffic": traffic, "pass_ms_avg": pass_ms,
                      "algorithmic_bytes_per_launch": PASS_BYTES_PER_CELL * N_MESH ** 3},
     }
+    if args.main_only:
+        print(json.dumps(out), flush=True)
+        return
     # the same step with the mixed-precision solve (FP32 cycles to the FP32
     # floor, FP64 cycles to the same FP64 tolerance)
     phi64 = phi.clone()
@@ -310,6 +366,7 @@ def main():
                     "speedup_time_to_tol_vs_fp64": solve_ms / mix_solve_ms,
                     "max_rel_diff_phi_vs_fp64": err}
     out["cycle_types"] = cycle_types(mg, L, C, delta, ws, par, phi64)
+    out["comparators"] = comparators(mg, L, C, delta, ws, par, phi64)
     del ws_mix, ws
     torch.cuda.empty_cache()
     out["vcycle_512"] = vcycle_time(mg, L, C, delta)

@@ -42,7 +42,7 @@ typedef enum {
     MG_ERR_WORKSPACE = -5   /* workspace pointer null or smaller than required */
 } mg_status;
 
-typedef enum { MG_FP64 = 0, MG_MIXED = 1 } mg_precision;
+typedef enum { MG_FP64 = 0, MG_MIXED = 1, MG_FP32 = 2 } mg_precision;
 typedef enum {
     MG_MODEL_DGP = 0,
     MG_MODEL_KMOUFLAGE = 1,
@@ -71,8 +71,12 @@ typedef struct {
     int precision;    /* mg_precision: MG_FP64, or MG_MIXED = FP32-storage FAS cycles
                          (FP64 discriminant, residuals and reductions) until the FP32
                          residual stops falling, then FP64 cycles from that field to
-                         tol; the final residual is always the FP64 one (forward
-                         solves only; the adjoint is FP64) */
+                         tol; the final residual is always the FP64 one; or MG_FP32 =
+                         the FP32-storage cycles alone (every multigrid array in FP32,
+                         as the single-precision arrays of Sec. 3.2.2), stopping at tol,
+                         max_cycles or the FP32 floor (a cycle that no longer halves
+                         the residual: MG_NOT_CONVERGED, phi valid).  Forward solves
+                         only; the adjoint and the Newton-GS comparator are FP64 */
     int cycle;        /* mg_cycle: MG_CYCLE_V (default), MG_CYCLE_F or MG_CYCLE_W;
                          mg_solve_adjoint accepts MG_CYCLE_V only */
     int profile;      /* 1: time every finest-level colour pass with HIP events
@@ -92,8 +96,8 @@ typedef struct {
     double seconds;             /* host wall clock of the call */
     double pass_ms_avg;         /* mean finest colour-pass duration (profile=1) */
     int pass_count;             /* number of timed finest colour passes */
-    int cycles_fp32;            /* MG_MIXED: cycles of the FP32 phase (included in cycles) */
-    double eps_fp32;            /* MG_MIXED: residual at the end of the FP32 phase */
+    int cycles_fp32;            /* MG_MIXED, MG_FP32: cycles in FP32 storage (included in cycles) */
+    double eps_fp32;            /* MG_MIXED, MG_FP32: residual at the end of the FP32 cycles */
 } mg_stats;
 
 /* nDGP background (eq:beta_dgp with the LCDM expansion eq:H_lcdm, flat,
@@ -187,6 +191,19 @@ mg_status mg_solve_dgp_newton(const mg_opts *opts, const mg_dgp_params *par, con
 mg_status mg_solve_kmouflage(const mg_opts *opts, const mg_kmo_params *par,
                              const double *delta, double *phi, void *ws, size_t ws_bytes,
                              hipStream_t stream, mg_stats *stats);
+
+/* Comparator: coefficient s of the linearised field equation lap(phi) = s
+ * delta in code units, for mg_solve_poisson (the linear solves the full
+ * equations are compared with).
+ *   MG_MODEL_DGP (params mg_dgp_params): dropping the two nonlinear terms
+ *     (eq:dgp_linear, phi/2 = Phi_N / (3 beta_DGP) with lap Phi_N =
+ *     3/2 Omega_m delta / a) gives s = Omega_m / (a beta_DGP).
+ *   MG_MODEL_KMOUFLAGE (params mg_kmo_params, n cells per side for c~):
+ *     eq:linearised_Kmo, i.e. Sigma_1 -> K_X of the background and
+ *     Sigma_2 -> 0, gives s = 3 beta A(phibar) Omega_m / (a c~ K_X).
+ * Host only, no GPU.  Errors: MG_ERR_ARG (null pointer, other model,
+ * invalid parameters). */
+mg_status mg_linear_source(int model, const void *params, int n, double *s);
 
 /* Solve the linear periodic Poisson equation lap(phi) = s (delta - mean
  * delta) with the same multigrid (zero-mean phi).  Equals the FFT solution

@@ -156,6 +156,8 @@ def lib():
         L.mg_kmo_background.argtypes = [C.POINTER(KmoBgParams), C.c_int, _P, _P, _P, _P, _P,
                                         C.POINTER(KmoBgInfo)]
         L.mg_kmo_background.restype = st
+        L.mg_linear_source.argtypes = [C.c_int, _P, C.c_int, C.POINTER(C.c_double)]
+        L.mg_linear_source.restype = st
         L.mg_status_string.argtypes = [C.c_int]
         L.mg_status_string.restype = C.c_char_p
         L.mg_last_error.argtypes = []
@@ -194,7 +196,7 @@ def _check_mesh(t, name, dtype=torch.float64):
     return t
 
 
-MG_FP64, MG_MIXED = 0, 1
+MG_FP64, MG_MIXED, MG_FP32 = 0, 1, 2
 
 
 def workspace(n: int, model: int = MODEL_DGP, adjoint: bool = False, device=None,
@@ -275,7 +277,7 @@ def _solve(fn, par, model, delta, phi0, ws, **kw):
 def solve_dgp(delta, phi0=None, a=1.0, omega_m=OMEGA_M, h0rc=1.0, ws=None, **kw):
     """nDGP field (eq:dgp_eom_code); returns (zero-mean phi, stats).
     Keywords: tol, max_cycles, nu_pre, nu_post, nu_coarse, profile,
-    precision (MG_FP64 or MG_MIXED), cycle (CYCLE_V, CYCLE_F or CYCLE_W)."""
+    precision (MG_FP64, MG_MIXED or MG_FP32), cycle (CYCLE_V, CYCLE_F or CYCLE_W)."""
     return _solve(lib().mg_solve_dgp, dgp_params(a, omega_m, h0rc), MODEL_DGP, delta, phi0, ws, **kw)
 
 
@@ -292,6 +294,21 @@ def solve_kmouflage(delta, phi0=None, box_mpch=512.0, n_k=3, k0=1.0, beta=0.1, l
     par = kmo_params(delta.shape[0], box_mpch, n_k, k0, beta, lam, a, omega_m, phibar,
                      dphibar_dtau_over_h0)
     return _solve(lib().mg_solve_kmouflage, par, MODEL_KMOUFLAGE, delta, phi0, ws, **kw)
+
+
+def linear_source(model, par, n=1):
+    """s of the linearised equation lap(phi) = s delta (eq:dgp_linear,
+    eq:linearised_Kmo) for MODEL_DGP or MODEL_KMOUFLAGE; n is the mesh size
+    (enters c~ of Kmouflage)."""
+    s = C.c_double()
+    _raise(lib().mg_linear_source(model, C.byref(par), n, C.byref(s)))
+    return s.value
+
+
+def solve_linearised(model, par, delta, phi0=None, ws=None, **kw):
+    """Comparator: the linearised field equation of model (MODEL_DGP or
+    MODEL_KMOUFLAGE) solved by the Poisson multigrid; returns (phi, stats)."""
+    return solve_poisson(delta, linear_source(model, par, delta.shape[0]), phi0, ws, **kw)
 
 
 def solve_poisson(delta, s, phi0=None, ws=None, **kw):
@@ -419,24 +436,28 @@ def _model_of(par):
     return {DgpParams: MODEL_DGP, KmoParams: MODEL_KMOUFLAGE, PoissonParams: MODEL_POISSON}[type(par)]
 
 
-def op_residual(par, phi, delta, f=0.0, h=1.0):
+def op_residual(par, phi, delta, f=0.0, h=1.0, model=None):
+    """L_h(phi) - f; model defaults to the one of par (MODEL_DGP_NEWTON takes
+    DgpParams)."""
+    model = _model_of(par) if model is None else model
     n = phi.shape[0]
     out = torch.empty_like(phi)
     ws = _op_ws(n, phi.device)
     fa = f if isinstance(f, torch.Tensor) else None
     fs = 0.0 if fa is not None else float(f)
-    _raise(lib().mg_op_residual(_model_of(par), C.byref(par), n, h, _ptr(phi), _ptr(delta),
+    _raise(lib().mg_op_residual(model, C.byref(par), n, h, _ptr(phi), _ptr(delta),
                                 _ptr(fa), fs, _ptr(out), _ptr(ws), ws.numel(), _stream()))
     return out
 
 
-def op_colour_pass(par, phi, delta, colour, f=0.0, h=1.0):
+def op_colour_pass(par, phi, delta, colour, f=0.0, h=1.0, model=None):
+    model = _model_of(par) if model is None else model
     n = phi.shape[0]
     out = torch.empty_like(phi)
     ws = _op_ws(n, phi.device)
     fa = f if isinstance(f, torch.Tensor) else None
     fs = 0.0 if fa is not None else float(f)
-    _raise(lib().mg_op_colour_pass(_model_of(par), C.byref(par), n, h, colour, _ptr(phi),
+    _raise(lib().mg_op_colour_pass(model, C.byref(par), n, h, colour, _ptr(phi),
                                    _ptr(delta), _ptr(fa), fs, _ptr(out), _ptr(ws), ws.numel(),
                                    _stream()))
     return out

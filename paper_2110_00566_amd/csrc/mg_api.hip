@@ -146,10 +146,11 @@ void layout_hier(Hier<R> &Hh, Carve &cv, int n, bool adjoint) {
     Hh.nlev = L;
 }
 
-// Lay the workspace out (base == nullptr: only measure).
-void layout(Ctx &C, Carve &cv, int n, bool adjoint, bool mixed) {
-    layout_hier(C.h64, cv, n, adjoint);
-    if (mixed) layout_hier(C.h32, cv, n, false);
+// Lay the workspace out (base == nullptr: only measure): the FP64 hierarchy
+// unless precision is MG_FP32, the FP32 one unless it is MG_FP64.
+void layout(Ctx &C, Carve &cv, int n, bool adjoint, int precision) {
+    if (precision != MG_FP32) layout_hier(C.h64, cv, n, adjoint);
+    if (precision != MG_FP64) layout_hier(C.h32, cv, n, false);
     C.npartials = std::max<size_t>((size_t)n * n * n / TPB + 1, 1024);
     C.partials = cv.take<double>(2 * C.npartials);
     C.scal = cv.take<double>(S_NSCAL);
@@ -316,8 +317,8 @@ mg_status check_opts(const mg_opts *o) {
     if (o->nu_pre < 0 || o->nu_post < 0 || o->nu_coarse < 1 || o->nu_pre > 64 || o->nu_post > 64 ||
         o->nu_coarse > 4096)
         return fail(MG_ERR_ARG, "sweep counts out of range");
-    if (o->precision != MG_FP64 && o->precision != MG_MIXED)
-        return fail(MG_ERR_ARG, "opts.precision must be MG_FP64 or MG_MIXED");
+    if (o->precision != MG_FP64 && o->precision != MG_MIXED && o->precision != MG_FP32)
+        return fail(MG_ERR_ARG, "opts.precision must be MG_FP64, MG_MIXED or MG_FP32");
     if (o->cycle < MG_CYCLE_V || o->cycle > MG_CYCLE_W)
         return fail(MG_ERR_ARG, "opts.cycle must be MG_CYCLE_V, MG_CYCLE_F or MG_CYCLE_W");
     return MG_OK;
@@ -611,6 +612,54 @@ struct Profiler {
     }
 };
 
+// Clamp count, timing and status of a finished forward solve.
+mg_status finish(Ctx &C, mg_status status, mg_stats *st,
+                 std::chrono::steady_clock::time_point t0) {
+    unsigned long long ncl = 0;
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(&ncl, C.clamp, sizeof(ncl), hipMemcpyDeviceToHost, C.st));
+    HIPCHK(hipStreamSynchronize(C.st));
+    st->n_clamped = (long long)ncl;
+    if (status == MG_OK && ncl > 0) status = MG_WARN_CLAMPED;
+    st->status = status;
+    st->pass_ms_avg = C.pass_count ? C.pass_ms / C.pass_count : 0.0;
+    st->pass_count = C.pass_count;
+    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return status;
+}
+
+// All-FP32 variant (the single-precision arrays of Sec. 3.2.2): every
+// multigrid array in FP32 (the discriminant, residual norms and reductions
+// stay FP64); delta and phi cross the boundary in FP64.  Cycles stop at tol,
+// at max_cycles, or when a cycle no longer halves the residual (the FP32
+// floor), which returns MG_NOT_CONVERGED with a valid phi.
+template <int OP>
+mg_status fp32_solve(const mg_opts *o, Ctx &C, const double *delta, double *phi, mg_stats *st,
+                     std::chrono::steady_clock::time_point t0) {
+    density_hierarchy<float>(C, delta);
+    HLevel<float> &G = C.h32.lv[0];
+    k_pack<double, float><<<nblocks(2 * G.half), TPB, 0, C.st>>>(phi, G.logn, G.u[0], G.u[1],
+                                                                 nullptr);
+    Solver<OP, float> S(C);
+    PhaseResult p;
+    mg_status rc = S.run(o->tol, o->max_cycles, 0.5, st, 0, p);
+    if (rc != MG_OK) return rc;
+    st->cycles = p.cycles;
+    st->cycles_fp32 = p.cycles;
+    st->eps0 = p.eps0;
+    st->eps = p.eps;
+    st->eps_fp32 = p.eps;
+    st->cell_updates = (long long)o->n * o->n * o->n * (o->nu_pre + o->nu_post) * st->cycles;
+    if (p.status < 0) {
+        st->status = p.status;
+        return (mg_status)p.status;
+    }
+    S.mean_of(G.u[0], G.u[1], G.half);
+    k_unpack<float, double><<<nblocks(2 * G.half), TPB, 0, C.st>>>(G.u[0], G.u[1], G.logn, phi,
+                                                                   C.scal + S_MEAN);
+    return finish(C, (mg_status)p.status, st, t0);
+}
+
 template <int OP>
 mg_status forward_solve(const mg_opts *o, const Mod &M, const double *delta, double *phi,
                         void *ws, size_t ws_bytes, hipStream_t stream, mg_stats *st) {
@@ -618,7 +667,7 @@ mg_status forward_solve(const mg_opts *o, const Mod &M, const double *delta, dou
     const bool mixed = o->precision == MG_MIXED;
     Ctx C;
     Carve cv{static_cast<char *>(ws), 0};
-    layout(C, cv, o->n, false, mixed);
+    layout(C, cv, o->n, false, o->precision);
     if (!ws || ws_bytes < cv.off)
         return fail(MG_ERR_WORKSPACE, "workspace too small: need " + std::to_string(cv.off) +
                                           " bytes");
@@ -630,6 +679,7 @@ mg_status forward_solve(const mg_opts *o, const Mod &M, const double *delta, dou
     C.cycle = o->cycle;
     Profiler prof(C, o->profile != 0, 2 * (o->nu_pre + o->nu_post) + 2);
     reset_scalars(C);
+    if (o->precision == MG_FP32) return fp32_solve<OP>(o, C, delta, phi, st, t0);
     HLevel<double> &F = C.h64.lv[0];
     PhaseResult p32, p64;
     int cycles32 = 0;
@@ -673,17 +723,7 @@ mg_status forward_solve(const mg_opts *o, const Mod &M, const double *delta, dou
     S.mean_of(F.u[0], F.u[1], F.half);
     k_unpack<double, double><<<nblocks(2 * F.half), TPB, 0, C.st>>>(F.u[0], F.u[1], F.logn, phi,
                                                                     C.scal + S_MEAN);
-    unsigned long long ncl = 0;
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(&ncl, C.clamp, sizeof(ncl), hipMemcpyDeviceToHost, C.st));
-    HIPCHK(hipStreamSynchronize(C.st));
-    st->n_clamped = (long long)ncl;
-    if (status == MG_OK && ncl > 0) status = MG_WARN_CLAMPED;
-    st->status = status;
-    st->pass_ms_avg = C.pass_count ? C.pass_ms / C.pass_count : 0.0;
-    st->pass_count = C.pass_count;
-    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    return status;
+    return finish(C, status, st, t0);
 }
 
 template <int MODEL>
@@ -717,7 +757,7 @@ mg_status adjoint_solve(const mg_opts *o, const Mod &M, const double *delta, con
     auto t0 = std::chrono::steady_clock::now();
     Ctx C;
     Carve cv{static_cast<char *>(ws), 0};
-    layout(C, cv, o->n, true, false);
+    layout(C, cv, o->n, true, MG_FP64);
     if (!ws || ws_bytes < cv.off)
         return fail(MG_ERR_WORKSPACE, "workspace too small: need " + std::to_string(cv.off) +
                                           " bytes");
@@ -865,12 +905,27 @@ extern "C" {
 size_t mg_workspace_bytes(int n, int precision, int model, int adjoint) {
     if (!is_pow2(n) || n < 8 || n > 2048 || model < 0 || model > 3) return 0;
     if (model == MG_MODEL_DGP_NEWTON && (adjoint || precision != MG_FP64)) return 0;
-    if (precision != MG_FP64 && precision != MG_MIXED) return 0;
+    if (precision != MG_FP64 && precision != MG_MIXED && precision != MG_FP32) return 0;
     if (adjoint && precision != MG_FP64) return 0;
     Ctx C;
     Carve cv{nullptr, 0};
-    layout(C, cv, n, adjoint != 0, precision == MG_MIXED);
+    layout(C, cv, n, adjoint != 0, precision);
     return cv.off + 256;
+}
+
+mg_status mg_linear_source(int model, const void *params, int n, double *s) {
+    g_err.clear();
+    if (!params || !s) return fail(MG_ERR_ARG, "params and s must not be NULL");
+    if (model != MG_MODEL_DGP && model != MG_MODEL_KMOUFLAGE)
+        return fail(MG_ERR_ARG, "model must be MG_MODEL_DGP or MG_MODEL_KMOUFLAGE");
+    if (model == MG_MODEL_KMOUFLAGE && (n < 1 || n > 65536))
+        return fail(MG_ERR_ARG, "n must be in [1, 65536]");
+    Mod M;
+    if (!model_mod(model, params, n, M)) return fail(MG_ERR_ARG, "invalid model parameters");
+    // nDGP: F(Sigma) -> Sigma / alpha at small Sigma, T -> 0, so lap phi = (s / alpha) delta.
+    // Kmouflage: Sigma_1 -> K_X = c0, Sigma_2 -> 0.
+    *s = model == MG_MODEL_DGP ? M.s / M.alpha : M.src / (M.ctil * M.c0);
+    return MG_OK;
 }
 
 mg_status mg_solve_dgp(const mg_opts *opts, const mg_dgp_params *par, const double *delta,

@@ -27,10 +27,15 @@ def test_every_declared_symbol_is_exported(L):
 def test_workspace_sizes(L):
     assert L.mg_workspace_bytes(7, 0, 0, 0) == 0
     assert L.mg_workspace_bytes(4096, 0, 0, 0) == 0
-    assert L.mg_workspace_bytes(32, 2, 0, 0) == 0          # unknown precision
+    assert L.mg_workspace_bytes(32, 3, 0, 0) == 0          # unknown precision
     assert L.mg_workspace_bytes(32, 1, 0, 1) == 0          # the adjoint is FP64 only
-    # mixed keeps an FP32 hierarchy beside the FP64 one
+    assert L.mg_workspace_bytes(32, 2, 0, 1) == 0
+    assert L.mg_workspace_bytes(32, 2, 3, 0) == 0          # Newton-GS comparator: FP64 only
+    # mixed keeps an FP32 hierarchy beside the FP64 one; all-FP32 has only the FP32 one
     assert L.mg_workspace_bytes(64, 1, 0, 0) > L.mg_workspace_bytes(64, 0, 0, 0)
+    f32, f64 = L.mg_workspace_bytes(64, 2, 0, 0), L.mg_workspace_bytes(64, 0, 0, 0)
+    assert f32 < 0.6 * f64
+    assert L.mg_workspace_bytes(64, 1, 0, 0) >= f32 + f64 - 2 * 8 * 64 ** 3
     a = L.mg_workspace_bytes(64, 0, 0, 0)
     b = L.mg_workspace_bytes(64, 0, 0, 1)
     # finest level: 5 half-arrays of FP64 = 20 bytes per cell, coarse levels add < 1/2
@@ -58,6 +63,24 @@ def _bad_solve(L, **over):
 def test_invalid_options_rejected_before_gpu(L, field, value):
     assert _bad_solve(L, **{field: value}) == mg.MG_ERR_ARG
     assert len(L.mg_last_error()) > 0
+
+
+def test_linear_source_host_values(L):
+    # host-only coefficient of the linearised equations, against the oracle's
+    # independent derivation (eq:dgp_linear, eq:linearised_Kmo)
+    import oracle
+    for a, h0rc in ((1.0, 1.0), (0.5, 0.3)):
+        s = mg.linear_source(mg.MODEL_DGP, mg.dgp_params(a, 0.3089, h0rc))
+        assert s == pytest.approx(oracle.linearised_dgp_model(a, 0.3089, h0rc).s, rel=1e-14)
+    args = (128, 256.0, 3, 2.0, 0.15, 1.3, 0.9, 0.3089, 0.01, 0.7)
+    s = mg.linear_source(mg.MODEL_KMOUFLAGE, mg.kmo_params(*args), 128)
+    assert s == pytest.approx(oracle.linearised_kmo_model(*args).s, rel=1e-14)
+    with pytest.raises(mg.MGError):
+        mg.linear_source(mg.MODEL_POISSON, mg.PoissonParams(1.0))
+    with pytest.raises(mg.MGError):
+        mg.linear_source(mg.MODEL_DGP, mg.DgpParams(1.0, 0.3089, -1.0))
+    out = C.c_double()
+    assert L.mg_linear_source(mg.MODEL_DGP, None, 1, C.byref(out)) == mg.MG_ERR_ARG
 
 
 def test_invalid_model_parameters_rejected(L):

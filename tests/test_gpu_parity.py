@@ -154,6 +154,133 @@ def test_f_and_w_cycles_converge_to_the_v_solution(cycle):
     assert st["cycles"] == rv.cycles
 
 
+# ------------------------------------------- Newton-Gauss-Seidel comparator
+
+@pytest.mark.parametrize("n,h", [(8, 1.0), (32, 2.0), (128, 1.0)])
+def test_newton_comparator_operations_parity(n, h):
+    # The Newton step divides by dL/dphi = -(6/h^2)(1 + 4D/(3 alpha)), which
+    # nears zero where a rough field has large Laplacians; there a 1-ulp
+    # change of phi moves the update by ~1e-10 and no fixed tolerance is
+    # meaningful.  The field amplitude keeps the step well conditioned: the
+    # oracle's own update moves by < 1e-14 under a 2e-16 relative change of phi.
+    gp = mg.dgp_params(0.8, OM, 1.0)
+    om = oracle.dgp_newton_model(0.8, OM, 1.0)
+    phi = field(n, 1, 0.3)
+    delta = inputs.lognormal_delta(n, 2)
+    f = field(n, 3, 0.1)
+    ref = oracle.residual(om, phi, delta, f, h=h)
+    out = c(mg.op_residual(gp, g(phi), g(delta), g(f), h=h, model=mg.MODEL_DGP_NEWTON))
+    assert rel(out, ref) <= 1e-12
+    p2 = phi * (1.0 + 2e-16 * np.random.default_rng(0).standard_normal(phi.shape))
+    for colour in (0, 1):
+        ref = oracle.colour_pass(om, phi, delta, colour, f, h=h)
+        assert rel(oracle.colour_pass(om, p2, delta, colour, f, h=h), ref) <= 1e-14
+        out = c(mg.op_colour_pass(gp, g(phi), g(delta), colour, g(f), h=h,
+                                  model=mg.MODEL_DGP_NEWTON))
+        assert rel(out, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("n,cycles,cycle,sigma", [(32, 3, mg.CYCLE_V, 1.0),
+                                                  (128, 2, mg.CYCLE_V, 0.5),
+                                                  (32, 2, mg.CYCLE_W, 1.0)])
+def test_newton_comparator_fixed_cycles_parity(n, cycles, cycle, sigma):
+    delta = inputs.lognormal_delta(n, 3, sigma)
+    r = oracle.solve(oracle.dgp_newton_model(1.0, OM, 1.0), delta, tol=0.0, max_cycles=cycles,
+                     cycle=cycle)
+    phi, st = mg.solve_dgp_newton(g(delta), tol=0.0, max_cycles=cycles, cycle=cycle)
+    assert rel(c(phi), r.phi) <= 1e-11
+    assert np.allclose(st["eps_hist"], r.hist[:cycles], rtol=1e-8, atol=1e-300)
+
+
+def test_newton_comparator_diverges_where_the_oracle_does():
+    # a log-normal density with sigma = 1 on 128^3 (peaks near 90) drives
+    # dL/dphi of the quadratic form through zero: Newton-GS diverges in the
+    # oracle and on the GPU alike, while the closed-form update converges
+    n = 128
+    delta = inputs.lognormal_delta(n, 3, 1.0)
+    r = oracle.solve(oracle.dgp_newton_model(1.0, OM, 1.0), delta, tol=1e-8, max_cycles=12)
+    assert r.status == mg.MG_ERR_DIVERGED
+    with pytest.raises(mg.MGError) as e:
+        mg.solve_dgp_newton(g(delta), tol=1e-8, max_cycles=12)
+    assert e.value.status == mg.MG_ERR_DIVERGED
+    phi, st = mg.solve_dgp(g(delta), tol=1e-8, max_cycles=12)
+    assert st["status"] == 0
+
+
+def test_newton_comparator_converged_parity():
+    n = 64
+    delta = inputs.lognormal_delta(n, 1)
+    r = oracle.solve(oracle.dgp_newton_model(1.0, OM, 1.0), delta, tol=1e-11, max_cycles=100)
+    phi, st = mg.solve_dgp_newton(g(delta), tol=1e-11, max_cycles=100)
+    assert st["status"] == 0 and st["cycles"] == r.cycles
+    assert rel(c(phi), r.phi) <= 1e-9
+
+
+# ------------------------------------------------- linearised comparators
+
+def test_linear_source_matches_oracle():
+    for a, h0rc in ((1.0, 1.0), (0.6, 0.5), (0.8, 5.0)):
+        s = mg.linear_source(mg.MODEL_DGP, mg.dgp_params(a, OM, h0rc))
+        assert s == pytest.approx(oracle.linearised_dgp_model(a, OM, h0rc).s, rel=1e-14)
+    for args in ((64, 128.0, 3, 1.0, 0.1, 1.2, 1.0, OM, 0.0, 0.0),
+                 (256, 512.0, 2, 5.0, 0.2, 1.4, 0.7, OM, 0.03, 0.4)):
+        s = mg.linear_source(mg.MODEL_KMOUFLAGE, mg.kmo_params(*args), args[0])
+        assert s == pytest.approx(oracle.linearised_kmo_model(*args).s, rel=1e-14)
+
+
+@pytest.mark.parametrize("name,n", [("dgp", 32), ("dgp", 128), ("kmo", 128)])
+def test_linearised_solve_parity(name, n):
+    delta = inputs.lognormal_delta(n, 8)
+    if name == "dgp":
+        par, om, model = mg.dgp_params(0.7, OM, 1.0), oracle.linearised_dgp_model(0.7, OM, 1.0), \
+            mg.MODEL_DGP
+    else:
+        args = (n, 0.05 * n, 2, 5.0, 0.2, 1.4, 0.7, OM, 0.03, 0.4)
+        par, om, model = mg.kmo_params(*args), oracle.linearised_kmo_model(*args), \
+            mg.MODEL_KMOUFLAGE
+    r = oracle.solve(om, delta, tol=0.0, max_cycles=2)
+    phi, st = mg.solve_linearised(model, par, g(delta), tol=0.0, max_cycles=2)
+    assert rel(c(phi), r.phi) <= 1e-11
+    # converged, against the FFT solution of the same linear equation (the
+    # residual tolerance is absolute, so it scales with the source)
+    phi, st = mg.solve_linearised(model, par, g(delta), tol=1e-12 * min(1.0, om.s),
+                                  max_cycles=60)
+    assert st["status"] == 0
+    ref = oracle.fft_poisson(om.s * delta)
+    assert rel(c(phi), ref) <= 1e-9
+
+
+# ----------------------------------------------------- all-FP32 variant
+
+@pytest.mark.parametrize("name,n", [("dgp", 32), ("dgp", 128), ("kmo3", 128), ("poisson", 64)])
+def test_fp32_variant_tracks_oracle(name, n):
+    gp, om = models(n)[name]
+    delta = inputs.lognormal_delta(n, 3)
+    r = oracle.solve(om, delta, tol=0.0, max_cycles=3)
+    fn = {"dgp": mg.lib().mg_solve_dgp, "kmo3": mg.lib().mg_solve_kmouflage,
+          "poisson": mg.lib().mg_solve_poisson}[name]
+    model = {"dgp": 0, "kmo3": 1, "poisson": 2}[name]
+    phi, st = mg._solve(fn, gp, model, g(delta), None, None, tol=0.0, max_cycles=3,
+                        precision=mg.MG_FP32)
+    assert st["cycles"] == 3 and st["cycles_fp32"] == 3
+    assert rel(c(phi), r.phi) <= 2e-5
+    assert np.allclose(st["eps_hist"], r.hist[:3], rtol=1e-3)
+
+
+@pytest.mark.parametrize("n", [64, 256])
+def test_fp32_variant_stops_at_its_floor(n):
+    delta = inputs.lognormal_delta(n, 1)
+    ref, st64 = mg.solve_dgp(g(delta), tol=1e-11, max_cycles=60)
+    phi, st = mg.solve_dgp(g(delta), tol=1e-11, max_cycles=60, precision=mg.MG_FP32)
+    # the FP32 floor stops the cycles before the FP64 tolerance
+    assert st["status"] == mg.MG_NOT_CONVERGED and st["cycles"] < 60
+    assert st["eps"] > 1e-11 and st["eps"] < 1e-3 * st["eps0"]
+    assert float((phi - ref).abs().max() / ref.abs().max()) <= 1e-4
+    # a tolerance above the floor converges
+    phi2, st2 = mg.solve_dgp(g(delta), tol=10 * st["eps"], max_cycles=60, precision=mg.MG_FP32)
+    assert st2["status"] == 0 and st2["eps"] <= 10 * st["eps"]
+
+
 def test_config1_fixed_cycles_parity():
     # 32^3 lognormal (sigma = 1), nDGP H0 r_c = 1, a = 1: three V(1,1) cycles
     n = 32
