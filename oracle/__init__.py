@@ -354,6 +354,21 @@ def pm_step(pos, mom, n_mesh: int, a: float, da: float, h0rc: float = 1.0,
     return pos, mom, res.phi, delta, phin
 
 
+def pm_step_newtonian(pos, mom, n_mesh: int, a: float, da: float, omega_m: float = OMEGA_M):
+    """The GLAM step of Sec. 3.1 without a fifth force (LCDM): the pm_step
+    above with Phi_N alone as the potential.  Returns new (pos, mom, delta)."""
+    pos = np.ascontiguousarray(pos, dtype=np.float32).copy()
+    mom = np.ascontiguousarray(mom, dtype=np.float32).copy()
+    _, delta = cic_density(pos, n_mesh)
+    phin = fft_poisson(1.5 * omega_m / a * delta)
+    ah = a + 0.5 * da
+    kick = da / (a * expansion_rate(a, omega_m))
+    drift = da / (ah ** 3 * expansion_rate(ah, omega_m))
+    lib().or_kick_drift(n_mesh, pos.shape[0], _c(phin), pos.reshape(-1), mom.reshape(-1), kick,
+                        drift)
+    return pos, mom, delta
+
+
 def kmo_background_values(bg, a: float, da: float) -> dict:
     """Background inputs of a Kmouflage PM step from an oracle background
     (oracle.background.solve): E at a and a + da/2, phibar, phibar' and

@@ -105,3 +105,62 @@ def test_multi_step_runs_track_the_oracle(model):
     assert periodic_diff(c(gp), po, n).max() <= 1e-3
     assert np.abs(c(gm) - mo).max() <= 1e-4 * np.abs(mo).max()
     assert np.abs(mo).max() > 0
+
+
+def test_gpu_pm_runs_follow_linear_growth():
+    # 50 GPU steps from a = 0.25 to 1 of a linear growing mode (64^3 mesh,
+    # 32^3 particles): nDGP must grow as the growth equation with
+    # G_eff = 1 + 1/(3 beta_DGP) (eq:dgp_linear), Kmouflage as eq:kmo_lin_growth,
+    # against an LCDM run (the Kmouflage step with beta = 0)
+    from scipy.interpolate import CubicSpline
+    from pm_growth import growing_mode_ics, large_scale_growth, linear_growth
+    n, npart, a0, a1, nst, h0rc, box = 64, 32, 0.25, 1.0, 50, 0.5, 128.0
+    nk, k0, beta = 2, 1.0, 0.2
+    da = (a1 - a0) / nst
+    e_lcdm = lambda a: np.sqrt(OM / a ** 3 + 1.0 - OM)
+    x0, p0, f0 = growing_mode_ics(n, npart, 12, a0, e_lcdm)
+    ap = np.linspace(0.2, 1.0, 300)
+    tab = {bt: mg.kmo_background(nk, k0, bt, ap) for bt in (0.0, beta)}
+    sp = {bt: {k: CubicSpline(ap, tab[bt][k]) for k in ("hubble", "phibar", "dphibar_dtau")}
+          for bt in tab}
+    runs = {}
+    for name in ("dgp", "kmo", "lcdm"):
+        gp, gm = g(x0), g(p0)
+        phi = torch.zeros((n,) * 3, dtype=torch.float64, device="cuda")
+        phin = torch.zeros_like(phi)
+        a = a0
+        for _ in range(nst):
+            if name == "dgp":
+                _, st = mg.pm_step(gp, gm, phi, phin, n, a, da, h0rc=h0rc)
+            else:
+                _, st = mg.pm_step_kmouflage(gp, gm, phi, phin, n, a, da, box, nk, k0,
+                                             beta if name == "kmo" else 0.0)
+            assert st["status"] in (0, 2)
+            a += da
+        runs[name] = mg.cic_delta(gp, n)
+    d0 = c(mg.cic_delta(g(x0), n))
+    grow = {k: large_scale_growth(d0, c(v)) for k, v in runs.items()}
+
+    def ode_kmo(bt):
+        s = sp[bt]
+        lam = tab[bt]["lambda"]
+
+        def geff(a):
+            xbar = float(s["dphibar_dtau"](a)) ** 2 / (2 * lam ** 2 * a ** 2)
+            return np.exp(bt * float(s["phibar"](a))) * (1.0 + 2 * bt ** 2 / (1.0 + nk * k0 * xbar ** (nk - 1)))
+
+        def rhs(a, y):
+            e = float(s["hubble"](a))
+            dphida = float(s["dphibar_dtau"](a)) / (a * a * e)
+            return [y[1] / (a ** 3 * e), 1.5 * OM * geff(a) * y[0] / (a ** 2 * e) - bt * dphida * y[1]]
+        from scipy.integrate import solve_ivp
+        return solve_ivp(rhs, (a0, a1), [1.0, a0 ** 3 * e_lcdm(a0) * f0], rtol=1e-9,
+                         atol=1e-14).y[0, -1]
+    beta_dgp = lambda a: 1.0 + 2.0 * e_lcdm(a) * h0rc * (1.0 - 0.5 * OM / a ** 3 / e_lcdm(a) ** 2)
+    ode = {"dgp": linear_growth(a0, a1, lambda a: 1.0 + 1.0 / (3.0 * beta_dgp(a)), f0, e_lcdm)[0],
+           "kmo": ode_kmo(beta), "lcdm": ode_kmo(0.0)}
+    for k in ode:
+        assert grow[k] == pytest.approx(ode[k], rel=0.03), k
+    for k in ("dgp", "kmo"):
+        assert ode[k] / ode["lcdm"] - 1.0 > 0.02
+        assert grow[k] / grow["lcdm"] - 1.0 == pytest.approx(ode[k] / ode["lcdm"] - 1.0, rel=0.06), k

@@ -74,3 +74,76 @@ def test_kmouflage_kick_momentum_and_newtonian_limit():
                                m4.reshape(-1), da / (a * v["e_a"]),
                                da / ((a + da / 2) ** 3 * v["e_half"]))
     assert np.array_equal(m3, m4) and np.array_equal(p3, p4)
+
+
+# ------------------------------------------------ linear growth of PM runs
+
+from pm_growth import growing_mode_ics, large_scale_growth, linear_growth as _growth  # noqa: E402
+
+
+def test_pm_runs_follow_linear_growth_with_the_dgp_enhancement():
+    # eq:dgp_linear: on large scales nDGP rescales Newton's constant by
+    # G_eff = 1 + 1/(3 beta_DGP(a)); 50 steps from a = 0.25 to 1 of a linear
+    # growing mode must grow as the G_eff-modified linear growth equation,
+    # and the LCDM run as the unmodified one
+    n, npart, a0, a1, nst, h0rc = 32, 16, 0.25, 1.0, 50, 0.5
+    da = (a1 - a0) / nst
+    e = lambda a: np.sqrt(OM / a ** 3 + 1.0 - OM)
+    beta = lambda a: 1.0 + 2.0 * e(a) * h0rc * (1.0 - 0.5 * OM / a ** 3 / e(a) ** 2)
+    x0, p0, f0 = growing_mode_ics(n, npart, 11, a0, e)
+    runs = {}
+    for name, step in (("lcdm", lambda x, p, a: oracle.pm_step_newtonian(x, p, n, a, da)),
+                       ("dgp", lambda x, p, a: oracle.pm_step(x, p, n, a, da, h0rc=h0rc))):
+        x, p, a = x0, p0, a0
+        for _ in range(nst):
+            x, p = step(x, p, a)[:2]
+            a += da
+        runs[name] = x
+    d0 = oracle.cic_density(x0, n)[1]
+    g_lcdm = large_scale_growth(d0, oracle.cic_density(runs["lcdm"], n)[1])
+    g_dgp = large_scale_growth(d0, oracle.cic_density(runs["dgp"], n)[1])
+    ode_lcdm = _growth(a0, a1, lambda a: 1.0, f0, e)[0]
+    ode_dgp = _growth(a0, a1, lambda a: 1.0 + 1.0 / (3.0 * beta(a)), f0, e)[0]
+    # absolute growth within the PM discretisation (time step, 3-point force, CIC)
+    assert g_lcdm == pytest.approx(ode_lcdm, rel=0.03)
+    assert g_dgp == pytest.approx(ode_dgp, rel=0.03)
+    # the enhancement, where those cancel, to 5% of itself (it is ~7%)
+    assert ode_dgp / ode_lcdm - 1.0 > 0.05
+    assert (g_dgp / g_lcdm - 1.0) == pytest.approx(ode_dgp / ode_lcdm - 1.0, rel=0.05)
+
+
+def test_kmouflage_pm_runs_follow_eq_kmo_lin_growth():
+    # eq:kmo_lin_growth in the PM step's variables: the friction
+    # (d ln A/d phi) phi' becomes -beta (d phibar/da) p, and the source is
+    # (3/2) Omega_m A(phibar) (1 + 2 beta^2/K_X) D / (a^2 E) with the
+    # background E, phibar, phibar' of the solver
+    from scipy.integrate import solve_ivp
+    n, npart, a0, a1, nst = 32, 16, 0.25, 1.0, 50
+    nk, k0, beta, box = 2, 1.0, 0.2, 64.0
+    da = (a1 - a0) / nst
+    b = bg.solve(nk, k0, beta)
+    e_lcdm = lambda a: np.sqrt(OM / a ** 3 + 1.0 - OM)
+    x0, p0, f0 = growing_mode_ics(n, npart, 11, a0, e_lcdm)
+
+    def rhs(a, y):
+        v = oracle.kmo_background_values(b, a, 0.0)
+        xbar = v["dphibar_dtau"] ** 2 / (2 * v["lam"] ** 2 * a ** 2)
+        geff = np.exp(beta * v["phibar"]) * (1.0 + 2 * beta ** 2 / (1.0 + nk * k0 * xbar ** (nk - 1)))
+        return [y[1] / (a ** 3 * v["e_a"]),
+                1.5 * OM * geff * y[0] / (a ** 2 * v["e_a"]) - beta * v["dphibar_da"] * y[1]]
+    # same initial momentum as the particles
+    ode_kmo = solve_ivp(rhs, (a0, a1), [1.0, a0 ** 3 * e_lcdm(a0) * f0], rtol=1e-9,
+                        atol=1e-14).y[0, -1]
+    ode_lcdm = _growth(a0, a1, lambda a: 1.0, f0, e_lcdm)[0]
+    xk, pk, xl, pl, a = x0, p0, x0, p0, a0
+    for _ in range(nst):
+        xk, pk = oracle.pm_step_kmouflage(xk, pk, n, a, da, box, nk, k0, beta,
+                                          oracle.kmo_background_values(b, a, da))[:2]
+        xl, pl = oracle.pm_step_newtonian(xl, pl, n, a, da)[:2]
+        a += da
+    d0 = oracle.cic_density(x0, n)[1]
+    g_kmo = large_scale_growth(d0, oracle.cic_density(xk, n)[1])
+    g_lcdm = large_scale_growth(d0, oracle.cic_density(xl, n)[1])
+    assert g_kmo == pytest.approx(ode_kmo, rel=0.03)
+    assert ode_kmo / ode_lcdm - 1.0 > 0.02
+    assert (g_kmo / g_lcdm - 1.0) == pytest.approx(ode_kmo / ode_lcdm - 1.0, rel=0.05)
