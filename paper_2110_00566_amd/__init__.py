@@ -14,7 +14,10 @@ Main entry points (tensors are float64, C order [z][y][x], on the GPU):
 * ``solve_poisson(delta, s, phi0=None, ...)``
 * ``solve_adjoint(model, params, delta, phi, w, mu0=None, ...)``
 * ``DGPSolve.apply(delta, h0rc, a, omega_m, tol)`` -- autograd wrapper
-* ``cic_delta(pos, n_mesh)`` and ``pm_step(pos, mom, phi, ...)``
+* ``cic_delta(pos, n_mesh)``, ``pm_step(pos, mom, phi, ...)`` and
+  ``pm_step_kmouflage(pos, mom, phi, ...)``
+* ``kmo_background(n_k, k0, beta, a)`` -- Kmouflage background cosmology (host)
+* comparators: ``solve_dgp_newton``, ``solve_linearised``, ``precision=MG_FP32``
 * ``op_*`` single operations of the solve (for parity tests).
 """
 from __future__ import annotations
