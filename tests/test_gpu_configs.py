@@ -48,17 +48,35 @@ def test_config2_cic_matches_oracle(delta256):
     assert abs(d_gpu.mean()) <= 1e-9
 
 
-@pytest.mark.parametrize("precision", [mg.MG_FP64, mg.MG_MIXED])
-def test_config2_h0rc1_elementwise(delta256, precision):
+def fifth_force_rel(phi, ref):
+    """Largest relative error over the three components of the central-
+    difference gradient (the fifth force up to its constant factor)."""
+    return max(rel(np.roll(phi, -1, ax) - np.roll(phi, 1, ax),
+                   np.roll(ref, -1, ax) - np.roll(ref, 1, ax)) for ax in range(3))
+
+
+@pytest.fixture(scope="module")
+def dgp256_ref(delta256):
     d, _ = delta256
-    ref = oracle.solve(oracle.dgp_model(1.0, OM, 1.0), d, tol=1e-10, max_cycles=60)
+    return oracle.solve(oracle.dgp_model(1.0, OM, 1.0), d, tol=1e-10, max_cycles=60)
+
+
+@pytest.mark.parametrize("precision", [mg.MG_FP64, mg.MG_MIXED, mg.MG_FP32])
+def test_config2_h0rc1_elementwise(delta256, dgp256_ref, precision):
+    # max relative error of phi and of the fifth force against the FP64
+    # oracle, stated per precision (printed) and bounded: 1e-6 for the solves
+    # that reach the 1e-8 residual, 1e-4 for the all-FP32 variant (its floor)
+    d, _ = delta256
     phi, st = mg.solve_dgp(g(d), h0rc=1.0, tol=1e-8, precision=precision)
-    assert st["status"] == 0 and st["eps"] <= 1e-8
-    assert rel(c(phi), ref.phi) <= 1e-6
-    for ax in range(3):
-        f_g = np.roll(c(phi), -1, ax) - np.roll(c(phi), 1, ax)
-        f_o = np.roll(ref.phi, -1, ax) - np.roll(ref.phi, 1, ax)
-        assert rel(f_g, f_o) <= 1e-6
+    e_phi, e_f5 = rel(c(phi), dgp256_ref.phi), fifth_force_rel(c(phi), dgp256_ref.phi)
+    print("\naccuracy nDGP 256^3 H0rc=1 precision=%d: cycles %d eps %.2e max rel err phi %.2e "
+          "fifth force %.2e" % (precision, st["cycles"], st["eps"], e_phi, e_f5))
+    if precision == mg.MG_FP32:
+        assert st["status"] == mg.MG_NOT_CONVERGED
+        assert e_phi <= 1e-4 and e_f5 <= 1e-4
+    else:
+        assert st["status"] == 0 and st["eps"] <= 1e-8
+        assert e_phi <= 1e-6 and e_f5 <= 1e-6
 
 
 @pytest.mark.parametrize("h0rc", [0.5, 1.0, 5.0])
@@ -84,7 +102,10 @@ def test_config3_kmouflage(delta256):
         phi, st = mg.solve_kmouflage(g(d), box_mpch=512.0, n_k=3, k0=1.0, beta=0.1, tol=1e-10,
                                      precision=precision)
         assert st["status"] == 0 and st["eps"] <= 1e-10
-        assert rel(c(phi), ref.phi) <= 1e-6
+        e_phi, e_f5 = rel(c(phi), ref.phi), fifth_force_rel(c(phi), ref.phi)
+        print("\naccuracy Kmouflage 256^3 n=3 precision=%d: cycles %d max rel err phi %.2e "
+              "fifth force %.2e" % (precision, st["cycles"], e_phi, e_f5))
+        assert e_phi <= 1e-6 and e_f5 <= 1e-5
         L = oracle.residual(om, c(phi), d)
         assert np.sqrt(np.mean((L - L.mean()) ** 2)) <= 1.05e-10
 
