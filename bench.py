@@ -323,6 +323,8 @@ def main():
                    "tol": TOL, "precision": "fp64"},
         "cycles": int(round(float(np.mean(cycles)))),
         "time_to_tol_ms": solve_ms,
+        "level_ms_per_cycle": [round(sum(s.level_ms[l] for s in stats) / sum(cycles), 4)
+                               for l in range(mg.LEVELS) if stats[0].level_ms[l] > 0],
         "ms_per_vcycle": solve_ms / float(np.mean(cycles)),
         "roofline": {"bound": "hbm", "kernel": "k_pass<OP_DGP> (finest colour pass)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

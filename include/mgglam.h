@@ -84,6 +84,7 @@ typedef struct {
 } mg_opts;
 
 #define MG_HIST 64
+#define MG_LEVELS 16
 typedef struct {
     int cycles;                 /* cycles run */
     int status;                 /* same as the return value */
@@ -98,6 +99,11 @@ typedef struct {
     int pass_count;             /* number of timed finest colour passes */
     int cycles_fp32;            /* MG_MIXED, MG_FP32: cycles in FP32 storage (included in cycles) */
     double eps_fp32;            /* MG_MIXED, MG_FP32: residual at the end of the FP32 cycles */
+    double level_ms[MG_LEVELS]; /* profile=1: GPU time of the cycles' work on each level
+                                   (0 = finest), summed over all cycles and both precisions;
+                                   the levels of the single-workgroup tail (<= 16^3) are
+                                   reported together at the tail's first level; the residual
+                                   evaluations outside the cycles are not included */
 } mg_stats;
 
 /* nDGP background (eq:beta_dgp with the LCDM expansion eq:H_lcdm, flat,

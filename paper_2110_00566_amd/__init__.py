@@ -38,6 +38,7 @@ MODEL_DGP, MODEL_KMOUFLAGE, MODEL_POISSON, MODEL_DGP_NEWTON = 0, 1, 2, 3
 CYCLE_V, CYCLE_F, CYCLE_W = 0, 1, 2
 OMEGA_M = 0.3089
 HIST = 64
+LEVELS = 16
 
 
 class MGError(RuntimeError):
@@ -57,7 +58,8 @@ class Stats(C.Structure):
                 ("eps", C.c_double), ("eps_hist", C.c_double * HIST), ("lambda_", C.c_double),
                 ("cell_updates", C.c_longlong), ("n_clamped", C.c_longlong),
                 ("seconds", C.c_double), ("pass_ms_avg", C.c_double), ("pass_count", C.c_int),
-                ("cycles_fp32", C.c_int), ("eps_fp32", C.c_double)]
+                ("cycles_fp32", C.c_int), ("eps_fp32", C.c_double),
+                ("level_ms", C.c_double * LEVELS)]
 
     def as_dict(self):
         k = min(self.cycles, HIST)
@@ -66,7 +68,7 @@ class Stats(C.Structure):
                     cell_updates=self.cell_updates, n_clamped=self.n_clamped,
                     seconds=self.seconds, pass_ms_avg=self.pass_ms_avg,
                     pass_count=self.pass_count, cycles_fp32=self.cycles_fp32,
-                    eps_fp32=self.eps_fp32)
+                    eps_fp32=self.eps_fp32, level_ms=list(self.level_ms))
 
 
 class DgpParams(C.Structure):

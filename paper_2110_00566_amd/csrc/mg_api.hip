@@ -103,6 +103,14 @@ struct Ctx {
     int ev_used = 0;
     double pass_ms = 0.0;
     int pass_count = 0;
+    // per-level timing (profile): events bracketing each level's segments
+    struct Segment {
+        int level, e0, e1;
+    };
+    std::vector<hipEvent_t> lev_ev;
+    std::vector<Segment> segs;
+    int lev_used = 0;
+    double level_ms[MG_LEVELS] = {};
 };
 
 template <typename R>
@@ -469,20 +477,40 @@ struct Solver {
         return Hh.nlev;
     }
 
+    // Profile mode: record an event on the stream (index, or -1), and a
+    // segment of level l's work between two of them.
+    int mark() {
+        if (!C.profile) return -1;
+        if (C.lev_used == (int)C.lev_ev.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return -1;
+            C.lev_ev.push_back(e);
+        }
+        (void)hipEventRecord(C.lev_ev[C.lev_used], C.st);
+        return C.lev_used++;
+    }
+    void segment(int l, int e0, int e1) {
+        if (e0 >= 0 && e1 >= 0) C.segs.push_back({std::min(l, MG_LEVELS - 1), e0, e1});
+    }
+
     // One cycle of type 0 (V), 1 (F: a coarse F-cycle then a coarse V-cycle)
     // or 2 (W: two coarse W-cycles) on level l (Sec. 3.2.1).
     void cycle(int l, int type) {
+        const int e0 = mark();
         if (l > 0 && l == tail_start()) {
             tail(l, type);
+            segment(l, e0, mark());
             return;
         }
         if (l == Hh.nlev - 1) {
             for (int s = 0; s < C.nuc; ++s) sweep(l);
+            segment(l, e0, mark());
             return;
         }
         for (int s = 0; s < C.nu1; ++s) sweep(l);
         resid_restrict(l);
         coarse_source(l + 1);
+        segment(l, e0, mark());
         if (type == 2) {
             cycle(l + 1, 2);
             cycle(l + 1, 2);
@@ -492,6 +520,7 @@ struct Solver {
         } else {
             cycle(l + 1, 0);
         }
+        const int e2 = mark();
         if (fused_prolong(l)) {
             prolong_pass0(l);
             pass(l, 1);
@@ -500,6 +529,7 @@ struct Solver {
             prolong(l);
             for (int s = 0; s < C.nu2; ++s) sweep(l);
         }
+        segment(l, e2, mark());
     }
 
     mg_status read_scal(double *hs) {
@@ -514,6 +544,13 @@ struct Solver {
                 ++C.pass_count;
             }
             C.ev_used = 0;
+            for (const auto &g : C.segs) {
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, C.lev_ev[g.e0], C.lev_ev[g.e1]));
+                C.level_ms[g.level] += ms;
+            }
+            C.segs.clear();
+            C.lev_used = 0;
         }
         return MG_OK;
     }
@@ -608,7 +645,9 @@ struct Profiler {
     }
     ~Profiler() {
         for (auto &e : C.ev) (void)hipEventDestroy(e);
+        for (auto &e : C.lev_ev) (void)hipEventDestroy(e);
         C.ev.clear();
+        C.lev_ev.clear();
     }
 };
 
@@ -624,6 +663,7 @@ mg_status finish(Ctx &C, mg_status status, mg_stats *st,
     st->status = status;
     st->pass_ms_avg = C.pass_count ? C.pass_ms / C.pass_count : 0.0;
     st->pass_count = C.pass_count;
+    for (int l = 0; l < MG_LEVELS; ++l) st->level_ms[l] = C.level_ms[l];
     st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return status;
 }

@@ -281,6 +281,20 @@ def test_fp32_variant_stops_at_its_floor(n):
     assert st2["status"] == 0 and st2["eps"] <= 10 * st["eps"]
 
 
+def test_level_timing_stats():
+    n = 256
+    delta = inputs.lognormal_delta(n, 2)
+    _, st = mg.solve_dgp(g(delta), tol=0.0, max_cycles=3, profile=True)
+    lv = st["level_ms"]
+    nlev = 7                                    # 256 .. 4; the tail starts at 16^3 (level 4)
+    assert all(x > 0 for x in lv[:5]) and all(x == 0 for x in lv[5:])
+    assert lv[0] == max(lv)
+    assert sum(lv) <= 1e3 * st["seconds"]
+    assert lv[0] > 4 * lv[1]                    # the finest level dominates (8x the cells)
+    _, st = mg.solve_dgp(g(delta), tol=0.0, max_cycles=3)
+    assert all(x == 0 for x in st["level_ms"]) and nlev == 7
+
+
 def test_config1_fixed_cycles_parity():
     # 32^3 lognormal (sigma = 1), nDGP H0 r_c = 1, a = 1: three V(1,1) cycles
     n = 32
