@@ -170,7 +170,9 @@ __device__ __forceinline__ void block_sum2(double a, double b, double *partials,
 // Residual d = (faces - 6u)/h^2 - K - f (double arithmetic) at the 8 children
 // of coarse cell t, restricted (8-cell mean) together with u.  With REDUCE
 // the sums of d and d^2 accumulate into s1, s2 (finest level: norm and mean).
-template <int OP, bool REDUCE, typename R>
+// UNR: unroll of the loop over the 8 children (the single-workgroup tail
+// keeps it rolled, to stay within its 128 registers per lane).
+template <int OP, bool REDUCE, typename R, int UNR = 8>
 __device__ __forceinline__ void dev_resid_restrict(const Mod &M, const LvlT<R> &L, const Coefs &Cf,
                                                    const double *fptr, double fscale, R *ru0,
                                                    R *ru1, R *rd0, R *rd1,
@@ -184,7 +186,7 @@ __device__ __forceinline__ void dev_resid_restrict(const Mod &M, const LvlT<R> &
         const int K = (int)(t >> (2 * lnc));
         double sd = 0.0, su = 0.0;
         const double inv_h2 = 1.0 / L.h2;
-#pragma unroll
+#pragma unroll UNR
         for (int q = 0; q < 8; ++q) {
             const int a = q & 1, b = (q >> 1) & 1, cc = q >> 2;
             const int j = 2 * J + b, k = 2 * K + cc;
@@ -504,6 +506,42 @@ __device__ void tail_sweeps(const Mod &M, const TailLv<R> &T, const Coefs &Cf, i
     }
 }
 
+// The sweeps of a level with at most 64 cells per colour (the 4^3 level) on
+// the first wavefront alone: a lane per cell, and no workgroup barrier
+// between passes.  A wavefront's LDS reads and writes take effect in program
+// order, so every read of a pass precedes its writes and follows the previous
+// pass's writes, as in tail_pass.
+template <int OP, typename R>
+__device__ void tail_sweeps_wave(const Mod &M, const TailLv<R> &T, const Coefs &Cf, int count) {
+    const LvlT<R> &L = T.L;
+    const int half = 1 << (3 * L.logn - 1);
+    const int t = threadIdx.x;
+    if (t < 64) {
+        const int m = t & ((1 << L.lognh) - 1);
+        const int j = (t >> L.lognh) & (L.n - 1);
+        const int k = t >> (L.lognh + L.logn);
+        for (int s = 0; s < count; ++s) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                R nv = (R)0;
+                if (t < half) {
+                    R faces;
+                    const R K = cell_term<OP, R, R>(M, L, Cf, c, m, j, k, faces, nullptr);
+                    const R f = (c ? L.f1 : L.f0)[t];
+                    if constexpr (OP == OP_NEWTON)
+                        nv = newton_update<R>(M, (c ? L.u1 : L.u0)[t], faces, K, f, (R)L.h2);
+                    else
+                        nv = (faces - (R)L.h2 * (K + f)) * (R)(1.0 / 6.0);
+                }
+                __builtin_amdgcn_wave_barrier();
+                if (t < half) (c ? L.u1 : L.u0)[t] = nv;
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+    }
+    __syncthreads();
+}
+
 // Elements of LDS the tail needs for levels l0 .. (u, d, f of every level,
 // R u of every level below the first).
 __host__ __device__ inline int tail_lds_elems(int logn0, int nl) {
@@ -520,7 +558,7 @@ __device__ __forceinline__ void tail_restrict(const Mod &M, TailLv<R> (&T)[NL],
     double s1 = 0.0, s2 = 0.0;
     const int ncoarse = 1 << (3 * Tc.L.logn);
     for (int t = threadIdx.x; t < ncoarse; t += TAIL_THREADS)
-        dev_resid_restrict<OP, false, R>(M, T[l].L, Cf[l], nullptr, 0.0, Tc.ru0, Tc.ru1,
+        dev_resid_restrict<OP, false, R, 1>(M, T[l].L, Cf[l], nullptr, 0.0, Tc.ru0, Tc.ru1,
                                          const_cast<R *>(Tc.L.f0), const_cast<R *>(Tc.L.f1),
                                          nullptr, (size_t)t, s1, s2);
     __syncthreads();
@@ -538,7 +576,10 @@ template <int OP, int NL, int LV, typename R>
 __device__ __forceinline__ void tail_cycle(const Mod &M, TailLv<R> (&T)[NL], const Coefs (&Cf)[NL],
                            const TailArgs<R> &A, int type) {
     if constexpr (LV == NL - 1) {
-        tail_sweeps<OP, R>(M, T[LV], Cf[LV], A.nuc);
+        if (T[LV].L.n == 4)
+            tail_sweeps_wave<OP, R>(M, T[LV], Cf[LV], A.nuc);
+        else
+            tail_sweeps<OP, R>(M, T[LV], Cf[LV], A.nuc);
     } else {
         tail_sweeps<OP, R>(M, T[LV], Cf[LV], A.nu1);
         tail_restrict<OP, NL, R>(M, T, Cf, LV);
