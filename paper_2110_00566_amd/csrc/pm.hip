@@ -128,14 +128,24 @@ __global__ void k_zero_u64(unsigned long long *a, size_t n) {
     if (t < n) a[t] = 0ull;
 }
 
-// g = -grad(Phi_N + cphi phi) by 3-point differences at the 8 CIC cells,
-// interpolated with the CIC weights; p = damp p + g kick; x += p drift
-// (periodic).  nDGP: cphi = 1/2, damp = 1; Kmouflage: cphi = beta c~ and
-// damp = 1 - beta (d phibar/da) da (the velocity term of eq:force_Kmo2).
+// Total potential psi = Phi_N + cphi phi on the mesh (nDGP: cphi = 1/2;
+// Kmouflage: cphi = beta c~), formed once so that the particle kernel
+// gathers one field instead of two.
+__global__ __launch_bounds__(PTPB) void k_total_potential(const double *__restrict__ phin,
+                                                           const double *__restrict__ phi,
+                                                           double cphi, double *__restrict__ psi,
+                                                           size_t ncell) {
+    const size_t t = (size_t)blockIdx.x * PTPB + threadIdx.x;
+    if (t < ncell) psi[t] = phin[t] + cphi * phi[t];
+}
+
+// g = -grad(psi) by 3-point differences at the 8 CIC cells, interpolated
+// with the CIC weights; p = damp p + g kick; x += p drift (periodic).
+// nDGP: damp = 1; Kmouflage: damp = 1 - beta (d phibar/da) da (the velocity
+// term of eq:force_Kmo2).
 __global__ __launch_bounds__(PTPB) void k_kick_drift(float *__restrict__ pos,
                                                       float *__restrict__ mom, size_t np, int logn,
-                                                      const double *__restrict__ phin,
-                                                      const double *__restrict__ phi, double cphi,
+                                                      const double *__restrict__ psi_mesh,
                                                       double damp, double kick, double drift) {
     const size_t t = (size_t)blockIdx.x * PTPB + threadIdx.x;
     if (t >= np) return;
@@ -146,7 +156,7 @@ __global__ __launch_bounds__(PTPB) void k_kick_drift(float *__restrict__ pos,
     double g[3] = {0.0, 0.0, 0.0};
     auto psi = [&](int i, int j, int k) {
         const size_t idx = ((size_t)(k & nm1) << (2 * logn)) + ((size_t)(j & nm1) << logn) + (i & nm1);
-        return phin[idx] + cphi * phi[idx];
+        return psi_mesh[idx];
     };
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -261,8 +271,10 @@ mg_status mg_pm_step(const mg_pm_params *par, float *pos, float *mom, double *ph
     const double kick = par->da / (a * E);
     const double drift = par->da / (ah * ah * ah * Eh);
     const size_t np = (size_t)par->n_part * par->n_part * par->n_part;
-    k_kick_drift<<<nb(np), PTPB, 0, stream>>>(pos, mom, np, ilog2(n), phi_newton, phi, 0.5, 1.0,
-                                              kick, drift);
+    // the CIC workspace (ncell 64-bit words) holds the total potential now
+    double *psi = reinterpret_cast<double *>(counts);
+    k_total_potential<<<nb(ncell), PTPB, 0, stream>>>(phi_newton, phi, 0.5, psi, ncell);
+    k_kick_drift<<<nb(np), PTPB, 0, stream>>>(pos, mom, np, ilog2(n), psi, 1.0, kick, drift);
     if (hipGetLastError() != hipSuccess) return MG_ERR_HIP;
     if (hipStreamSynchronize(stream) != hipSuccess) return MG_ERR_HIP;
     if (pst.status == MG_NOT_CONVERGED && rc == MG_OK) rc = MG_NOT_CONVERGED;
@@ -306,8 +318,9 @@ mg_status mg_pm_step_kmouflage(const mg_pm_kmo_params *par, float *pos, float *m
     const double drift = par->da / (ah * ah * ah * par->e_half);
     const double damp = 1.0 - K.beta * par->dphibar_da * par->da;
     const size_t np = (size_t)par->n_part * par->n_part * par->n_part;
-    k_kick_drift<<<nb(np), PTPB, 0, stream>>>(pos, mom, np, ilog2(n), phi_newton, phi,
-                                              K.beta * ctil, damp, kick, drift);
+    double *psi = reinterpret_cast<double *>(counts);
+    k_total_potential<<<nb(ncell), PTPB, 0, stream>>>(phi_newton, phi, K.beta * ctil, psi, ncell);
+    k_kick_drift<<<nb(np), PTPB, 0, stream>>>(pos, mom, np, ilog2(n), psi, damp, kick, drift);
     if (hipGetLastError() != hipSuccess) return MG_ERR_HIP;
     if (hipStreamSynchronize(stream) != hipSuccess) return MG_ERR_HIP;
     if (pst.status == MG_NOT_CONVERGED && rc == MG_OK) rc = MG_NOT_CONVERGED;
