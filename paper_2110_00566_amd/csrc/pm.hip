@@ -82,12 +82,27 @@ __global__ __launch_bounds__(PTPB) void k_cic_gather(const float *__restrict__ p
     const int x0 = bx * CGX, y0 = by * CGY, z0 = bz * CGZ;
     for (int q = threadIdx.x; q < CG_CELLS; q += PTPB) acc[q] = 0ull;
     __syncthreads();
-    for (int q = threadIdx.x; q < CG_LISTS; q += PTPB) {
+    // the heads of a thread's lists are loaded together, then walked
+    constexpr int NR = (CG_LISTS + PTPB - 1) / PTPB;
+    int hd[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int q = threadIdx.x + r * PTPB;
+        hd[r] = -1;
+        if (q < CG_LISTS) {
+            const int lx = q % (CGX + 1) - 1, ly = (q / (CGX + 1)) % (CGY + 1) - 1,
+                      lz = q / ((CGX + 1) * (CGY + 1)) - 1;
+            const size_t L = ((size_t)((z0 + lz) & nm1) << (2 * logn)) +
+                             ((size_t)((y0 + ly) & nm1) << logn) + (size_t)((x0 + lx) & nm1);
+            hd[r] = head[L];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int q = threadIdx.x + r * PTPB;
         const int lx = q % (CGX + 1) - 1, ly = (q / (CGX + 1)) % (CGY + 1) - 1,
                   lz = q / ((CGX + 1) * (CGY + 1)) - 1;   // corner in tile coordinates
-        const size_t L = ((size_t)((z0 + lz) & nm1) << (2 * logn)) +
-                         ((size_t)((y0 + ly) & nm1) << logn) + (size_t)((x0 + lx) & nm1);
-        for (int p = head[L]; p >= 0; p = next[p]) {
+        for (int p = hd[r]; p >= 0; p = next[p]) {
             double f[3];
             int i0[3];
             cic_weights(pos + 3 * (size_t)p, f, i0);
