@@ -191,6 +191,47 @@ def comparators(mg, L, C, delta, ws, par, phi_ref):
     return res
 
 
+def other_solves(mg, delta, phi_dgp):
+    """The other solves of the path on the bench density from a zero start:
+    Kmouflage (n = 3, K0 = 1, beta = 0.1, L = 512 Mpc/h) in FP64 and mixed
+    precision, and the nDGP adjoint of loss = sum(phi w) (w seeded N(0,1)) at
+    the converged bench field: cycles, ms to tol, ms per cycle."""
+    import numpy as np
+    import torch
+    import inputs
+    n = delta.shape[0]
+    res = {}
+    for name, prec in (("kmouflage_fp64", mg.MG_FP64), ("kmouflage_mixed", mg.MG_MIXED)):
+        ws = mg.workspace(n, mg.MODEL_KMOUFLAGE, False, delta.device, prec)
+        secs, st = [], None
+        for rep in range(3):
+            _, st = mg.solve_kmouflage(delta, box_mpch=BOX, n_k=3, k0=1.0, beta=0.1, ws=ws,
+                                       tol=TOL, max_cycles=60, precision=prec)
+            if rep:
+                secs.append(st["seconds"])
+        assert st["status"] == 0 and st["eps"] <= TOL, (name, st["status"])
+        ms = 1e3 * float(np.mean(secs))
+        res[name] = {"cycles": st["cycles"], "time_to_tol_ms": ms, "ms_per_cycle": ms / st["cycles"]}
+        del ws
+        torch.cuda.empty_cache()
+    w = torch.from_numpy(inputs.gaussian_weights(n, 3)).to(delta.device)
+    ws = mg.workspace(n, mg.MODEL_DGP, True, delta.device)
+    par = mg.dgp_params(A, OMEGA_M, H0RC)
+    secs, st = [], None
+    for rep in range(3):
+        _, _, st = mg.solve_adjoint(mg.MODEL_DGP, par, delta, phi_dgp, w, ws=ws, tol=TOL,
+                                    max_cycles=60)
+        if rep:
+            secs.append(st["seconds"])
+    assert st["status"] == 0, st["status"]
+    ms = 1e3 * float(np.mean(secs))
+    res["adjoint_dgp_fp64"] = {"cycles": st["cycles"], "time_to_tol_ms": ms,
+                               "ms_per_cycle": ms / st["cycles"]}
+    del ws, w
+    torch.cuda.empty_cache()
+    return res
+
+
 def pm_steps(mg, pos0, dev, steps=3):
     """Particle-mesh steps of both models on the bench workload (512^3 mesh,
     256^3 particles, L = 512 Mpc/h) from a = 0.5, da = 0.01: CIC, Newtonian
@@ -369,6 +410,7 @@ def main():
                     "max_rel_diff_phi_vs_fp64": err}
     out["cycle_types"] = cycle_types(mg, L, C, delta, ws, par, phi64)
     out["comparators"] = comparators(mg, L, C, delta, ws, par, phi64)
+    out["other_solves"] = other_solves(mg, delta, phi64)
     del ws_mix, ws
     torch.cuda.empty_cache()
     out["vcycle_512"] = vcycle_time(mg, L, C, delta)
