@@ -170,9 +170,11 @@ __device__ __forceinline__ void block_sum2(double a, double b, double *partials,
 // Residual d = (faces - 6u)/h^2 - K - f (double arithmetic) at the 8 children
 // of coarse cell t, restricted (8-cell mean) together with u.  With REDUCE
 // the sums of d and d^2 accumulate into s1, s2 (finest level: norm and mean).
-// UNR: unroll of the loop over the 8 children (the single-workgroup tail
-// keeps it rolled, to stay within its 128 registers per lane).
-template <int OP, bool REDUCE, typename R, int UNR = 8>
+// The loop over the 8 children stays rolled (UNR = 1): unrolled, the adjoint
+// and Kmouflage terms need 450-512 registers per lane (one wave per SIMD,
+// with spills; the adjoint residual took 11.8 ms at 512^3, 3.8 ms rolled) and
+// the single-workgroup tail spills at its 128-register cap.
+template <int OP, bool REDUCE, typename R, int UNR = 1>
 __device__ __forceinline__ void dev_resid_restrict(const Mod &M, const LvlT<R> &L, const Coefs &Cf,
                                                    const double *fptr, double fscale, R *ru0,
                                                    R *ru1, R *rd0, R *rd1,
@@ -558,7 +560,7 @@ __device__ __forceinline__ void tail_restrict(const Mod &M, TailLv<R> (&T)[NL],
     double s1 = 0.0, s2 = 0.0;
     const int ncoarse = 1 << (3 * Tc.L.logn);
     for (int t = threadIdx.x; t < ncoarse; t += TAIL_THREADS)
-        dev_resid_restrict<OP, false, R, 1>(M, T[l].L, Cf[l], nullptr, 0.0, Tc.ru0, Tc.ru1,
+        dev_resid_restrict<OP, false, R>(M, T[l].L, Cf[l], nullptr, 0.0, Tc.ru0, Tc.ru1,
                                          const_cast<R *>(Tc.L.f0), const_cast<R *>(Tc.L.f1),
                                          nullptr, (size_t)t, s1, s2);
     __syncthreads();
