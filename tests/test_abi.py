@@ -127,3 +127,15 @@ def test_product_does_not_import_the_oracle():
     for f in list(pkg.rglob("*.py")) + list(pkg.rglob("*.hip")) + list(pkg.rglob("*.h")):
         txt = f.read_text()
         assert "import oracle" not in txt and "from oracle" not in txt and "mg_oracle" not in txt
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # one GPU only: --gpus N > 1 exits with a message before touching a device
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
