@@ -9,7 +9,27 @@
 
 #include "../../include/mgglam.h"
 
+namespace mgglam_internal {
+void set_error(const char *msg);   // mg_last_error() of the library
+}
+
 namespace {
+
+mg_status fail(mg_status s, const char *msg) {
+    mgglam_internal::set_error(msg);
+    return s;
+}
+
+// status of the launches enqueued so far (and, with sync, of their execution)
+mg_status hip_status(hipStream_t stream, bool sync) {
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && sync) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        const std::string m = std::string("HIP: ") + hipGetErrorString(e);
+        return fail(MG_ERR_HIP, m.c_str());
+    }
+    return MG_OK;
+}
 
 constexpr int PTPB = 256;
 constexpr double FIX_SCALE = 4294967296.0;   // 2^32 fixed-point units per particle
@@ -218,12 +238,12 @@ mg_status cic(int n_mesh, int n_part, const float *pos, double *delta, unsigned 
         k_cic_link<<<nb(np), PTPB, 0, s>>>(pos, (int)np, logn, head, next);
         k_cic_gather<<<(unsigned)(ncell / CG_CELLS), PTPB, 0, s>>>(pos, logn, head, next, scale,
                                                                   delta);
-        return hipGetLastError() == hipSuccess ? MG_OK : MG_ERR_HIP;
+        return hip_status(s, false);
     }
     k_zero_u64<<<nb(ncell), PTPB, 0, s>>>(counts, ncell);
     k_cic<<<nb(np), PTPB, 0, s>>>(pos, np, logn, counts);
     k_counts_to_delta<<<nb(ncell), PTPB, 0, s>>>(counts, ncell, scale, delta);
-    return hipGetLastError() == hipSuccess ? MG_OK : MG_ERR_HIP;
+    return hip_status(s, false);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -241,26 +261,32 @@ size_t mg_pm_workspace_bytes(int n_mesh) {
 
 mg_status mg_cic_delta(int n_mesh, int n_part, const float *pos, double *delta, void *ws,
                        size_t ws_bytes, hipStream_t stream) {
-    if (!pow2(n_mesh) || n_mesh < 8 || n_mesh > 2048 || n_part < 1 || n_part > 2048 || !pos ||
-        !delta)
-        return MG_ERR_ARG;
+    mgglam_internal::set_error("");
+    if (!pow2(n_mesh) || n_mesh < 8 || n_mesh > 2048)
+        return fail(MG_ERR_ARG, "n_mesh must be a power of two in [8, 2048]");
+    if (n_part < 1 || n_part > 2048) return fail(MG_ERR_ARG, "n_part must be in [1, 2048]");
+    if (!pos || !delta) return fail(MG_ERR_ARG, "pos and delta must be device pointers");
     const size_t need = (size_t)n_mesh * n_mesh * n_mesh * sizeof(unsigned long long);
-    if (!ws || ws_bytes < need) return MG_ERR_WORKSPACE;
+    if (!ws || ws_bytes < need) return fail(MG_ERR_WORKSPACE, "workspace is NULL or too small");
     mg_status rc = cic(n_mesh, n_part, pos, delta, (unsigned long long *)ws, stream);
     if (rc != MG_OK) return rc;
-    return hipStreamSynchronize(stream) == hipSuccess ? MG_OK : MG_ERR_HIP;
+    return hip_status(stream, true);
 }
 
 mg_status mg_pm_step(const mg_pm_params *par, float *pos, float *mom, double *phi,
                      double *phi_newton, double *delta_out, void *ws, size_t ws_bytes,
                      hipStream_t stream, mg_stats *stats) {
-    if (!par || !pos || !mom || !phi || !phi_newton || !delta_out || !stats) return MG_ERR_ARG;
+    mgglam_internal::set_error("");
+    if (!par || !pos || !mom || !phi || !phi_newton || !delta_out || !stats)
+        return fail(MG_ERR_ARG, "a parameter, array or stats pointer is NULL");
     const int n = par->n_mesh;
-    if (!pow2(n) || n < 8 || n > 2048 || par->mg.n != n || par->n_part < 1 || par->n_part > 2048 ||
-        !(par->a > 0.0) || !std::isfinite(par->da) || !(par->omega_m > 0.0) || !(par->omega_m < 1.0))
-        return MG_ERR_ARG;
+    if (!pow2(n) || n < 8 || n > 2048 || par->mg.n != n)
+        return fail(MG_ERR_ARG, "n_mesh must be a power of two in [8, 2048] equal to mg.n");
+    if (par->n_part < 1 || par->n_part > 2048 || !(par->a > 0.0) || !std::isfinite(par->da) ||
+        !(par->omega_m > 0.0) || !(par->omega_m < 1.0))
+        return fail(MG_ERR_ARG, "invalid n_part, a, da or omega_m");
     const size_t need = mg_pm_workspace_bytes(n);
-    if (!ws || ws_bytes < need) return MG_ERR_WORKSPACE;
+    if (!ws || ws_bytes < need) return fail(MG_ERR_WORKSPACE, "workspace is NULL or too small");
     const size_t ncell = (size_t)n * n * n;
     unsigned long long *counts = (unsigned long long *)ws;
     char *solver_ws = (char *)ws + align256(ncell * sizeof(unsigned long long));
@@ -290,8 +316,8 @@ mg_status mg_pm_step(const mg_pm_params *par, float *pos, float *mom, double *ph
     double *psi = reinterpret_cast<double *>(counts);
     k_total_potential<<<nb(ncell), PTPB, 0, stream>>>(phi_newton, phi, 0.5, psi, ncell);
     k_kick_drift<<<nb(np), PTPB, 0, stream>>>(pos, mom, np, ilog2(n), psi, 1.0, kick, drift);
-    if (hipGetLastError() != hipSuccess) return MG_ERR_HIP;
-    if (hipStreamSynchronize(stream) != hipSuccess) return MG_ERR_HIP;
+    const mg_status hs = hip_status(stream, true);
+    if (hs != MG_OK) return hs;
     if (pst.status == MG_NOT_CONVERGED && rc == MG_OK) rc = MG_NOT_CONVERGED;
     return rc;
 }
@@ -299,16 +325,20 @@ mg_status mg_pm_step(const mg_pm_params *par, float *pos, float *mom, double *ph
 mg_status mg_pm_step_kmouflage(const mg_pm_kmo_params *par, float *pos, float *mom, double *phi,
                                double *phi_newton, double *delta_out, void *ws, size_t ws_bytes,
                                hipStream_t stream, mg_stats *stats) {
-    if (!par || !pos || !mom || !phi || !phi_newton || !delta_out || !stats) return MG_ERR_ARG;
+    mgglam_internal::set_error("");
+    if (!par || !pos || !mom || !phi || !phi_newton || !delta_out || !stats)
+        return fail(MG_ERR_ARG, "a parameter, array or stats pointer is NULL");
     const int n = par->n_mesh;
     const mg_kmo_params &K = par->kmo;
-    if (!pow2(n) || n < 8 || n > 2048 || par->mg.n != n || par->n_part < 1 || par->n_part > 2048 ||
-        !(par->a > 0.0) || !std::isfinite(par->da) || K.a != par->a || !(par->e_a > 0.0) ||
-        !(par->e_half > 0.0) || !std::isfinite(par->dphibar_da) || !(K.box_mpch > 0.0) ||
-        !(K.omega_m > 0.0) || !(K.omega_m < 1.0))
-        return MG_ERR_ARG;
+    if (!pow2(n) || n < 8 || n > 2048 || par->mg.n != n)
+        return fail(MG_ERR_ARG, "n_mesh must be a power of two in [8, 2048] equal to mg.n");
+    if (par->n_part < 1 || par->n_part > 2048 || !(par->a > 0.0) || !std::isfinite(par->da) ||
+        K.a != par->a || !(par->e_a > 0.0) || !(par->e_half > 0.0) ||
+        !std::isfinite(par->dphibar_da) || !(K.box_mpch > 0.0) || !(K.omega_m > 0.0) ||
+        !(K.omega_m < 1.0))
+        return fail(MG_ERR_ARG, "invalid n_part, a, da, background values or kmo parameters");
     const size_t need = mg_pm_workspace_bytes(n);
-    if (!ws || ws_bytes < need) return MG_ERR_WORKSPACE;
+    if (!ws || ws_bytes < need) return fail(MG_ERR_WORKSPACE, "workspace is NULL or too small");
     const size_t ncell = (size_t)n * n * n;
     unsigned long long *counts = (unsigned long long *)ws;
     char *solver_ws = (char *)ws + align256(ncell * sizeof(unsigned long long));
@@ -336,8 +366,8 @@ mg_status mg_pm_step_kmouflage(const mg_pm_kmo_params *par, float *pos, float *m
     double *psi = reinterpret_cast<double *>(counts);
     k_total_potential<<<nb(ncell), PTPB, 0, stream>>>(phi_newton, phi, K.beta * ctil, psi, ncell);
     k_kick_drift<<<nb(np), PTPB, 0, stream>>>(pos, mom, np, ilog2(n), psi, damp, kick, drift);
-    if (hipGetLastError() != hipSuccess) return MG_ERR_HIP;
-    if (hipStreamSynchronize(stream) != hipSuccess) return MG_ERR_HIP;
+    const mg_status hs = hip_status(stream, true);
+    if (hs != MG_OK) return hs;
     if (pst.status == MG_NOT_CONVERGED && rc == MG_OK) rc = MG_NOT_CONVERGED;
     return rc;
 }

@@ -139,3 +139,20 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_pm_entry_points_reject_bad_arguments_with_a_message(L):
+    d = C.c_void_p(0x1000)
+    assert L.mg_cic_delta(24, 16, d, d, d, 1 << 40, None) == mg.MG_ERR_ARG
+    assert b"power of two" in L.mg_last_error()
+    assert L.mg_cic_delta(32, 16, d, d, None, 0, None) == mg.MG_ERR_WORKSPACE
+    assert len(L.mg_last_error()) > 0
+    par = mg.PmParams(32, 16, 0.3089, 1.0, 1.0, 0.01, mg.make_opts(16))
+    st = mg.Stats()
+    assert L.mg_pm_step(C.byref(par), d, d, d, d, d, d, 1 << 40, None, C.byref(st)) == mg.MG_ERR_ARG
+    assert b"mg.n" in L.mg_last_error()
+    kp = mg.PmKmoParams(32, 16, 0.5, 0.01, mg.kmo_params(32, 64.0, a=0.7), 1.0, 1.0, 0.0,
+                        mg.make_opts(32))
+    assert L.mg_pm_step_kmouflage(C.byref(kp), d, d, d, d, d, d, 1 << 40, None,
+                                  C.byref(st)) == mg.MG_ERR_ARG
+    assert b"kmo parameters" in L.mg_last_error()
