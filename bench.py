@@ -269,19 +269,44 @@ def pm_steps(mg, pos0, dev, steps=3):
     return res
 
 
-def vcycle_1024(mg, L, C, dev):
+def vcycle_1024(mg, L, C, pos):
     """FP64 V-cycle on a 1024^3 mesh: CIC of 512^3 Zel'dovich particles
     (L = 1 Gpc/h)."""
     import torch
-
-    import inputs
-    pos = torch.from_numpy(inputs.za_particles(512, 1024, 5)).to(dev)
     delta = mg.cic_delta(pos, 1024)
-    del pos
     r = vcycle_time(mg, L, C, delta)
     del delta
     torch.cuda.empty_cache()
     return r
+
+
+def pm_step_1024(mg, dev, pos, steps=2):
+    """nDGP PM steps on the full-size PM configuration: 1024^3 mesh, 512^3
+    Zel'dovich particles (pos, moved in place), L = 1 Gpc/h, a = 1,
+    da = 0.0063, fields to 1e-8 (warm-started after the first step)."""
+    import numpy as np
+    import torch
+    n = 1024
+    mom = torch.zeros_like(pos)
+    phi = torch.zeros((n,) * 3, dtype=torch.float64, device=dev)
+    phin = torch.zeros_like(phi)
+    ws = torch.empty(mg.lib().mg_pm_workspace_bytes(n), dtype=torch.uint8, device=dev)
+    a, da, times, cycles = 1.0, 0.0063, [], []
+    for s in range(steps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = mg.pm_step(pos, mom, phi, phin, n, a, da, h0rc=H0RC, ws=ws, tol=TOL)
+        torch.cuda.synchronize()
+        assert st["status"] >= 0
+        if s:
+            times.append(time.perf_counter() - t0)
+            cycles.append(st["cycles"])
+        a += da
+    del pos, mom, phi, phin, ws
+    torch.cuda.empty_cache()
+    return {"ms_per_step": 1e3 * float(np.mean(times)),
+            "scalar_cycles_per_step": float(np.mean(cycles)),
+            "config": "1024^3 mesh, 512^3 particles, L=1 Gpc/h, a=1, da=0.0063, tol=1e-8"}
 
 
 def main():
@@ -416,7 +441,10 @@ def main():
     out["vcycle_512"] = vcycle_time(mg, L, C, delta)
     out["pm_steps"] = pm_steps(mg, pos, dev)
     if not args.no_big:
-        out["vcycle_1024"] = vcycle_1024(mg, L, C, dev)
+        pos1024 = torch.from_numpy(inputs.za_particles(512, 1024, 5)).to(dev)
+        out["vcycle_1024"] = vcycle_1024(mg, L, C, pos1024)
+        out["pm_step_1024"] = pm_step_1024(mg, dev, pos1024)
+        del pos1024
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(pos_np)
     print(json.dumps(out), flush=True)
