@@ -185,8 +185,9 @@ mg_status mg_solve_dgp(const mg_opts *opts, const mg_dgp_params *par, const doub
  * dL_N/du = -(6/h^2)(1 + 4 D / (3 alpha)) -- the iteration Sec. 3.2.3
  * replaces.  Same FAS cycles, transfers, bordering and gauge as mg_solve_dgp;
  * stats.eps is the RMS of the mean-projected L_N residual (equal to the
- * mg_solve_dgp residual to first order in Sigma/alpha^2).  FP64 only, untiled
- * kernels at every level; same arguments as mg_solve_dgp. */
+ * mg_solve_dgp residual to first order in Sigma/alpha^2).  FP64 only; the same
+ * kernels as mg_solve_dgp (LDS-tiled on levels >= 128^3) with the Newton step
+ * in place of the closed form; same arguments as mg_solve_dgp. */
 mg_status mg_solve_dgp_newton(const mg_opts *opts, const mg_dgp_params *par, const double *delta,
                               double *phi, void *ws, size_t ws_bytes, hipStream_t stream,
                               mg_stats *stats);

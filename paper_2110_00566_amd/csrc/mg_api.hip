@@ -204,7 +204,7 @@ unsigned nblocks(size_t threads) { return (unsigned)((threads + TPB - 1) / TPB);
 bool tiled_level(int n) { return n >= 128; }
 
 // The tiled kernels implement the closed-form update only.
-constexpr bool tiled_op(int OP) { return OP != OP_ADJ && OP != OP_NEWTON; }
+constexpr bool tiled_op(int OP) { return OP != OP_ADJ; }
 
 // z-planes per block so that a launch has ~4096 blocks (at least 4 planes).
 TileGeom tile_geom(int n, int planes) {

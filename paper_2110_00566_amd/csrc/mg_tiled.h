@@ -70,6 +70,33 @@ __device__ __forceinline__ NbT<T> lds_nb(const R *Am, const R *A0, const R *Ap, 
     return s;
 }
 
+// Non-Laplacian term of the tiled kernels at a cell with face sum faces and
+// centre value u.  OP_NEWTON (the Newton-GS comparator) works on the
+// quadratic form: Sigma/alpha - 2 D^2/(3 alpha), D = (faces - 6u)/h^2.
+template <int OP, typename T, typename L_>
+__device__ __forceinline__ T tiled_term(const Mod &M, const L_ &L, const NbT<T> &s, T delta,
+                                        T faces, T u, unsigned long long *clamp) {
+    if constexpr (OP == OP_NEWTON)
+        return newton_term<T>(M, dgp_sigma_over_alpha<T>(M, L, s, delta),
+                              (faces - (T)6 * u) / (T)L.h2);
+    else
+        return model_term<OP, T>(M, L, s, delta, clamp);
+}
+
+// New value of a cell in a colour pass: the closed-form update, or for
+// OP_NEWTON the Newton-Gauss-Seidel step on the quadratic form.
+template <int OP, typename R, typename L_>
+__device__ __forceinline__ R tiled_update(const Mod &M, const L_ &L, const NbT<R> &s, R delta,
+                                          R faces, R u, R f, unsigned long long *clamp) {
+    if constexpr (OP == OP_NEWTON) {
+        return newton_update<R>(M, u, faces, dgp_sigma_over_alpha<R>(M, L, s, delta), f,
+                                (R)L.h2);
+    } else {
+        const R K = model_term<OP, R>(M, L, s, delta, clamp);
+        return (faces - (R)L.h2 * (K + f)) * (R)(1.0 / 6.0);
+    }
+}
+
 // One colour pass (see k_pass) on an LDS-staged tile.
 template <int OP, typename R>
 __global__ __launch_bounds__(TPB) void k_pass_tiled(Mod M, LvlT<R> L, int c, R *__restrict__ out,
@@ -145,11 +172,11 @@ __global__ __launch_bounds__(TPB) void k_pass_tiled(Mod M, LvlT<R> L, int c, R *
             const NbT<R> s = lds_nb<R, R>(sA[sm], sA[s0], sA[sp], sB[s0], sB[sm], sB[sp], row + 1,
                                           tx + 1, p);
             const R faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
-            const R K = model_term<OP, R>(M, L, s, h ? d1 : d0, clamp);
             const R f = (h ? f1 : f0) + fs;
+            const R nv = tiled_update<OP, R>(M, L, s, h ? d1 : d0, faces,
+                                             sA[s0][(row + 1) * TXH + tx + 1], f, clamp);
             // streamed: the next reader is a later launch
-            __builtin_nontemporal_store((faces - (R)L.h2 * (K + f)) * (R)(1.0 / 6.0),
-                                        ptr(out, plane_off<R>(k, L.logn, L.lognh), coff[h]));
+            __builtin_nontemporal_store(nv, ptr(out, plane_off<R>(k, L.logn, L.lognh), coff[h]));
         }
         __syncthreads();
     }
@@ -259,7 +286,8 @@ __global__ __launch_bounds__(TPB) void k_resid_restrict_tiled(Mod M, LvlT<R> L, 
                 const double faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
                 const double f = (HASF ? (double)fc[2 * b + c] : 0.0) + fs;
                 const double d = (faces - 6.0 * u) * inv_h2 -
-                                 model_term<OP, double>(M, L, s, (double)dc[2 * b + c], clamp) - f;
+                                 tiled_term<OP, double>(M, L, s, (double)dc[2 * b + c], faces, u,
+                                                        clamp) - f;
                 sd += d;
                 su += u;
                 if (REDUCE) {
@@ -538,10 +566,10 @@ __global__ __launch_bounds__(TPB) void k_prolong_pass_tiled(Mod M, LvlT<R> L, R 
                                           tx + 1, p);
             const size_t pl = plane_off<R>(k, L.logn, L.lognh);
             const R faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
-            const R K = model_term<OP, R>(M, L, s, h ? d1 : d0, clamp);
             const R f = (h ? f1 : f0) + fs;
-            __builtin_nontemporal_store((faces - (R)L.h2 * (K + f)) * (R)(1.0 / 6.0),
-                                        ptr(out0, pl, coff[h]));
+            const R nv = tiled_update<OP, R>(M, L, s, h ? d1 : d0, faces,
+                                             sA[s0][(row + 1) * TXH + tx + 1], f, clamp);
+            __builtin_nontemporal_store(nv, ptr(out0, pl, coff[h]));
             __builtin_nontemporal_store(sB[s0][(row + 1) * TXH + tx + 1], ptr(out1, pl, coff[h]));
         }
         if (cnew) interp(xnx);
@@ -624,7 +652,7 @@ __global__ __launch_bounds__(TPB) void k_coarse_source_tiled(Mod M, LvlT<R> Lc, 
             R *S = ptr(c ? s1 : s0, pl, o);
             const double rd = (double)*S - sh;
             *S = (R)((faces - 6.0 * (double)ru) / Lc.h2
-                     - model_term<OP, double>(M, Lc, s, delta, nullptr) - rd);
+                     - tiled_term<OP, double>(M, Lc, s, delta, faces, (double)ru, nullptr) - rd);
             *ptr(c ? u1 : u0, pl, o) = ru;
         }
         __syncthreads();
