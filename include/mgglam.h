@@ -98,7 +98,9 @@ typedef struct {
     double pass_ms_avg;         /* mean finest colour-pass duration (profile=1) */
     int pass_count;             /* number of timed finest colour passes */
     int cycles_fp32;            /* MG_MIXED, MG_FP32: cycles in FP32 storage (included in cycles) */
-    double eps_fp32;            /* MG_MIXED, MG_FP32: residual at the end of the FP32 cycles */
+    double eps_fp32;            /* MG_FP32: residual at the end of the FP32 cycles; MG_MIXED:
+                                   the last in-cycle residual of the FP32 phase (a stall
+                                   hands over to FP64 without a separate evaluation) */
     double level_ms[MG_LEVELS]; /* profile=1: GPU time of the cycles' work on each level
                                    (0 = finest), summed over all cycles and both precisions;
                                    the levels of the single-workgroup tail (<= 16^3) are

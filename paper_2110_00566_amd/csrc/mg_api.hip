@@ -559,14 +559,20 @@ struct Solver {
     // until the residual is <= tol (confirmed by a residual evaluation of the
     // post-smoothed field), max_cycles, or -- with stall > 0 -- until a cycle
     // reduces the in-cycle residual by less than the factor stall.  Cycle
-    // residuals go to hist[hist0 ...].
+    // residuals go to hist[hist0 ...].  With eps_in >= 0 the initial residual
+    // evaluation is skipped (eps_in stands for it and mu keeps its value);
+    // with confirm_stall false a stall ends the phase without a final
+    // residual evaluation (eps is then the last in-cycle residual).
     mg_status run(double tol, int max_cycles, double stall, mg_stats *st, int hist0,
-                  PhaseResult &pr) {
-        double hs[S_NSCAL];
+                  PhaseResult &pr, double eps_in = -1.0, bool confirm_stall = true) {
+        double hs[S_NSCAL] = {};
         mg_status rc;
-        resid_restrict(0);
-        if ((rc = read_scal(hs)) != MG_OK) return rc;
-        double eps = std::sqrt(hs[S_EPS2]);
+        double eps = eps_in;
+        if (eps_in < 0.0) {
+            resid_restrict(0);
+            if ((rc = read_scal(hs)) != MG_OK) return rc;
+            eps = std::sqrt(hs[S_EPS2]);
+        }
         pr.eps0 = eps;
         pr.eps = eps;
         if (!std::isfinite(eps)) {
@@ -594,6 +600,10 @@ struct Solver {
                 if (em < best) best = em;
                 const bool stalled = stall > 0.0 && em > stall * prev;
                 prev = em;
+                if (stalled && !confirm_stall && em > tol) {
+                    eps = em;
+                    break;
+                }
                 if (em <= tol || cyc == max_cycles || stalled) {
                     resid_restrict(0);
                     if ((rc = read_scal(hs)) != MG_OK) return rc;
@@ -730,7 +740,8 @@ mg_status forward_solve(const mg_opts *o, const Mod &M, const double *delta, dou
         k_pack<double, float><<<nblocks(2 * G.half), TPB, 0, C.st>>>(phi, G.logn, G.u[0], G.u[1],
                                                                      nullptr);
         Solver<OP, float> S32(C);
-        mg_status rc = S32.run(o->tol, o->max_cycles, 0.5, st, 0, p32);
+        // a stall hands over to FP64 without a confirming FP32 residual
+        mg_status rc = S32.run(o->tol, o->max_cycles, 0.5, st, 0, p32, -1.0, false);
         if (rc != MG_OK) return rc;
         if (p32.status < 0) {
             st->status = p32.status;
@@ -748,7 +759,11 @@ mg_status forward_solve(const mg_opts *o, const Mod &M, const double *delta, dou
     // FP64 cycles (the whole solve, or the finish of the mixed one)
     density_hierarchy<double>(C, delta);
     Solver<OP, double> S(C);
-    mg_status rc = S.run(o->tol, o->max_cycles - cycles32, 0.0, st, cycles32, p64);
+    // after an FP32 stall the FP64 cycles start without a separate residual
+    // evaluation (mu from the FP32 phase; the first FP64 cycle refreshes it)
+    const double eps_in = (mixed && p32.status == MG_NOT_CONVERGED && p32.eps > o->tol &&
+                           cycles32 < o->max_cycles) ? p32.eps : -1.0;
+    mg_status rc = S.run(o->tol, o->max_cycles - cycles32, 0.0, st, cycles32, p64, eps_in);
     if (rc != MG_OK) return rc;
     st->cycles = cycles32 + p64.cycles;
     st->eps0 = mixed ? p32.eps0 : p64.eps0;
