@@ -126,7 +126,8 @@ def test_tiled_levels_fixed_cycles_parity(name, n, cycles, nu1, nu2):
 
 
 @pytest.mark.parametrize("cycle", [mg.CYCLE_F, mg.CYCLE_W])
-@pytest.mark.parametrize("name,n", [("dgp", 32), ("kmo3", 32), ("dgp", 128), ("dgp_h05", 64)])
+@pytest.mark.parametrize("name,n", [("dgp", 32), ("kmo3", 32), ("dgp", 128), ("dgp_h05", 64),
+                                    ("kmo3", 128)])
 def test_f_and_w_cycles_fixed_cycles_parity(name, n, cycle):
     # F- and W-cycle arrangements (Sec. 3.2.1): the host recursion on the
     # per-level kernels and the recursion inside the single-workgroup tail
