@@ -183,7 +183,8 @@ def test_newton_comparator_operations_parity(n, h):
 
 @pytest.mark.parametrize("n,cycles,cycle,sigma", [(32, 3, mg.CYCLE_V, 1.0),
                                                   (128, 2, mg.CYCLE_V, 0.5),
-                                                  (32, 2, mg.CYCLE_W, 1.0)])
+                                                  (32, 2, mg.CYCLE_W, 1.0),
+                                                  (128, 2, mg.CYCLE_F, 0.5)])
 def test_newton_comparator_fixed_cycles_parity(n, cycles, cycle, sigma):
     delta = inputs.lognormal_delta(n, 3, sigma)
     r = oracle.solve(oracle.dgp_newton_model(1.0, OM, 1.0), delta, tol=0.0, max_cycles=cycles,
