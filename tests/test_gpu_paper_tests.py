@@ -1,0 +1,95 @@
+"""The paper's code tests (Sec. 4.2) run directly on the GPU solver at sizes
+that use the LDS-tiled kernels, against their exact discrete or analytic
+solutions (not through the oracle): the 1D sine tests of both models and the
+nDGP top-hat profile."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import inputs
+import paper_2110_00566_amd as mg
+from oracle import pins
+
+pytestmark = pytest.mark.gpu
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_tests.json")))
+OM = GOLD["cosmology"]["omega_m"]
+
+
+def g(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def c(t):
+    return t.detach().cpu().numpy()
+
+
+def beta_dgp(a, h0rc):
+    # eq:beta_dgp with the LCDM H of eq:H_lcdm (H0 = c = 1)
+    e2 = OM / a ** 3 + 1.0 - OM
+    return 1.0 + 2.0 * np.sqrt(e2) * h0rc * (1.0 - 0.5 * OM / a ** 3 / e2)
+
+
+@pytest.mark.parametrize("n", [128, 256])
+def test_paper_dgp_sine_exact_on_gpu(n):
+    # eq:sine_nDGP: the discrete solution is the analytic amplitude 1/(4 pi^2)
+    # times (pi/N)^2 / sin^2(pi/N)
+    amp = GOLD["sine_test"]["nDGP_phi_amplitude"]
+    delta = pins.dgp_sine_delta_paper(n, beta_dgp(1.0, 1.0))
+    phi, st = mg.solve_dgp(g(delta), tol=1e-13, max_cycles=80)
+    exact = pins.dgp_sine_phi_discrete(n)
+    exact -= exact.mean()
+    assert st["status"] == 0
+    assert np.abs(c(phi) - exact).max() <= 1e-9 * np.abs(exact).max()
+    assert np.abs(c(phi) - pins.sine_1d(n, amp)).max() <= 2 * (np.pi / n) ** 2 * amp
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_dgp_nonlinear_sine_exact_on_gpu(axis):
+    # large amplitude (the branch sqrt(D) = alpha + 4 D_xx/3 of the root); the
+    # amplitude scales with n^2 to keep the second difference of the 32^3 test
+    n = 128
+    phi = pins.sine_1d(n, 20.0 * (n / 32) ** 2, 1, axis)
+    delta = pins.dgp_sine_delta_discrete(phi, beta_dgp(1.0, 1.0), axis=axis)
+    out, st = mg.solve_dgp(g(delta), tol=1e-11, max_cycles=80)
+    phi -= phi.mean()
+    assert st["status"] == 0
+    assert np.abs(c(out) - phi).max() <= 1e-9 * np.abs(phi).max()
+
+
+@pytest.mark.parametrize("nk,amp", [(2, GOLD["sine_test"]["kmo_A"]), (2, 2.0), (3, 2.0)])
+def test_kmo_sine_exact_on_gpu(nk, amp):
+    # Sec. 4.2.2 with the exact discrete source of the prescribed phi; the
+    # amplitude scales with n to keep the gradients of the 32^3, 64 Mpc/h test
+    n, box = 128, 256.0
+    k0, beta, waves = GOLD["sine_test"]["kmo_K0"], GOLD["sine_test"]["kmo_beta"], GOLD["sine_test"]["kmo_K"]
+    p = pins.kmo_params(n, box, nk, k0, beta)
+    phi = pins.sine_1d(n, amp * n / 32, waves)
+    delta = pins.kmo_sine_delta_discrete(phi, p)
+    out, st = mg.solve_kmouflage(g(delta), box_mpch=box, n_k=nk, k0=k0, beta=beta, tol=1e-12,
+                                 max_cycles=80)
+    phi -= phi.mean()
+    assert st["status"] == 0
+    assert np.abs(c(out) - phi).max() <= 1e-9 * np.abs(phi).max()
+
+
+@pytest.mark.parametrize("h0rc", GOLD["sphere_test_dgp"]["h0rc"])
+def test_dgp_sphere_profile_on_gpu(h0rc):
+    # Sec. 4.2.3 top-hat (delta = 0.5, R = 0.1 N): the radial derivative along
+    # the x axis through the centre against the analytic profile (reading of
+    # the printed R_c as R_c^2); periodic images and the subtracted mean
+    # shift it, so the shape is compared to 15% near the sphere
+    n = 128
+    R = GOLD["sphere_test_dgp"]["radius_over_N"] * n
+    dl = GOLD["sphere_test_dgp"]["delta"]
+    d = inputs.tophat_delta(n, dl, R)
+    phi, st = mg.solve_dgp(g(d - d.mean()), h0rc=h0rc, tol=1e-10, max_cycles=100)
+    assert st["status"] == 0
+    row = c(phi)[n // 2, n // 2, :]
+    x = np.arange(n) + 0.5 - n / 2
+    dphi = (np.roll(row, -1) - np.roll(row, 1)) / 2.0
+    sel = (x > 1.0) & (x < 1.5 * R)
+    ana = pins.dgp_sphere_dphidr(x[sel], dl, R, beta_dgp(1.0, h0rc), h0rc)
+    assert np.abs(dphi[sel] - ana).max() <= 0.15 * np.abs(ana).max()
