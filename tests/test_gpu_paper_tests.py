@@ -1,7 +1,7 @@
 """The paper's code tests (Sec. 4.2) run directly on the GPU solver at sizes
 that use the LDS-tiled kernels, against their exact discrete or analytic
 solutions (not through the oracle): the 1D sine tests of both models and the
-nDGP top-hat profile."""
+top-hat profiles of both models."""
 import json
 import os
 
@@ -92,4 +92,27 @@ def test_dgp_sphere_profile_on_gpu(h0rc):
     dphi = (np.roll(row, -1) - np.roll(row, 1)) / 2.0
     sel = (x > 1.0) & (x < 1.5 * R)
     ana = pins.dgp_sphere_dphidr(x[sel], dl, R, beta_dgp(1.0, h0rc), h0rc)
+    assert np.abs(dphi[sel] - ana).max() <= 0.15 * np.abs(ana).max()
+
+
+@pytest.mark.parametrize("k0", GOLD["sphere_test_kmo"]["K0"])
+def test_kmo_sphere_profile_on_gpu(k0):
+    # Sec. 4.2.3 Kmouflage top-hat (delta = 5000, R = 0.1 N, n = 2, beta = 0.2)
+    # with the code-test cell size (L = 256 Mpc/h on 256 cells) at 128^3,
+    # against the paper's closed-form (Cardano) profile, shape to 15%
+    n = 128
+    box = n * GOLD["code_test_box"]["L_mpch"] / GOLD["code_test_box"]["N_g"]
+    beta = GOLD["sphere_test_kmo"]["beta"]
+    p = pins.kmo_params(n, box, 2, k0, beta)
+    R = GOLD["sphere_test_kmo"]["radius_over_N"] * n
+    dl = GOLD["sphere_test_kmo"]["delta"]
+    d = inputs.tophat_delta(n, dl, R)
+    phi, st = mg.solve_kmouflage(g(d - d.mean()), box_mpch=box, n_k=2, k0=k0, beta=beta,
+                                 tol=1e-9, max_cycles=100)
+    assert st["status"] == 0
+    row = c(phi)[n // 2, n // 2, :]
+    x = np.arange(n) + 0.5 - n / 2
+    dphi = (np.roll(row, -1) - np.roll(row, 1)) / 2.0
+    sel = (x > 1.0) & (x < 1.5 * R)
+    ana = pins.kmo_sphere_cardano_paper(x[sel], dl, R, p["gamma"], beta, p["ctil"])
     assert np.abs(dphi[sel] - ana).max() <= 0.15 * np.abs(ana).max()
