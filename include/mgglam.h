@@ -19,7 +19,8 @@
  *    MG_ERR_ARG and mg_last_error() says which.  Positive status codes mean
  *    the outputs are valid (see the stats); negative codes leave outputs
  *    unspecified.
- *  - Calls that share a workspace must not overlap in time.
+ *  - Calls that share a workspace must not overlap in time.  Workspaces
+ *    start on a 256-byte boundary (hipMalloc's and torch's allocations do).
  */
 #ifndef MGGLAM_H
 #define MGGLAM_H
@@ -39,7 +40,7 @@ typedef enum {
     MG_ERR_HIP = -2,
     MG_ERR_NONFINITE = -3,  /* residual became NaN/Inf (e.g. NaN in delta) */
     MG_ERR_DIVERGED = -4,   /* residual grew 1e3x above its minimum */
-    MG_ERR_WORKSPACE = -5   /* workspace pointer null or smaller than required */
+    MG_ERR_WORKSPACE = -5   /* workspace null, smaller than required or not 256-byte aligned */
 } mg_status;
 
 typedef enum { MG_FP64 = 0, MG_MIXED = 1, MG_FP32 = 2 } mg_precision;

@@ -718,9 +718,9 @@ mg_status forward_solve(const mg_opts *o, const Mod &M, const double *delta, dou
     Ctx C;
     Carve cv{static_cast<char *>(ws), 0};
     layout(C, cv, o->n, false, o->precision);
-    if (!ws || ws_bytes < cv.off)
-        return fail(MG_ERR_WORKSPACE, "workspace too small: need " + std::to_string(cv.off) +
-                                          " bytes");
+    if (!ws || ws_bytes < cv.off || ((uintptr_t)ws & 255))
+        return fail(MG_ERR_WORKSPACE, "workspace too small (need " + std::to_string(cv.off) +
+                                          " bytes) or not 256-byte aligned");
     C.st = stream;
     C.M = M;
     C.nu1 = o->nu_pre;
@@ -813,9 +813,9 @@ mg_status adjoint_solve(const mg_opts *o, const Mod &M, const double *delta, con
     Ctx C;
     Carve cv{static_cast<char *>(ws), 0};
     layout(C, cv, o->n, true, MG_FP64);
-    if (!ws || ws_bytes < cv.off)
-        return fail(MG_ERR_WORKSPACE, "workspace too small: need " + std::to_string(cv.off) +
-                                          " bytes");
+    if (!ws || ws_bytes < cv.off || ((uintptr_t)ws & 255))
+        return fail(MG_ERR_WORKSPACE, "workspace too small (need " + std::to_string(cv.off) +
+                                          " bytes) or not 256-byte aligned");
     C.st = stream;
     C.M = M;
     C.nu1 = o->nu_pre;
@@ -879,7 +879,8 @@ struct OpWs {
 mg_status op_layout(int n, double h, void *ws, size_t ws_bytes, OpWs &W) {
     if (!is_pow2(n) || n < 4 || n > 2048) return fail(MG_ERR_ARG, "n must be a power of two in [4, 2048]");
     if (!(h > 0.0)) return fail(MG_ERR_ARG, "h must be > 0");
-    if (!ws || ws_bytes < op_workspace_bytes(n)) return fail(MG_ERR_WORKSPACE, "workspace too small");
+    if (!ws || ws_bytes < op_workspace_bytes(n) || ((uintptr_t)ws & 255))
+        return fail(MG_ERR_WORKSPACE, "workspace too small or not 256-byte aligned");
     Carve cv{static_cast<char *>(ws), 0};
     HLevel<double> &H = W.H;
     H.n = n;
@@ -942,6 +943,7 @@ mg_status common_checks(const mg_opts *o, const void *delta, const void *phi, vo
     if (!delta || !phi) return fail(MG_ERR_ARG, "delta and phi must be device pointers");
     if (!st) return fail(MG_ERR_ARG, "stats is NULL");
     if (!ws) return fail(MG_ERR_WORKSPACE, "workspace is NULL");
+    if ((uintptr_t)ws & 255) return fail(MG_ERR_WORKSPACE, "workspace is not 256-byte aligned");
     std::memset(st, 0, sizeof(*st));
     g_err.clear();
     return MG_OK;

@@ -49,6 +49,98 @@ __device__ __forceinline__ R *ptr(R *base, size_t plane, unsigned off) {
     return reinterpret_cast<R *>(reinterpret_cast<char *>(base) + plane + off);
 }
 
+// Staging of one z-plane (tile plus halo: TYH rows of TXH values) of two
+// arrays of a level into LDS.  A staged plane starts one value into its LDS
+// slot of TSLOT values.  FP64: each row's 64 interior values are read as 32
+// 16-byte vectors (rows start on 512-byte boundaries of the level's arrays)
+// and land on 16-byte LDS addresses (slot base + 8 + 528 r + 16 i); the two
+// halo columns are single values.  320 vectors + 20 halo values: every thread
+// takes one vector, then threads 0..63 one more and threads 64..83 a halo
+// value.  FP32: one value per load.
+constexpr int TSLOT = TPLANE + 2;
+
+template <typename R>
+struct Stage2 {
+    unsigned soff[TLOADS];
+    R ra[TLOADS], rb[TLOADS];
+    __device__ __forceinline__ void init(int tid, int j0, int m0, int logn, int lognh) {
+#pragma unroll
+        for (int q = 0; q < TLOADS; ++q) soff[q] = stage_off<R>(tid + q * TPB, j0, m0, logn, lognh);
+    }
+    __device__ __forceinline__ void fetch(const R *A, const R *B, size_t pl, int tid) {
+#pragma unroll
+        for (int q = 0; q < TLOADS; ++q) {
+            if (tid + q * TPB < TPLANE) {
+                ra[q] = ld(A, pl, soff[q]);
+                rb[q] = ld(B, pl, soff[q]);
+            }
+        }
+    }
+    // sa, sb: the slots' plane views (slot base + 1)
+    __device__ __forceinline__ void store(R *sa, R *sb, int tid) const {
+#pragma unroll
+        for (int q = 0; q < TLOADS; ++q) {
+            const int e = tid + q * TPB;
+            if (e < TPLANE) {
+                sa[e] = ra[q];
+                sb[e] = rb[q];
+            }
+        }
+    }
+};
+
+template <>
+struct Stage2<double> {
+    static constexpr int NV = TYH * (TX / 2);   // 320 vectors per plane
+    static_assert(TPB == 256 && NV - TPB == 64 && 2 * TYH <= TPB - 64, "staging split");
+    unsigned g0, g1;   // byte offsets inside a plane
+    int l0, l1;        // value offsets inside a plane view
+    double2 a0, a1, b0, b1;
+    double ha, hb;
+    __device__ __forceinline__ void init(int tid, int j0, int m0, int logn, int lognh) {
+        const unsigned jm = (1u << logn) - 1, mm = (1u << lognh) - 1;
+        {
+            const int r = tid >> 5, i = tid & 31;
+            g0 = ((((unsigned)(j0 - 1 + r) & jm) << lognh) + (unsigned)(m0 + 2 * i)) * 8u;
+            l0 = r * TXH + 1 + 2 * i;
+        }
+        if (tid < 64) {
+            const int r = 8 + (tid >> 5), i = tid & 31;
+            g1 = ((((unsigned)(j0 - 1 + r) & jm) << lognh) + (unsigned)(m0 + 2 * i)) * 8u;
+            l1 = r * TXH + 1 + 2 * i;
+        } else {
+            const int h = tid < 64 + 2 * TYH ? tid - 64 : 0, r = h >> 1, side = h & 1;
+            const unsigned m = (unsigned)(side ? m0 + TX : m0 - 1) & mm;
+            g1 = ((((unsigned)(j0 - 1 + r) & jm) << lognh) + m) * 8u;
+            l1 = r * TXH + (side ? TXH - 1 : 0);
+        }
+    }
+    __device__ __forceinline__ void fetch(const double *A, const double *B, size_t pl, int tid) {
+        const char *a = reinterpret_cast<const char *>(A) + pl;
+        const char *b = reinterpret_cast<const char *>(B) + pl;
+        a0 = *reinterpret_cast<const double2 *>(a + g0);
+        b0 = *reinterpret_cast<const double2 *>(b + g0);
+        if (tid < 64) {
+            a1 = *reinterpret_cast<const double2 *>(a + g1);
+            b1 = *reinterpret_cast<const double2 *>(b + g1);
+        } else if (tid < 64 + 2 * TYH) {
+            ha = *reinterpret_cast<const double *>(a + g1);
+            hb = *reinterpret_cast<const double *>(b + g1);
+        }
+    }
+    __device__ __forceinline__ void store(double *sa, double *sb, int tid) const {
+        *reinterpret_cast<double2 *>(sa + l0) = a0;
+        *reinterpret_cast<double2 *>(sb + l0) = b0;
+        if (tid < 64) {
+            *reinterpret_cast<double2 *>(sa + l1) = a1;
+            *reinterpret_cast<double2 *>(sb + l1) = b1;
+        } else if (tid < 64 + 2 * TYH) {
+            sa[l1] = ha;
+            sb[l1] = hb;
+        }
+    }
+};
+
 // Stencil of the cell at local (r, q) (halo-shifted tile coordinates) with
 // packed-x parity p, from staged planes: B = opposite colour at plane k,
 // A = own colour at k-1 / k / k+1, Bz = opposite colour at k-1 / k+1.
@@ -102,7 +194,7 @@ template <int OP, typename R>
 __global__ __launch_bounds__(TPB) void k_pass_tiled(Mod M, LvlT<R> L, int c, R *__restrict__ out,
                                                     const double *fptr, double fscale,
                                                     unsigned long long *clamp, TileGeom G) {
-    __shared__ R sA[3][TPLANE], sB[3][TPLANE];
+    __shared__ __align__(16) R sA[3][TSLOT], sB[3][TSLOT];
     const size_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int bx = (int)(blk % G.ntx);
     const int by = (int)((blk / G.ntx) % G.nty);
@@ -114,32 +206,13 @@ __global__ __launch_bounds__(TPB) void k_pass_tiled(Mod M, LvlT<R> L, int c, R *
     const R *F = c ? L.f1 : L.f0;
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     const R fs = (R)(fptr ? fscale * (*fptr) : 0.0);
-    unsigned soff[TLOADS], coff[2];
-#pragma unroll
-    for (int q = 0; q < TLOADS; ++q) soff[q] = stage_off<R>(tid + q * TPB, j0, m0, L.logn, L.lognh);
+    unsigned coff[2];
+    Stage2<R> S;
+    S.init(tid, j0, m0, L.logn, L.lognh);
 #pragma unroll
     for (int h = 0; h < 2; ++h) coff[h] = cell_off<R>(j0 + ty + 4 * h, m0 + tx, L.lognh);
-    R ra[TLOADS], rb[TLOADS];
-    auto fetch = [&](int k) {
-        const size_t pl = plane_off<R>(k, L.logn, L.lognh);
-#pragma unroll
-        for (int q = 0; q < TLOADS; ++q) {
-            if (tid + q * TPB < TPLANE) {
-                ra[q] = ld(A, pl, soff[q]);
-                rb[q] = ld(B, pl, soff[q]);
-            }
-        }
-    };
-    auto store = [&](int slot) {
-#pragma unroll
-        for (int q = 0; q < TLOADS; ++q) {
-            const int e = tid + q * TPB;
-            if (e < TPLANE) {
-                sA[slot][e] = ra[q];
-                sB[slot][e] = rb[q];
-            }
-        }
-    };
+    auto fetch = [&](int k) { S.fetch(A, B, plane_off<R>(k, L.logn, L.lognh), tid); };
+    auto store = [&](int slot) { S.store(sA[slot] + 1, sB[slot] + 1, tid); };
     // own cells' delta and f, one plane ahead
     R dn[2], fn[2];
     auto fetch_cells = [&](int k) {
@@ -169,12 +242,12 @@ __global__ __launch_bounds__(TPB) void k_pass_tiled(Mod M, LvlT<R> L, int c, R *
             const int row = ty + 4 * h;
             const int j = j0 + row;
             const int p = (j + k + c) & 1;
-            const NbT<R> s = lds_nb<R, R>(sA[sm], sA[s0], sA[sp], sB[s0], sB[sm], sB[sp], row + 1,
-                                          tx + 1, p);
+            const NbT<R> s = lds_nb<R, R>(sA[sm] + 1, sA[s0] + 1, sA[sp] + 1, sB[s0] + 1,
+                                          sB[sm] + 1, sB[sp] + 1, row + 1, tx + 1, p);
             const R faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
             const R f = (h ? f1 : f0) + fs;
             const R nv = tiled_update<OP, R>(M, L, s, h ? d1 : d0, faces,
-                                             sA[s0][(row + 1) * TXH + tx + 1], f, clamp);
+                                             sA[s0][1 + (row + 1) * TXH + tx + 1], f, clamp);
             // streamed: the next reader is a later launch
             __builtin_nontemporal_store(nv, ptr(out, plane_off<R>(k, L.logn, L.lognh), coff[h]));
         }
@@ -195,7 +268,7 @@ __global__ __launch_bounds__(TPB) void k_resid_restrict_tiled(Mod M, LvlT<R> L, 
                                                               R *rd0, R *rd1, double *partials,
                                                               unsigned long long *clamp,
                                                               TileGeom G) {
-    __shared__ R s0[3][TPLANE], s1[3][TPLANE];
+    __shared__ __align__(16) R s0[3][TSLOT], s1[3][TSLOT];
     const size_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int bx = (int)(blk % G.ntx);
     const int by = (int)((blk / G.ntx) % G.nty);
@@ -204,32 +277,13 @@ __global__ __launch_bounds__(TPB) void k_resid_restrict_tiled(Mod M, LvlT<R> L, 
     const int m0 = bx * TX, j0 = by * TY, k0 = 2 * bz * G.kz, k1 = k0 + 2 * G.kz;
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     const int lnc = L.logn - 1;
-    unsigned soff[TLOADS], coff[2];
-#pragma unroll
-    for (int q = 0; q < TLOADS; ++q) soff[q] = stage_off<R>(tid + q * TPB, j0, m0, L.logn, L.lognh);
+    unsigned coff[2];
+    Stage2<R> S;
+    S.init(tid, j0, m0, L.logn, L.lognh);
 #pragma unroll
     for (int b = 0; b < 2; ++b) coff[b] = cell_off<R>(j0 + 2 * ty + b, m0 + tx, L.lognh);
-    R ra[TLOADS], rb[TLOADS];
-    auto fetch = [&](int k) {
-        const size_t pl = plane_off<R>(k, L.logn, L.lognh);
-#pragma unroll
-        for (int q = 0; q < TLOADS; ++q) {
-            if (tid + q * TPB < TPLANE) {
-                ra[q] = ld(L.u0, pl, soff[q]);
-                rb[q] = ld(L.u1, pl, soff[q]);
-            }
-        }
-    };
-    auto store = [&](int slot) {
-#pragma unroll
-        for (int q = 0; q < TLOADS; ++q) {
-            const int e = tid + q * TPB;
-            if (e < TPLANE) {
-                s0[slot][e] = ra[q];
-                s1[slot][e] = rb[q];
-            }
-        }
-    };
+    auto fetch = [&](int k) { S.fetch(L.u0, L.u1, plane_off<R>(k, L.logn, L.lognh), tid); };
+    auto store = [&](int slot) { S.store(s0[slot] + 1, s1[slot] + 1, tid); };
     // delta (and f) of the 4 children in a fine plane, one plane ahead
     R dn[4], fn[4];
     auto fetch_cells = [&](int k) {
@@ -274,12 +328,12 @@ __global__ __launch_bounds__(TPB) void k_resid_restrict_tiled(Mod M, LvlT<R> L, 
             for (int c = 0; c < 2; ++c) {
                 const int row = 2 * ty + b;
                 const int p = (j0 + row + k + c) & 1;
-                const R *Am = c ? s1[sm] : s0[sm];
-                const R *A0 = c ? s1[sz] : s0[sz];
-                const R *Ap = c ? s1[sp] : s0[sp];
-                const R *Bm = c ? s0[sm] : s1[sm];
-                const R *B0 = c ? s0[sz] : s1[sz];
-                const R *Bp = c ? s0[sp] : s1[sp];
+                const R *Am = (c ? s1[sm] : s0[sm]) + 1;
+                const R *A0 = (c ? s1[sz] : s0[sz]) + 1;
+                const R *Ap = (c ? s1[sp] : s0[sp]) + 1;
+                const R *Bm = (c ? s0[sm] : s1[sm]) + 1;
+                const R *B0 = (c ? s0[sz] : s1[sz]) + 1;
+                const R *Bp = (c ? s0[sp] : s1[sp]) + 1;
                 const int r = row + 1, q = tx + 1;
                 const Nb s = lds_nb<double, R>(Am, A0, Ap, B0, Bm, Bp, r, q, p);
                 const double u = (double)A0[r * TXH + q];

@@ -267,7 +267,8 @@ mg_status mg_cic_delta(int n_mesh, int n_part, const float *pos, double *delta, 
     if (n_part < 1 || n_part > 2048) return fail(MG_ERR_ARG, "n_part must be in [1, 2048]");
     if (!pos || !delta) return fail(MG_ERR_ARG, "pos and delta must be device pointers");
     const size_t need = (size_t)n_mesh * n_mesh * n_mesh * sizeof(unsigned long long);
-    if (!ws || ws_bytes < need) return fail(MG_ERR_WORKSPACE, "workspace is NULL or too small");
+    if (!ws || ws_bytes < need || ((uintptr_t)ws & 255))
+        return fail(MG_ERR_WORKSPACE, "workspace is NULL, too small or not 256-byte aligned");
     mg_status rc = cic(n_mesh, n_part, pos, delta, (unsigned long long *)ws, stream);
     if (rc != MG_OK) return rc;
     return hip_status(stream, true);
@@ -286,7 +287,8 @@ mg_status mg_pm_step(const mg_pm_params *par, float *pos, float *mom, double *ph
         !(par->omega_m > 0.0) || !(par->omega_m < 1.0))
         return fail(MG_ERR_ARG, "invalid n_part, a, da or omega_m");
     const size_t need = mg_pm_workspace_bytes(n);
-    if (!ws || ws_bytes < need) return fail(MG_ERR_WORKSPACE, "workspace is NULL or too small");
+    if (!ws || ws_bytes < need || ((uintptr_t)ws & 255))
+        return fail(MG_ERR_WORKSPACE, "workspace is NULL, too small or not 256-byte aligned");
     const size_t ncell = (size_t)n * n * n;
     unsigned long long *counts = (unsigned long long *)ws;
     char *solver_ws = (char *)ws + align256(ncell * sizeof(unsigned long long));
@@ -338,7 +340,8 @@ mg_status mg_pm_step_kmouflage(const mg_pm_kmo_params *par, float *pos, float *m
         !(K.omega_m < 1.0))
         return fail(MG_ERR_ARG, "invalid n_part, a, da, background values or kmo parameters");
     const size_t need = mg_pm_workspace_bytes(n);
-    if (!ws || ws_bytes < need) return fail(MG_ERR_WORKSPACE, "workspace is NULL or too small");
+    if (!ws || ws_bytes < need || ((uintptr_t)ws & 255))
+        return fail(MG_ERR_WORKSPACE, "workspace is NULL, too small or not 256-byte aligned");
     const size_t ncell = (size_t)n * n * n;
     unsigned long long *counts = (unsigned long long *)ws;
     char *solver_ws = (char *)ws + align256(ncell * sizeof(unsigned long long));

@@ -103,6 +103,12 @@ def test_null_pointers_and_workspace(L):
     assert L.mg_solve_dgp(C.byref(o), C.byref(par), d, d, None, 1 << 30, None, C.byref(st)) == mg.MG_ERR_WORKSPACE
     assert L.mg_solve_dgp(C.byref(o), C.byref(par), d, d, d, 16, None, C.byref(st)) == mg.MG_ERR_WORKSPACE
     assert L.mg_solve_dgp(None, C.byref(par), d, d, d, 1 << 30, None, C.byref(st)) == mg.MG_ERR_ARG
+    # workspaces start on 256-byte boundaries (the tiled kernels read 16-byte vectors)
+    odd = C.c_void_p(0x1000 + 8)
+    assert L.mg_solve_dgp(C.byref(o), C.byref(par), d, d, odd, 1 << 30, None, C.byref(st)) == mg.MG_ERR_WORKSPACE
+    assert b"aligned" in L.mg_last_error()
+    assert L.mg_cic_delta(32, 16, d, d, odd, 1 << 40, None) == mg.MG_ERR_WORKSPACE
+    assert b"aligned" in L.mg_last_error()
 
 
 def test_adjoint_accepts_v_cycles_only(L):
