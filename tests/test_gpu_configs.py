@@ -6,6 +6,9 @@
 * 256^3 Kmouflage (n = 3, K0 = 1, beta = 0.1) on the same density.
 * 256^3 nDGP adjoint: gradient of sum(phi w) against central finite
   differences on 64 random cells (eps = 1e-4).
+* The benchmark workload (512^3 mesh, CIC of 256^3 particles, L = 512 Mpc/h,
+  H0 r_c = 1, tol 1e-8) in FP64 and mixed precision: CIC density
+  element-wise, the oracle's operator on windows of the returned field.
 * PM step on a 1024^3 mesh with 512^3 particles: CIC density element-wise,
   the potentials through their discrete equations on sampled cells, and the
   kick-drift of sampled particles recomputed by the oracle.
@@ -220,3 +223,31 @@ def test_config5_pm_step_1024():
     dp = np.abs(gp - p_s)
     dp = np.minimum(dp, nm - dp)
     assert dp.max() <= 1e-4
+
+
+@pytest.mark.parametrize("precision", [mg.MG_FP64, mg.MG_MIXED])
+def test_bench_workload_512(precision):
+    # the solve bench.py times (same particles, seed, options and entry points)
+    import bench
+    nm, np_ = bench.N_MESH, bench.N_PART
+    pos = inputs.za_particles(np_, nm, bench.SEED)
+    delta = mg.cic_delta(g(pos), nm)
+    phi, st = mg.solve_dgp(delta, a=bench.A, omega_m=bench.OMEGA_M, h0rc=bench.H0RC,
+                           tol=bench.TOL, max_cycles=60, precision=precision)
+    assert st["status"] == 0 and st["eps"] <= bench.TOL
+    d = c(delta)
+    _, d_or = oracle.cic_density(pos, nm)
+    assert np.abs(d - d_or).max() <= 1e-7
+    del d_or
+    ph = c(phi)
+    assert abs(ph.mean()) <= 1e-12 * np.abs(ph).max()
+    # the oracle's operator on the whole returned field: the RMS of its
+    # mean-projected residual is the solver's stopping quantity
+    m = oracle.dgp_model(bench.A, bench.OMEGA_M, bench.H0RC)
+    res = oracle.residual(m, ph, d)
+    res -= res.mean()
+    rms = float(np.sqrt(np.mean(res ** 2)))
+    print("bench workload %s: cycles %d eps %.3e, oracle RMS of the returned field %.3e"
+          % (("fp64", "mixed")[precision], st["cycles"], st["eps"], rms))
+    assert rms <= bench.TOL
+    assert rms == pytest.approx(st["eps"], rel=1e-6)
