@@ -95,8 +95,11 @@ __global__ __launch_bounds__(TPB) void k_adj_coefs(Mod M, Lvl L, CoefsW W, doubl
         e[1] = ec * gx * gz;
         e[2] = ec * gy * gz;
     }
+    // nDGP and Poisson: the x+ and x- (y, z) coefficients are equal and the
+    // minus arrays alias the plus ones, so only the plus arrays are written
 #pragma unroll
-    for (int q = 0; q < 6; ++q) W.c[q][c][tt] = f[q];
+    for (int q = 0; q < 6; ++q)
+        if (MODEL == MODEL_KMO || !(q & 1)) W.c[q][c][tt] = f[q];
 #pragma unroll
     for (int q = 0; q < 3; ++q) W.c[6 + q][c][tt] = e[q];
 }

@@ -186,6 +186,17 @@ LvlT<R> view(const HLevel<R> &H, bool with_f) {
     return L;
 }
 
+// The adjoint's face coefficients dK/dphi at x+ and x- (y, z) are equal for
+// the nDGP and Poisson terms (both depend on phi through second differences
+// only): point the minus arrays at the plus ones, so k_adj_coefs writes 6
+// arrays instead of 9 and an adjoint pass reads 3 face arrays instead of 6.
+template <typename R>
+void alias_face_coefs(HLevel<R> &H, bool symmetric) {
+    if (!symmetric) return;
+    for (int q = 1; q < 6; q += 2)
+        for (int c = 0; c < 2; ++c) H.cf[q][c] = H.cf[q - 1][c];
+}
+
 template <typename R>
 Coefs coefs(const HLevel<R> &H) {
     Coefs C;
@@ -790,6 +801,7 @@ void adj_coefficients(Ctx &C, const double *phi) {
                                                                   F.lin[1], nullptr);
     for (int l = 0; l < Hh.nlev; ++l) {
         HLevel<double> &H = Hh.lv[l];
+        alias_face_coefs(H, MODEL != MODEL_KMO);
         if (l + 1 < Hh.nlev) {
             HLevel<double> &Hc = Hh.lv[l + 1];
             k_restrict<double><<<nblocks(2 * Hc.half), TPB, 0, C.st>>>(H.lin[0], H.lin[1], H.logn,
@@ -1163,6 +1175,7 @@ mg_status mg_op_jt_apply(int model, const void *params, int n, double h, const d
     const unsigned nb = nblocks(2 * H.half);
     k_pack<double, double><<<nb, TPB, 0, stream>>>(phi, H.logn, H.u[0], H.u[1], nullptr);
     k_pack<double, double><<<nb, TPB, 0, stream>>>(delta, H.logn, H.d[0], H.d[1], nullptr);
+    alias_face_coefs(H, model != MG_MODEL_KMOUFLAGE);
     CoefsW Wc;
     for (int q = 0; q < 9; ++q)
         for (int c = 0; c < 2; ++c) Wc.c[q][c] = H.cf[q][c];
