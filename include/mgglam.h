@@ -61,7 +61,11 @@ typedef enum { MG_CYCLE_V = 0, MG_CYCLE_F = 1, MG_CYCLE_W = 2 } mg_cycle;
  * Gauss-Seidel smoothing, 8-cell mean restriction, 27/9/3/1 prolongation,
  * coarsest level 4^3. */
 typedef struct {
-    int n;            /* cells per side of the finest mesh (power of two, 8..2048) */
+    int n;            /* cells per side of the finest mesh (power of two, 8..2048).
+                         Workspace plus the caller's FP64 delta and phi: 49 GB at
+                         1024^3 (FP64); at 2048^3 393 GB (FP64), so only MG_FP32
+                         (266 GB) fits in one MI355X's 288 GB.  Sizes above 1024
+                         are untested. */
     int max_cycles;   /* cap on cycles (0..100000); default 50 */
     double tol;       /* stop when the RMS of the mean-projected finest residual
                          is <= tol (code units); 0 runs exactly max_cycles */
