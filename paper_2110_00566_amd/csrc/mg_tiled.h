@@ -44,6 +44,13 @@ template <typename R>
 __device__ __forceinline__ R ld(const R *base, size_t plane, unsigned off) {
     return *reinterpret_cast<const R *>(reinterpret_cast<const char *>(base) + plane + off);
 }
+// A cell's own delta and f are read once per launch: non-temporal loads
+// keep them from displacing the staged planes' halo rows in the caches.
+template <typename R>
+__device__ __forceinline__ R ld_once(const R *base, size_t plane, unsigned off) {
+    return __builtin_nontemporal_load(
+        reinterpret_cast<const R *>(reinterpret_cast<const char *>(base) + plane + off));
+}
 template <typename R>
 __device__ __forceinline__ R *ptr(R *base, size_t plane, unsigned off) {
     return reinterpret_cast<R *>(reinterpret_cast<char *>(base) + plane + off);
@@ -219,8 +226,8 @@ __global__ __launch_bounds__(TPB) void k_pass_tiled(Mod M, LvlT<R> L, int c, R *
         const size_t pl = plane_off<R>(k, L.logn, L.lognh);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            dn[h] = ld(D, pl, coff[h]);
-            fn[h] = F ? ld(F, pl, coff[h]) : (R)0;
+            dn[h] = ld_once(D, pl, coff[h]);
+            fn[h] = F ? ld_once(F, pl, coff[h]) : (R)0;
         }
     };
     // slot of plane k: (k - k0 + 1) mod 3
@@ -290,11 +297,11 @@ __global__ __launch_bounds__(TPB) void k_resid_restrict_tiled(Mod M, LvlT<R> L, 
         const size_t pl = plane_off<R>(k, L.logn, L.lognh);
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-            dn[2 * b] = ld(L.d0, pl, coff[b]);
-            dn[2 * b + 1] = ld(L.d1, pl, coff[b]);
+            dn[2 * b] = ld_once(L.d0, pl, coff[b]);
+            dn[2 * b + 1] = ld_once(L.d1, pl, coff[b]);
             if (HASF) {
-                fn[2 * b] = ld(L.f0, pl, coff[b]);
-                fn[2 * b + 1] = ld(L.f1, pl, coff[b]);
+                fn[2 * b] = ld_once(L.f0, pl, coff[b]);
+                fn[2 * b + 1] = ld_once(L.f1, pl, coff[b]);
             }
         }
     };
@@ -562,8 +569,8 @@ __global__ __launch_bounds__(TPB) void k_prolong_pass_tiled(Mod M, LvlT<R> L, R 
         const size_t pl = plane_off<R>(k, L.logn, L.lognh);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            dn[h] = ld(L.d0, pl, coff[h]);
-            fn[h] = L.f0 ? ld(L.f0, pl, coff[h]) : (R)0;
+            dn[h] = ld_once(L.d0, pl, coff[h]);
+            fn[h] = L.f0 ? ld_once(L.f0, pl, coff[h]) : (R)0;
         }
     };
 
