@@ -21,6 +21,9 @@
  *    unspecified.
  *  - Calls that share a workspace must not overlap in time.  Workspaces
  *    start on a 256-byte boundary (hipMalloc's and torch's allocations do).
+ *  - Solver calls read the stopping residual through one 128-byte pinned
+ *    host buffer per calling thread, allocated on first use and kept until
+ *    the process ends.
  */
 #ifndef MGGLAM_H
 #define MGGLAM_H

@@ -111,7 +111,44 @@ struct Ctx {
     std::vector<Segment> segs;
     int lev_used = 0;
     double level_ms[MG_LEVELS] = {};
+    // Early read of the cycle's stopping scalars: they are final once the
+    // finest in-cycle residual has been reduced, so they are copied to pinned
+    // host memory at that point and the host decides on the next cycle while
+    // the coarse levels and the post-smoothing still run.
+    double *pin = nullptr;
+    hipEvent_t pin_ev = nullptr;
+    bool pin_pending = false;
+    Ctx() = default;
+    Ctx(const Ctx &) = delete;
+    Ctx &operator=(const Ctx &) = delete;
+    ~Ctx() {
+        if (pin_ev) (void)hipEventDestroy(pin_ev);
+    }
 };
+
+// Pinned host buffer for the per-cycle scalars, one per host thread (calls on
+// one thread never overlap), allocated on first use and kept until the
+// process ends.  nullptr if the allocation fails: the solver then reads the
+// scalars after the whole cycle.
+double *pinned_scalars() {
+    thread_local double *p = nullptr;
+    if (!p) {
+        void *q = nullptr;
+        if (hipHostMalloc(&q, sizeof(double) * S_NSCAL, hipHostMallocDefault) == hipSuccess)
+            p = static_cast<double *>(q);
+        else
+            (void)hipGetLastError();
+    }
+    return p;
+}
+
+void arm_early_read(Ctx &C) {
+    C.pin = pinned_scalars();
+    if (C.pin && hipEventCreateWithFlags(&C.pin_ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        C.pin_ev = nullptr;
+    }
+}
 
 template <typename R>
 Hier<R> &hier(Ctx &C);
@@ -520,6 +557,7 @@ struct Solver {
         }
         for (int s = 0; s < C.nu1; ++s) sweep(l);
         resid_restrict(l);
+        if (l == 0) copy_scal_early();
         coarse_source(l + 1);
         segment(l, e0, mark());
         if (type == 2) {
@@ -543,8 +581,25 @@ struct Solver {
         segment(l, e2, mark());
     }
 
+    // Scalars of the finest in-cycle residual into pinned memory (not in
+    // profile mode, whose event timings need the whole cycle).  No kernel
+    // later in the cycle writes mu or eps^2.
+    void copy_scal_early() {
+        if (C.profile || !C.pin || !C.pin_ev) return;
+        if (hipMemcpyAsync(C.pin, C.scal, sizeof(double) * S_NSCAL, hipMemcpyDeviceToHost,
+                           C.st) == hipSuccess &&
+            hipEventRecord(C.pin_ev, C.st) == hipSuccess)
+            C.pin_pending = true;
+    }
+
     mg_status read_scal(double *hs) {
         HIPCHK(hipGetLastError());
+        if (C.pin_pending) {
+            C.pin_pending = false;
+            HIPCHK(hipEventSynchronize(C.pin_ev));
+            std::memcpy(hs, C.pin, sizeof(double) * S_NSCAL);
+            return MG_OK;
+        }
         HIPCHK(hipMemcpyAsync(hs, C.scal, sizeof(double) * S_NSCAL, hipMemcpyDeviceToHost, C.st));
         HIPCHK(hipStreamSynchronize(C.st));
         if (C.profile) {
@@ -739,6 +794,7 @@ mg_status forward_solve(const mg_opts *o, const Mod &M, const double *delta, dou
     C.nuc = o->nu_coarse;
     C.cycle = o->cycle;
     Profiler prof(C, o->profile != 0, 2 * (o->nu_pre + o->nu_post) + 2);
+    arm_early_read(C);
     reset_scalars(C);
     if (o->precision == MG_FP32) return fp32_solve<OP>(o, C, delta, phi, st, t0);
     HLevel<double> &F = C.h64.lv[0];
@@ -835,6 +891,7 @@ mg_status adjoint_solve(const mg_opts *o, const Mod &M, const double *delta, con
     C.nuc = o->nu_coarse;
     C.kappa = 6.0;   // 6/h^2 on the finest level: removes the mean of mu in one pass
     Profiler prof(C, false, 0);
+    arm_early_read(C);
     reset_scalars(C);
     density_hierarchy<double>(C, delta);
     adj_coefficients<MODEL>(C, phi);
