@@ -122,6 +122,9 @@ struct Ctx {
     Ctx(const Ctx &) = delete;
     Ctx &operator=(const Ctx &) = delete;
     ~Ctx() {
+        // an early copy still in flight (a call that ended on an error) must
+        // land before the next call on this thread reuses the pinned buffer
+        if (pin_pending) (void)hipEventSynchronize(pin_ev);
         if (pin_ev) (void)hipEventDestroy(pin_ev);
     }
 };
