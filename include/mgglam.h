@@ -174,7 +174,9 @@ typedef struct { double s; } mg_poisson_params;
 
 /* Bytes of device workspace needed by a solve on an n^3 mesh.  precision is
  * an mg_precision, model an mg_model; adjoint != 0 sizes mg_solve_adjoint
- * (FP64 only).  Returns 0 for invalid arguments. */
+ * (FP64 only), whose Kmouflage workspace is larger than the nDGP and Poisson
+ * one (9 Jacobian coefficient arrays per level instead of 6).  Returns 0 for
+ * invalid arguments. */
 size_t mg_workspace_bytes(int n, int precision, int model, int adjoint);
 
 /* Solve the nDGP scalar-field equation eq:dgp_eom_code in the form of

@@ -161,7 +161,7 @@ template <>
 Hier<float> &hier<float>(Ctx &C) { return C.h32; }
 
 template <typename R>
-void layout_hier(Hier<R> &Hh, Carve &cv, int n, bool adjoint) {
+void layout_hier(Hier<R> &Hh, Carve &cv, int n, bool adjoint, bool sym_coefs) {
     int L = 0;
     for (int m = n; m >= 4; m >>= 1) {
         HLevel<R> &H = Hh.lv[L];
@@ -186,8 +186,11 @@ void layout_hier(Hier<R> &Hh, Carve &cv, int n, bool adjoint) {
         if (adjoint) {
             H.lin[0] = cv.take<double>(H.half);
             H.lin[1] = cv.take<double>(H.half);
+            // nDGP and Poisson: the minus face arrays alias the plus ones
             for (int q = 0; q < 9; ++q)
-                for (int c = 0; c < 2; ++c) H.cf[q][c] = cv.take<double>(H.half);
+                for (int c = 0; c < 2; ++c)
+                    H.cf[q][c] = (sym_coefs && q < 6 && (q & 1)) ? H.cf[q - 1][c]
+                                                                 : cv.take<double>(H.half);
         }
         ++L;
     }
@@ -196,9 +199,9 @@ void layout_hier(Hier<R> &Hh, Carve &cv, int n, bool adjoint) {
 
 // Lay the workspace out (base == nullptr: only measure): the FP64 hierarchy
 // unless precision is MG_FP32, the FP32 one unless it is MG_FP64.
-void layout(Ctx &C, Carve &cv, int n, bool adjoint, int precision) {
-    if (precision != MG_FP32) layout_hier(C.h64, cv, n, adjoint);
-    if (precision != MG_FP64) layout_hier(C.h32, cv, n, false);
+void layout(Ctx &C, Carve &cv, int n, bool adjoint, int precision, bool sym_coefs = false) {
+    if (precision != MG_FP32) layout_hier(C.h64, cv, n, adjoint, sym_coefs);
+    if (precision != MG_FP64) layout_hier(C.h32, cv, n, false, false);
     C.npartials = std::max<size_t>((size_t)n * n * n / TPB + 1, 1024);
     C.partials = cv.take<double>(2 * C.npartials);
     C.scal = cv.take<double>(S_NSCAL);
@@ -883,7 +886,7 @@ mg_status adjoint_solve(const mg_opts *o, const Mod &M, const double *delta, con
     auto t0 = std::chrono::steady_clock::now();
     Ctx C;
     Carve cv{static_cast<char *>(ws), 0};
-    layout(C, cv, o->n, true, MG_FP64);
+    layout(C, cv, o->n, true, MG_FP64, MODEL != MODEL_KMO);
     if (!ws || ws_bytes < cv.off || ((uintptr_t)ws & 255))
         return fail(MG_ERR_WORKSPACE, "workspace too small (need " + std::to_string(cv.off) +
                                           " bytes) or not 256-byte aligned");
@@ -1038,7 +1041,7 @@ size_t mg_workspace_bytes(int n, int precision, int model, int adjoint) {
     if (adjoint && precision != MG_FP64) return 0;
     Ctx C;
     Carve cv{nullptr, 0};
-    layout(C, cv, n, adjoint != 0, precision);
+    layout(C, cv, n, adjoint != 0, precision, model != MG_MODEL_KMOUFLAGE);
     return cv.off + 256;
 }
 

@@ -41,6 +41,11 @@ def test_workspace_sizes(L):
     # finest level: 5 half-arrays of FP64 = 20 bytes per cell, coarse levels add < 1/2
     assert 20 * 64 ** 3 <= a <= 40 * 64 ** 3
     assert b > a
+    # adjoint: the nDGP and Poisson minus face coefficients alias the plus
+    # ones, 3 FP64 arrays of both colours (24 B/cell) fewer than Kmouflage
+    bk = L.mg_workspace_bytes(64, 0, 1, 1)
+    assert bk - b >= 24 * 64 ** 3
+    assert L.mg_workspace_bytes(64, 0, 2, 1) == b
     assert L.mg_workspace_bytes(64, 0, 0, 0) == a          # deterministic
     assert L.mg_pm_workspace_bytes(64) >= a + 8 * 64 ** 3
 
