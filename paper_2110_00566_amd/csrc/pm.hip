@@ -87,9 +87,12 @@ __global__ __launch_bounds__(PTPB) void k_cic_link(const float *__restrict__ pos
 // of every corner cell whose particles reach the tile (the tile and one cell
 // below it in each axis), adding the fixed-point weights that land inside
 // the tile into LDS; then it writes the tile's delta.
-constexpr int CGX = 32, CGY = 4, CGZ = 4;
-constexpr int CG_CELLS = CGX * CGY * CGZ;                      // 512
-constexpr int CG_LISTS = (CGX + 1) * (CGY + 1) * (CGZ + 1);    // 825
+// 32 x 8 x 8 walks 1.31 lists per cell (32 x 4 x 4: 1.61) and ran 16% faster
+// on 256^3 particles over 512^3 cells than 32 x 4 x 4; taller or wider tiles
+// were slower (fewer blocks per CU).
+constexpr int CGX = 32, CGY = 8, CGZ = 8;
+constexpr int CG_CELLS = CGX * CGY * CGZ;                      // 2048
+constexpr int CG_LISTS = (CGX + 1) * (CGY + 1) * (CGZ + 1);    // 2673
 
 __global__ __launch_bounds__(PTPB) void k_cic_gather(const float *__restrict__ pos, int logn,
                                                       const int *__restrict__ head,

@@ -426,7 +426,7 @@ def test_autograd_matches_finite_differences():
 
 # -------------------------------------------------------- CIC and PM step
 
-@pytest.mark.parametrize("np_,nm", [(16, 32), (32, 32), (8, 16)])
+@pytest.mark.parametrize("np_,nm", [(16, 32), (32, 32), (8, 16), (64, 128)])
 def test_cic_parity(np_, nm):
     pos = inputs.za_particles(np_, nm, 2, amplitude=30.0)
     _, ref = oracle.cic_density(pos, nm)
