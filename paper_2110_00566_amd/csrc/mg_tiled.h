@@ -96,6 +96,53 @@ struct Stage2 {
     }
 };
 
+// FP32: 16 vectors of 4 values per row (160 per plane) and 20 halo values,
+// one per thread; a vector lands in LDS as two 8-byte halves (a staged row
+// starts 8 bytes off a 16-byte boundary in every other slot and row).
+template <>
+struct Stage2<float> {
+    static constexpr int NV = TYH * (TX / 4);   // 160 vectors per plane
+    static_assert(NV + 2 * TYH <= TPB, "staging split");
+    unsigned g;   // byte offset inside a plane
+    int l;        // value offset inside a plane view
+    float4 a, b;
+    __device__ __forceinline__ void init(int tid, int j0, int m0, int logn, int lognh) {
+        const unsigned jm = (1u << logn) - 1, mm = (1u << lognh) - 1;
+        if (tid < NV) {
+            const int r = tid >> 4, i = tid & 15;
+            g = ((((unsigned)(j0 - 1 + r) & jm) << lognh) + (unsigned)(m0 + 4 * i)) * 4u;
+            l = r * TXH + 1 + 4 * i;
+        } else {
+            const int h = tid < NV + 2 * TYH ? tid - NV : 0, r = h >> 1, side = h & 1;
+            const unsigned m = (unsigned)(side ? m0 + TX : m0 - 1) & mm;
+            g = ((((unsigned)(j0 - 1 + r) & jm) << lognh) + m) * 4u;
+            l = r * TXH + (side ? TXH - 1 : 0);
+        }
+    }
+    __device__ __forceinline__ void fetch(const float *A, const float *B, size_t pl, int tid) {
+        const char *pa = reinterpret_cast<const char *>(A) + pl + g;
+        const char *pb = reinterpret_cast<const char *>(B) + pl + g;
+        if (tid < NV) {
+            a = *reinterpret_cast<const float4 *>(pa);
+            b = *reinterpret_cast<const float4 *>(pb);
+        } else if (tid < NV + 2 * TYH) {
+            a.x = *reinterpret_cast<const float *>(pa);
+            b.x = *reinterpret_cast<const float *>(pb);
+        }
+    }
+    __device__ __forceinline__ void store(float *sa, float *sb, int tid) const {
+        if (tid < NV) {
+            *reinterpret_cast<float2 *>(sa + l) = make_float2(a.x, a.y);
+            *reinterpret_cast<float2 *>(sa + l + 2) = make_float2(a.z, a.w);
+            *reinterpret_cast<float2 *>(sb + l) = make_float2(b.x, b.y);
+            *reinterpret_cast<float2 *>(sb + l + 2) = make_float2(b.z, b.w);
+        } else if (tid < NV + 2 * TYH) {
+            sa[l] = a.x;
+            sb[l] = b.x;
+        }
+    }
+};
+
 template <>
 struct Stage2<double> {
     static constexpr int NV = TYH * (TX / 2);   // 320 vectors per plane
