@@ -699,7 +699,7 @@ template <int OP, typename R>
 __global__ __launch_bounds__(TPB) void k_coarse_source_tiled(Mod M, LvlT<R> Lc, R *s0, R *s1,
                                                              R *u0, R *u1, const double *shift,
                                                              TileGeom G) {
-    __shared__ R sA[3][TPLANE], sB[3][TPLANE];   // colour 0 / colour 1 of R u
+    __shared__ __align__(16) R sA[3][TSLOT], sB[3][TSLOT];   // colour 0 / colour 1 of R u
     const size_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int bx = (int)(blk % G.ntx);
     const int by = (int)((blk / G.ntx) % G.nty);
@@ -707,33 +707,13 @@ __global__ __launch_bounds__(TPB) void k_coarse_source_tiled(Mod M, LvlT<R> Lc, 
     const int m0 = bx * TX, j0 = by * TY, k0 = bz * G.kz;
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
     const double sh = shift ? *shift : 0.0;
-    unsigned soff[TLOADS], coff[2];
-#pragma unroll
-    for (int q = 0; q < TLOADS; ++q)
-        soff[q] = stage_off<R>(tid + q * TPB, j0, m0, Lc.logn, Lc.lognh);
+    unsigned coff[2];
+    Stage2<R> S2;
+    S2.init(tid, j0, m0, Lc.logn, Lc.lognh);
 #pragma unroll
     for (int h = 0; h < 2; ++h) coff[h] = cell_off<R>(j0 + ty + 4 * h, m0 + tx, Lc.lognh);
-    R ra[TLOADS], rb[TLOADS];
-    auto fetch = [&](int k) {
-        const size_t pl = plane_off<R>(k, Lc.logn, Lc.lognh);
-#pragma unroll
-        for (int q = 0; q < TLOADS; ++q) {
-            if (tid + q * TPB < TPLANE) {
-                ra[q] = ld(Lc.u0, pl, soff[q]);
-                rb[q] = ld(Lc.u1, pl, soff[q]);
-            }
-        }
-    };
-    auto store = [&](int slot) {
-#pragma unroll
-        for (int q = 0; q < TLOADS; ++q) {
-            const int e = tid + q * TPB;
-            if (e < TPLANE) {
-                sA[slot][e] = ra[q];
-                sB[slot][e] = rb[q];
-            }
-        }
-    };
+    auto fetch = [&](int k) { S2.fetch(Lc.u0, Lc.u1, plane_off<R>(k, Lc.logn, Lc.lognh), tid); };
+    auto store = [&](int slot) { S2.store(sA[slot] + 1, sB[slot] + 1, tid); };
     fetch(k0 - 1);
     store(0);
     fetch(k0);
@@ -749,20 +729,20 @@ __global__ __launch_bounds__(TPB) void k_coarse_source_tiled(Mod M, LvlT<R> Lc, 
             const int row = ty + 4 * (h & 1), c = h >> 1;
             const int j = j0 + row;
             const int p = (j + k + c) & 1;
-            const R *Am = c ? sB[sm] : sA[sm];
-            const R *A0 = c ? sB[sz] : sA[sz];
-            const R *Ap = c ? sB[sp] : sA[sp];
-            const R *Bm = c ? sA[sm] : sB[sm];
-            const R *B0 = c ? sA[sz] : sB[sz];
-            const R *Bp = c ? sA[sp] : sB[sp];
+            const R *Am = (c ? sB[sm] : sA[sm]) + 1;
+            const R *A0 = (c ? sB[sz] : sA[sz]) + 1;
+            const R *Ap = (c ? sB[sp] : sA[sp]) + 1;
+            const R *Bm = (c ? sA[sm] : sB[sm]) + 1;
+            const R *B0 = (c ? sA[sz] : sB[sz]) + 1;
+            const R *Bp = (c ? sA[sp] : sB[sp]) + 1;
             const Nb s = lds_nb<double, R>(Am, A0, Ap, B0, Bm, Bp, row + 1, tx + 1, p);
             const size_t pl = plane_off<R>(k, Lc.logn, Lc.lognh);
             const unsigned o = coff[h & 1];
             const R ru = A0[(row + 1) * TXH + tx + 1];
             const double faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
-            const double delta = (double)ld(c ? Lc.d1 : Lc.d0, pl, o);
+            const double delta = (double)ld_once(c ? Lc.d1 : Lc.d0, pl, o);
             R *S = ptr(c ? s1 : s0, pl, o);
-            const double rd = (double)*S - sh;
+            const double rd = (double)ld_once(c ? s1 : s0, pl, o) - sh;
             *S = (R)((faces - 6.0 * (double)ru) / Lc.h2
                      - tiled_term<OP, double>(M, Lc, s, delta, faces, (double)ru, nullptr) - rd);
             *ptr(c ? u1 : u0, pl, o) = ru;
