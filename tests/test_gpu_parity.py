@@ -506,3 +506,19 @@ def test_mixed_kmouflage_sphere():
                                  max_cycles=100, precision=mg.MG_MIXED)
     assert st["status"] == 0 and st["eps"] <= 1e-9
     assert rel(c(phi), r.phi) <= 1e-6
+
+
+@pytest.mark.parametrize("cycle,precision", [(mg.CYCLE_V, mg.MG_FP64), (mg.CYCLE_W, mg.MG_FP64),
+                                             (mg.CYCLE_V, mg.MG_MIXED)])
+def test_early_residual_read_changes_nothing(cycle, precision):
+    # profile mode reads each cycle's stopping scalars after the whole cycle;
+    # otherwise they are read as soon as the finest in-cycle residual is
+    # reduced: the iterates, histories and stopping decisions are identical
+    n = 128
+    delta = g(inputs.lognormal_delta(n, 31))
+    kw = dict(tol=1e-9, max_cycles=40, cycle=cycle, precision=precision)
+    a, sa = mg.solve_dgp(delta, **kw)
+    b, sb = mg.solve_dgp(delta, profile=True, **kw)
+    assert torch.equal(a, b)
+    assert sa["cycles"] == sb["cycles"] and sa["eps"] == sb["eps"]
+    assert sa["eps_hist"][:sa["cycles"]] == sb["eps_hist"][:sb["cycles"]]
