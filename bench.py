@@ -392,7 +392,7 @@ def main():
         "level_ms_per_cycle": [round(sum(s.level_ms[l] for s in stats) / sum(cycles), 4)
                                for l in range(mg.LEVELS) if stats[0].level_ms[l] > 0],
         "ms_per_vcycle": solve_ms / float(np.mean(cycles)),
-        "roofline": {"bound": "hbm", "kernel": "k_pass<OP_DGP> (finest colour pass)",
+        "roofline": {"bound": "hbm", "kernel": "k_pass_tiled<OP_DGP, double> (finest colour pass)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "pass_ms_avg": pass_ms,
