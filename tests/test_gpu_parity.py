@@ -522,3 +522,21 @@ def test_early_residual_read_changes_nothing(cycle, precision):
     assert torch.equal(a, b)
     assert sa["cycles"] == sb["cycles"] and sa["eps"] == sb["eps"]
     assert sa["eps_hist"][:sa["cycles"]] == sb["eps_hist"][:sb["cycles"]]
+
+
+@pytest.mark.parametrize("n", [8, 16])
+@pytest.mark.parametrize("name", ["dgp", "kmo3", "poisson"])
+@pytest.mark.parametrize("cycle", [mg.CYCLE_V, mg.CYCLE_F])
+def test_smallest_meshes_converged_parity(n, name, cycle):
+    # the smallest meshes: every level below the finest runs in the
+    # single-workgroup tail (8^3: only the 4^3 level)
+    gp, om = models(n)[name]
+    delta = inputs.lognormal_delta(n, 41)
+    r = oracle.solve(om, delta, tol=1e-11, max_cycles=80, cycle=cycle)
+    fn = {"dgp": mg.lib().mg_solve_dgp, "kmo3": mg.lib().mg_solve_kmouflage,
+          "poisson": mg.lib().mg_solve_poisson}[name]
+    model = {"dgp": 0, "kmo3": 1, "poisson": 2}[name]
+    phi, st = mg._solve(fn, gp, model, g(delta), None, None, tol=1e-11, max_cycles=80,
+                        cycle=cycle)
+    assert st["status"] == 0 and st["cycles"] == r.cycles
+    assert rel(c(phi), r.phi) <= 1e-9
