@@ -540,3 +540,22 @@ def test_smallest_meshes_converged_parity(n, name, cycle):
                         cycle=cycle)
     assert st["status"] == 0 and st["cycles"] == r.cycles
     assert rel(c(phi), r.phi) <= 1e-9
+
+
+@pytest.mark.parametrize("n", [16, 128])
+def test_zero_source_and_zero_cycles(n):
+    # delta = 0 from phi = 0: the initial residual is already 0, no cycle
+    # runs and phi stays exactly 0, for every model
+    z = g(np.zeros((n, n, n)))
+    for name, fn, model in (("dgp", mg.lib().mg_solve_dgp, 0),
+                            ("kmo3", mg.lib().mg_solve_kmouflage, 1),
+                            ("poisson", mg.lib().mg_solve_poisson, 2)):
+        gp, _ = models(n)[name]
+        phi, st = mg._solve(fn, gp, model, z, None, None, tol=1e-8, max_cycles=10)
+        assert st["status"] == 0 and st["cycles"] == 0 and st["eps"] == 0.0
+        assert torch.count_nonzero(phi).item() == 0
+    # max_cycles = 0 returns the initial guess in the zero-mean gauge
+    phi0 = inputs.uniform_phi(n, 8)
+    phi, st = mg.solve_dgp(g(inputs.lognormal_delta(n, 9)), g(phi0), tol=1e-8, max_cycles=0)
+    assert st["cycles"] == 0 and st["status"] == mg.MG_NOT_CONVERGED
+    assert np.abs(c(phi) - (phi0 - phi0.mean())).max() <= 1e-14 * np.abs(phi0).max()
