@@ -232,6 +232,17 @@ def other_solves(mg, delta, phi_dgp):
     return res
 
 
+def pm_phases(sts):
+    """Mean GPU time of a PM step's phases (HIP events in the library) and the
+    cycles of its two field solves."""
+    import numpy as np
+    names = ("cic", "newtonian_solve", "scalar_solve", "potential_kick_drift")
+    return {"phase_ms": {k: float(np.mean([s["pm_ms"][q] for s in sts]))
+                         for q, k in enumerate(names)},
+            "newtonian_cycles_per_step": float(np.mean([s["pm_newton_cycles"] for s in sts])),
+            "scalar_cycles_per_step": float(np.mean([s["cycles"] for s in sts]))}
+
+
 def pm_steps(mg, pos0, dev, steps=3):
     """Particle-mesh steps of both models on the bench workload (512^3 mesh,
     256^3 particles, L = 512 Mpc/h) from a = 0.5, da = 0.01: CIC, Newtonian
@@ -245,7 +256,11 @@ def pm_steps(mg, pos0, dev, steps=3):
         phi = torch.zeros((N_MESH,) * 3, dtype=torch.float64, device=dev)
         phin = torch.zeros_like(phi)
         ws = torch.empty(mg.lib().mg_pm_workspace_bytes(N_MESH), dtype=torch.uint8, device=dev)
-        a, da, times, cycles = 0.5, 0.01, [], []
+        a, da, times, sts = 0.5, 0.01, [], []
+        table = None
+        if model == "kmouflage":   # background table of every step's a and a + da/2
+            pts = [0.5 + q * da for q in range(steps + 1)]
+            table = mg.kmo_background(2, 1.0, 0.2, sorted(pts + [x + 0.5 * da for x in pts]))
         for s in range(steps + 1):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -253,15 +268,14 @@ def pm_steps(mg, pos0, dev, steps=3):
                 _, st = mg.pm_step(pos, mom, phi, phin, N_MESH, a, da, h0rc=H0RC, ws=ws, tol=TOL)
             else:
                 _, st = mg.pm_step_kmouflage(pos, mom, phi, phin, N_MESH, a, da, BOX, 2, 1.0, 0.2,
-                                             ws=ws, tol=TOL)
+                                             table=table, ws=ws, tol=TOL)
             torch.cuda.synchronize()
             assert st["status"] >= 0
             if s:
                 times.append(time.perf_counter() - t0)
-                cycles.append(st["cycles"])
+                sts.append(st)
             a += da
-        res[model] = {"ms_per_step": 1e3 * float(np.mean(times)),
-                      "scalar_cycles_per_step": float(np.mean(cycles))}
+        res[model] = {"ms_per_step": 1e3 * float(np.mean(times)), **pm_phases(sts)}
         del ws, phi, phin
         torch.cuda.empty_cache()
     res["config"] = "512^3 mesh, 256^3 particles, L=512 Mpc/h, a=0.5, da=0.01, tol=1e-8; " \
@@ -291,7 +305,7 @@ def pm_step_1024(mg, dev, pos, steps=2):
     phi = torch.zeros((n,) * 3, dtype=torch.float64, device=dev)
     phin = torch.zeros_like(phi)
     ws = torch.empty(mg.lib().mg_pm_workspace_bytes(n), dtype=torch.uint8, device=dev)
-    a, da, times, cycles = 1.0, 0.0063, [], []
+    a, da, times, sts = 1.0, 0.0063, [], []
     for s in range(steps + 1):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -300,12 +314,11 @@ def pm_step_1024(mg, dev, pos, steps=2):
         assert st["status"] >= 0
         if s:
             times.append(time.perf_counter() - t0)
-            cycles.append(st["cycles"])
+            sts.append(st)
         a += da
     del pos, mom, phi, phin, ws
     torch.cuda.empty_cache()
-    return {"ms_per_step": 1e3 * float(np.mean(times)),
-            "scalar_cycles_per_step": float(np.mean(cycles)),
+    return {"ms_per_step": 1e3 * float(np.mean(times)), **pm_phases(sts),
             "config": "1024^3 mesh, 512^3 particles, L=1 Gpc/h, a=1, da=0.0063, tol=1e-8"}
 
 
@@ -339,16 +352,20 @@ def main():
     delta = torch.empty((N_MESH,) * 3, dtype=torch.float64, device=dev)
     phi = torch.empty_like(delta)
     par = mg.dgp_params(A, OMEGA_M, H0RC)
-    opts = mg.make_opts(N_MESH, tol=TOL, max_cycles=60, profile=True)
+    # the timed steps run the production solve; one extra untimed step with
+    # profile = 1 (HIP events around every finest pass and level) gives the
+    # pass duration and the per-level split
+    opts = mg.make_opts(N_MESH, tol=TOL, max_cycles=60)
+    opts_prof = mg.make_opts(N_MESH, tol=TOL, max_cycles=60, profile=True)
     import ctypes as C
 
-    def step():
+    def step(o=opts):
         stream = mg._stream()
         mg._raise(L.mg_cic_delta(N_MESH, N_PART, mg._ptr(pos), mg._ptr(delta), mg._ptr(ws_pm),
                                  ws_pm.numel(), stream))
         phi.zero_()
         st = mg.Stats()
-        mg._raise(L.mg_solve_dgp(C.byref(opts), C.byref(par), mg._ptr(delta), mg._ptr(phi),
+        mg._raise(L.mg_solve_dgp(C.byref(o), C.byref(par), mg._ptr(delta), mg._ptr(phi),
                                  mg._ptr(ws), ws.numel(), stream, C.byref(st)))
         return st
 
@@ -361,13 +378,16 @@ def main():
         stats.append(step())
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    prof = step(opts_prof)
+    torch.cuda.synchronize()
 
     cycles = [s.cycles for s in stats]
     assert all(s.status == 0 and s.eps <= TOL for s in stats), [s.status for s in stats]
+    assert prof.status == 0 and prof.cycles == cycles[-1], (prof.status, prof.cycles)
     updates = sum(N_MESH ** 3 * 2 * c for c in cycles)
     ms_step = 1e3 * dt / args.steps
     solve_ms = 1e3 * float(np.mean([s.seconds for s in stats]))
-    pass_ms = float(np.mean([s.pass_ms_avg for s in stats]))
+    pass_ms = prof.pass_ms_avg
     achieved = PASS_BYTES_PER_CELL * N_MESH ** 3 / (pass_ms * 1e-3) / 1e9
     traffic = measured_traffic()
     out = {
@@ -389,8 +409,9 @@ def main():
                    "tol": TOL, "precision": "fp64"},
         "cycles": int(round(float(np.mean(cycles)))),
         "time_to_tol_ms": solve_ms,
-        "level_ms_per_cycle": [round(sum(s.level_ms[l] for s in stats) / sum(cycles), 4)
-                               for l in range(mg.LEVELS) if stats[0].level_ms[l] > 0],
+        "level_ms_per_cycle": [round(prof.level_ms[l] / prof.cycles, 4)
+                               for l in range(mg.LEVELS) if prof.level_ms[l] > 0],
+        "profiled_step": {"time_to_tol_ms": 1e3 * prof.seconds, "pass_count": prof.pass_count},
         "ms_per_vcycle": solve_ms / float(np.mean(cycles)),
         "roofline": {"bound": "hbm", "kernel": "k_pass_tiled<OP_DGP, double> (finest colour pass)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

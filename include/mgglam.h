@@ -114,6 +114,11 @@ typedef struct {
                                    the levels of the single-workgroup tail (<= 16^3) are
                                    reported together at the tail's first level; the residual
                                    evaluations outside the cycles are not included */
+    double pm_ms[4];            /* mg_pm_step, mg_pm_step_kmouflage: GPU time (HIP events on
+                                   the stream) of the step's phases: CIC deposit, Newtonian
+                                   potential solve, scalar-field solve, total potential +
+                                   force interpolation + kick-drift */
+    int pm_newton_cycles;       /* mg_pm_step*: cycles of the Newtonian potential solve */
 } mg_stats;
 
 /* nDGP background (eq:beta_dgp with the LCDM expansion eq:H_lcdm, flat,
@@ -258,23 +263,37 @@ mg_status mg_pm_step(const mg_pm_params *par, float *pos, float *mom, double *ph
                      double *phi_newton, double *delta_out, void *ws, size_t ws_bytes,
                      hipStream_t stream, mg_stats *stats);
 
-/* One Kmouflage particle-mesh step (Sec. 3.2.4): CIC density, Newtonian
- * potential with the rescaled mass, lap Phi_N = 1.5 A(phibar) Omega_m delta / a
- * (eq:kmf_Poission_eqn_codeunit), the scalar field of eq:kmf_eqn_codeunit_final
- * (warm start from phi), and eq:force_Kmo1/2: kick
+/* Host table of a Kmouflage background, as mg_kmo_background returns it:
+ * n strictly increasing scale factors a with hubble = H/H0, phibar and
+ * dphibar_dtau there, and the model's lambda (mg_kmo_bg_info.lambda).  The
+ * caller owns the arrays. */
+typedef struct {
+    int n;
+    const double *a, *hubble, *phibar, *dphibar_dtau;
+    double lambda;
+} mg_kmo_bg_table;
+
+/* One Kmouflage particle-mesh step (Sec. 3.2.4) from a to a + da: CIC
+ * density, Newtonian potential with the rescaled mass,
+ * lap Phi_N = 1.5 A(phibar) Omega_m delta / a (eq:kmf_Poission_eqn_codeunit),
+ * the scalar field of eq:kmf_eqn_codeunit_final (warm start from phi), and
+ * eq:force_Kmo1/2: kick
  * p <- (1 - beta (d phibar/da) da) p - (da / (a E(a))) grad(Phi_N + beta c~ phi)
- * at a, drift x += da / (a_h^3 E(a_h)) p at a_h = a + da/2.  The background
- * values (E at a and a_h, d phibar/da, and kmo.lambda / phibar /
- * dphibar_dtau_over_h0 at a) come from mg_kmo_background.  Same arrays and
- * workspace as mg_pm_step. */
+ * at a, drift x += da / (a_h^3 E(a_h)) p at a_h = a + da/2 (a_h <= 1).  The
+ * library derives every background value the step needs -- lambda, phibar
+ * and its conformal-time derivative at a, E at a and a_h, and
+ * d phibar/da = (d phibar/d tau) / (a^2 E(a)) -- from the background of bg:
+ * looked up in table when given (it must hold a and a_h, relative match
+ * 1e-12), otherwise solved by the library for this step (as
+ * mg_kmo_background does, a few ms of host time).  c~ = (n_mesh / box_mpch)
+ * c/H0.  Same arrays and workspace as mg_pm_step. */
 typedef struct {
     int n_mesh, n_part;
     double a, da;
-    mg_kmo_params kmo;   /* field parameters at a (kmo.a == a) */
-    double e_a;          /* H/H0 of the Kmouflage background at a */
-    double e_half;       /* H/H0 at a + da/2 */
-    double dphibar_da;   /* d phibar / d a at a */
-    mg_opts mg;          /* options of both field solves; mg.n must equal n_mesh */
+    double box_mpch;
+    mg_kmo_bg_params bg;           /* model (n_k, K0, beta) and background cosmology */
+    const mg_kmo_bg_table *table;  /* HOST, optional (NULL: solve the background here) */
+    mg_opts mg;                    /* options of both field solves; mg.n must equal n_mesh */
 } mg_pm_kmo_params;
 mg_status mg_pm_step_kmouflage(const mg_pm_kmo_params *par, float *pos, float *mom, double *phi,
                                double *phi_newton, double *delta_out, void *ws, size_t ws_bytes,

@@ -59,7 +59,8 @@ class Stats(C.Structure):
                 ("cell_updates", C.c_longlong), ("n_clamped", C.c_longlong),
                 ("seconds", C.c_double), ("pass_ms_avg", C.c_double), ("pass_count", C.c_int),
                 ("cycles_fp32", C.c_int), ("eps_fp32", C.c_double),
-                ("level_ms", C.c_double * LEVELS)]
+                ("level_ms", C.c_double * LEVELS), ("pm_ms", C.c_double * 4),
+                ("pm_newton_cycles", C.c_int)]
 
     def as_dict(self):
         k = min(self.cycles, HIST)
@@ -68,7 +69,8 @@ class Stats(C.Structure):
                     cell_updates=self.cell_updates, n_clamped=self.n_clamped,
                     seconds=self.seconds, pass_ms_avg=self.pass_ms_avg,
                     pass_count=self.pass_count, cycles_fp32=self.cycles_fp32,
-                    eps_fp32=self.eps_fp32, level_ms=list(self.level_ms))
+                    eps_fp32=self.eps_fp32, level_ms=list(self.level_ms),
+                    pm_ms=list(self.pm_ms), pm_newton_cycles=self.pm_newton_cycles)
 
 
 class DgpParams(C.Structure):
@@ -102,10 +104,15 @@ class PmParams(C.Structure):
                 ("h0rc", C.c_double), ("a", C.c_double), ("da", C.c_double), ("mg", Opts)]
 
 
+class KmoBgTable(C.Structure):
+    _fields_ = [("n", C.c_int), ("a", C.c_void_p), ("hubble", C.c_void_p),
+                ("phibar", C.c_void_p), ("dphibar_dtau", C.c_void_p), ("lambda_", C.c_double)]
+
+
 class PmKmoParams(C.Structure):
     _fields_ = [("n_mesh", C.c_int), ("n_part", C.c_int), ("a", C.c_double), ("da", C.c_double),
-                ("kmo", KmoParams), ("e_a", C.c_double), ("e_half", C.c_double),
-                ("dphibar_da", C.c_double), ("mg", Opts)]
+                ("box_mpch", C.c_double), ("bg", KmoBgParams), ("table", C.POINTER(KmoBgTable)),
+                ("mg", Opts)]
 
 
 _lib = None
@@ -347,13 +354,22 @@ def solve_adjoint(model, par, delta, phi, w, mu0=None, ws=None, tol=1e-10, max_c
     return grad, mu, st.as_dict()
 
 
+def _require_converged(st, what):
+    # an unconverged field (MG_NOT_CONVERGED) would give a silently wrong
+    # gradient; a clamped discriminant (MG_WARN_CLAMPED) is converged
+    if st["status"] == MG_NOT_CONVERGED:
+        raise MGError(MG_NOT_CONVERGED, "%s did not converge (residual %.3g after %d cycles)"
+                      % (what, st["eps"], st["cycles"]))
+
+
 class DGPSolve(torch.autograd.Function):
     """phi = solve_dgp(delta); backward through the adjoint multigrid."""
 
     @staticmethod
     def forward(ctx, delta, h0rc=1.0, a=1.0, omega_m=OMEGA_M, tol=1e-10):
-        phi, _ = solve_dgp(delta.detach(), a=a, omega_m=omega_m, h0rc=h0rc, tol=tol,
-                           max_cycles=100)
+        phi, st = solve_dgp(delta.detach(), a=a, omega_m=omega_m, h0rc=h0rc, tol=tol,
+                            max_cycles=100)
+        _require_converged(st, "forward nDGP solve")
         ctx.save_for_backward(delta.detach(), phi)
         ctx.par = dgp_params(a, omega_m, h0rc)
         ctx.tol = tol
@@ -362,8 +378,9 @@ class DGPSolve(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_phi):
         delta, phi = ctx.saved_tensors
-        g, _, _ = solve_adjoint(MODEL_DGP, ctx.par, delta, phi, grad_phi.contiguous(),
-                                tol=ctx.tol, max_cycles=100)
+        g, _, st = solve_adjoint(MODEL_DGP, ctx.par, delta, phi, grad_phi.contiguous(),
+                                 tol=ctx.tol, max_cycles=100)
+        _require_converged(st, "adjoint solve")
         return g, None, None, None, None
 
 
@@ -382,10 +399,34 @@ def cic_delta(pos, n_mesh: int, ws=None):
     return delta
 
 
+def _check_pm(pos, mom, phi, phi_newton, n_mesh, require_gpu=True):
+    """Arguments of a PM step: pos and mom float32 [n_part^3, 3] (same shape,
+    contiguous, a cube number of particles), phi and phi_newton float64
+    contiguous n_mesh^3 cubes, all on the GPU.  Returns n_part; raises before
+    anything reaches the library."""
+    for t, nm in ((pos, "pos"), (mom, "mom")):
+        if not isinstance(t, torch.Tensor) or (require_gpu and not t.is_cuda):
+            raise TypeError("%s must be a GPU tensor" % nm)
+        if t.dtype != torch.float32 or t.dim() != 2 or t.shape[1] != 3 or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous float32 [n_part^3, 3] tensor" % nm)
+    if mom.shape != pos.shape:
+        raise ValueError("pos and mom must have the same shape")
+    n_part = round(pos.shape[0] ** (1.0 / 3.0))
+    if n_part < 1 or n_part ** 3 != pos.shape[0]:
+        raise ValueError("number of particles must be a positive cube")
+    for t, nm in ((phi, "phi"), (phi_newton, "phi_newton")):
+        if not isinstance(t, torch.Tensor) or (require_gpu and not t.is_cuda):
+            raise TypeError("%s must be a GPU tensor" % nm)
+        if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != (n_mesh,) * 3:
+            raise ValueError("%s must be a contiguous float64 tensor of shape (%d, %d, %d)"
+                             % ((nm,) + (n_mesh,) * 3))
+    return n_part
+
+
 def pm_step(pos, mom, phi, phi_newton, n_mesh, a, da, h0rc=1.0, omega_m=OMEGA_M, ws=None, **kw):
     """One nDGP PM step in place on pos/mom (float32 [n^3,3]), phi and phi_newton
     (float64 warm starts, updated).  Returns (delta, stats)."""
-    n_part = round(pos.shape[0] ** (1.0 / 3.0))
+    n_part = _check_pm(pos, mom, phi, phi_newton, n_mesh)
     delta = torch.empty((n_mesh,) * 3, dtype=torch.float64, device=pos.device)
     if ws is None:
         ws = torch.empty(lib().mg_pm_workspace_bytes(n_mesh), dtype=torch.uint8, device=pos.device)
@@ -396,38 +437,37 @@ def pm_step(pos, mom, phi, phi_newton, n_mesh, a, da, h0rc=1.0, omega_m=OMEGA_M,
     return delta, st.as_dict()
 
 
-def kmo_pm_background(n_k, k0, beta, a, da, omega_m=OMEGA_M):
-    """Background inputs of a Kmouflage PM step from the library's background
-    solver: lambda, E at a and a + da/2, phibar, phibar' and d phibar/da at a."""
-    ah = a + 0.5 * da
-    pts = sorted({a, ah})          # the table must increase strictly
-    bg = kmo_background(n_k, k0, beta, pts, omega_m)
-    ia, ih = pts.index(a), pts.index(ah)
-    e_a = float(bg["hubble"][ia])
-    dtau = float(bg["dphibar_dtau"][ia])
-    return dict(lam=bg["lambda"], e_a=e_a, e_half=float(bg["hubble"][ih]),
-                phibar=float(bg["phibar"][ia]), dphibar_dtau=dtau, dphibar_da=dtau / (a * a * e_a))
+def kmo_bg_params(n_k, k0, beta, omega_m=OMEGA_M, omega_r=None, z_init=1e5, htol=1e-10):
+    """mg_kmo_bg_params of a Kmouflage model (omega_r from omega_radiation())."""
+    return KmoBgParams(n_k, k0, beta, omega_m, omega_radiation() if omega_r is None else omega_r,
+                       z_init, htol)
 
 
 def pm_step_kmouflage(pos, mom, phi, phi_newton, n_mesh, a, da, box_mpch, n_k=2, k0=1.0,
-                      beta=0.2, omega_m=OMEGA_M, bgv=None, ws=None, **kw):
+                      beta=0.2, omega_m=OMEGA_M, table=None, ws=None, **kw):
     """One Kmouflage PM step in place on pos/mom (float32 [n^3,3]), phi and
-    phi_newton (float64 warm starts, updated); bgv: kmo_pm_background (computed
-    when None).  Returns (delta, stats)."""
-    if bgv is None:
-        bgv = kmo_pm_background(n_k, k0, beta, a, da, omega_m)
-    n_part = round(pos.shape[0] ** (1.0 / 3.0))
+    phi_newton (float64 warm starts, updated).  The library derives the
+    background values of the step; table (a kmo_background() result holding
+    a and a + da/2) spares it the background solve.  Returns (delta, stats)."""
+    import numpy as np
+    n_part = _check_pm(pos, mom, phi, phi_newton, n_mesh)
     delta = torch.empty((n_mesh,) * 3, dtype=torch.float64, device=pos.device)
     if ws is None:
         ws = torch.empty(lib().mg_pm_workspace_bytes(n_mesh), dtype=torch.uint8, device=pos.device)
-    kmo = KmoParams(n_k, k0, beta, bgv["lam"], a, omega_m, box_mpch, bgv["phibar"],
-                    bgv["dphibar_dtau"])
-    par = PmKmoParams(n_mesh, n_part, a, da, kmo, bgv["e_a"], bgv["e_half"], bgv["dphibar_da"],
-                      make_opts(n_mesh, **kw))
+    tab, keep = None, None
+    if table is not None:
+        keep = [np.ascontiguousarray(table[k], dtype=np.float64)
+                for k in ("a", "hubble", "phibar", "dphibar_dtau")]
+        if len({x.size for x in keep}) != 1:
+            raise ValueError("table arrays must have equal lengths")
+        tab = KmoBgTable(keep[0].size, *[x.ctypes.data for x in keep], table["lambda"])
+    par = PmKmoParams(n_mesh, n_part, a, da, box_mpch, kmo_bg_params(n_k, k0, beta, omega_m),
+                      C.pointer(tab) if tab is not None else None, make_opts(n_mesh, **kw))
     st = Stats()
     _raise(lib().mg_pm_step_kmouflage(C.byref(par), _ptr(pos), _ptr(mom), _ptr(phi),
                                       _ptr(phi_newton), _ptr(delta), _ptr(ws), ws.numel(),
                                       _stream(), C.byref(st)))
+    del keep
     return delta, st.as_dict()
 
 

@@ -251,6 +251,77 @@ mg_status cic(int n_mesh, int n_part, const float *pos, double *delta, unsigned 
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// GPU time of the phases of a PM step (CIC, Newtonian potential, scalar
+// field, total potential + kick-drift): HIP events on the step's stream at
+// the phase boundaries, read after the step's final synchronisation.
+struct PhaseTimer {
+    static constexpr int NP = 4;
+    hipEvent_t ev[NP + 1] = {};
+    bool ok = true;
+    hipStream_t st;
+    explicit PhaseTimer(hipStream_t s) : st(s) {
+        for (auto &e : ev)
+            if (ok && hipEventCreate(&e) != hipSuccess) ok = false;
+        if (!ok) (void)hipGetLastError();
+    }
+    void mark(int q) {
+        if (ok && hipEventRecord(ev[q], st) != hipSuccess) ok = false;
+    }
+    void read(mg_stats *s) {
+        for (int q = 0; q < NP; ++q) {
+            float ms = 0.f;
+            if (ok && hipEventElapsedTime(&ms, ev[q], ev[q + 1]) == hipSuccess)
+                s->pm_ms[q] = ms;
+        }
+        (void)hipGetLastError();
+    }
+    ~PhaseTimer() {
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+// Background values of a Kmouflage step at a: lambda, phibar, d phibar/d tau
+// and E = H/H0 at a and at a_h = a + da/2, from the caller's table or from
+// the background solver.
+struct KmoStepBg {
+    double lambda, phibar, dphibar_dtau, e_a, e_half;
+};
+
+// index of x in the increasing host array t (relative match 1e-12), or -1
+int table_index(const double *t, int n, double x) {
+    for (int k = 0; k < n; ++k)
+        if (std::fabs(t[k] - x) <= 1e-12 * std::fabs(x)) return k;
+    return -1;
+}
+
+mg_status kmo_step_background(const mg_pm_kmo_params *par, KmoStepBg &b) {
+    const double a = par->a, ah = a + 0.5 * par->da;
+    const mg_kmo_bg_table *T = par->table;
+    if (T) {
+        if (T->n < 1 || !T->a || !T->hubble || !T->phibar || !T->dphibar_dtau ||
+            !(T->lambda > 0.0))
+            return fail(MG_ERR_ARG, "background table: n >= 1 host arrays and lambda > 0 needed");
+        const int ia = table_index(T->a, T->n, a), ih = table_index(T->a, T->n, ah);
+        if (ia < 0 || ih < 0)
+            return fail(MG_ERR_ARG, "background table must hold a and a + da/2");
+        b = {T->lambda, T->phibar[ia], T->dphibar_dtau[ia], T->hubble[ia], T->hubble[ih]};
+    } else {
+        // the background solver tabulates at a and a_h (one point when da = 0)
+        const double at[2] = {a, ah};
+        const int nt = ah > a ? 2 : 1;
+        double hub[2], hdot[2], pb[2], pd[2];
+        mg_kmo_bg_info info;
+        const mg_status rc = mg_kmo_background(&par->bg, nt, at, hub, hdot, pb, pd, &info);
+        if (rc != MG_OK) return rc;
+        b = {info.lambda, pb[0], pd[0], hub[0], hub[nt - 1]};
+    }
+    if (!(b.e_a > 0.0) || !(b.e_half > 0.0) || !std::isfinite(b.phibar) ||
+        !std::isfinite(b.dphibar_dtau))
+        return fail(MG_ERR_ARG, "background values are not finite and positive");
+    return MG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -297,17 +368,22 @@ mg_status mg_pm_step(const mg_pm_params *par, float *pos, float *mom, double *ph
     char *solver_ws = (char *)ws + align256(ncell * sizeof(unsigned long long));
     const size_t solver_bytes = ws_bytes - align256(ncell * sizeof(unsigned long long));
 
+    PhaseTimer T(stream);
+    T.mark(0);
     mg_status rc = cic(n, par->n_part, pos, delta_out, counts, stream);
     if (rc != MG_OK) return rc;
+    T.mark(1);
     // Newtonian potential, eq:GR_poisson_codeunit
     mg_poisson_params pp{1.5 * par->omega_m / par->a};
     mg_stats pst;
     rc = mg_solve_poisson(&par->mg, &pp, delta_out, phi_newton, solver_ws, solver_bytes, stream, &pst);
     if (rc < 0) return rc;
+    T.mark(2);
     // scalar field, eq:dgp_eom_code
     mg_dgp_params dp{par->a, par->omega_m, par->h0rc};
     rc = mg_solve_dgp(&par->mg, &dp, delta_out, phi, solver_ws, solver_bytes, stream, stats);
     if (rc < 0) return rc;
+    T.mark(3);
     // leapfrog: kick with H0/adot = 1/(a E(a)) at a, drift with
     // H0/(a^2 adot) at a + da/2 (E^2 = Omega_m a^-3 + 1 - Omega_m)
     const double om = par->omega_m;
@@ -321,8 +397,11 @@ mg_status mg_pm_step(const mg_pm_params *par, float *pos, float *mom, double *ph
     double *psi = reinterpret_cast<double *>(counts);
     k_total_potential<<<nb(ncell), PTPB, 0, stream>>>(phi_newton, phi, 0.5, psi, ncell);
     k_kick_drift<<<nb(np), PTPB, 0, stream>>>(pos, mom, np, ilog2(n), psi, 1.0, kick, drift);
+    T.mark(4);
     const mg_status hs = hip_status(stream, true);
     if (hs != MG_OK) return hs;
+    T.read(stats);
+    stats->pm_newton_cycles = pst.cycles;
     if (pst.status == MG_NOT_CONVERGED && rc == MG_OK) rc = MG_NOT_CONVERGED;
     return rc;
 }
@@ -334,46 +413,59 @@ mg_status mg_pm_step_kmouflage(const mg_pm_kmo_params *par, float *pos, float *m
     if (!par || !pos || !mom || !phi || !phi_newton || !delta_out || !stats)
         return fail(MG_ERR_ARG, "a parameter, array or stats pointer is NULL");
     const int n = par->n_mesh;
-    const mg_kmo_params &K = par->kmo;
     if (!pow2(n) || n < 8 || n > 2048 || par->mg.n != n)
         return fail(MG_ERR_ARG, "n_mesh must be a power of two in [8, 2048] equal to mg.n");
-    if (par->n_part < 1 || par->n_part > 2048 || !(par->a > 0.0) || !std::isfinite(par->da) ||
-        K.a != par->a || !(par->e_a > 0.0) || !(par->e_half > 0.0) ||
-        !std::isfinite(par->dphibar_da) || !(K.box_mpch > 0.0) || !(K.omega_m > 0.0) ||
-        !(K.omega_m < 1.0))
-        return fail(MG_ERR_ARG, "invalid n_part, a, da, background values or kmo parameters");
+    if (par->n_part < 1 || par->n_part > 2048 || !(par->a > 0.0) || !(par->da >= 0.0) ||
+        !std::isfinite(par->da) || !(par->a + 0.5 * par->da <= 1.0) || !(par->box_mpch > 0.0) ||
+        !std::isfinite(par->box_mpch))
+        return fail(MG_ERR_ARG, "invalid n_part, a, da (need a + da/2 <= 1) or box_mpch");
     const size_t need = mg_pm_workspace_bytes(n);
     if (!ws || ws_bytes < need || ((uintptr_t)ws & 255))
         return fail(MG_ERR_WORKSPACE, "workspace is NULL, too small or not 256-byte aligned");
+    KmoStepBg bg;
+    mg_status rc = kmo_step_background(par, bg);
+    if (rc != MG_OK) return rc;
+    const double a = par->a, ah = a + 0.5 * par->da;
+    const mg_kmo_params K{par->bg.n_k,     par->bg.k0, par->bg.beta, bg.lambda,     a,
+                          par->bg.omega_m, par->box_mpch, bg.phibar, bg.dphibar_dtau};
     const size_t ncell = (size_t)n * n * n;
     unsigned long long *counts = (unsigned long long *)ws;
     char *solver_ws = (char *)ws + align256(ncell * sizeof(unsigned long long));
     const size_t solver_bytes = ws_bytes - align256(ncell * sizeof(unsigned long long));
 
-    mg_status rc = cic(n, par->n_part, pos, delta_out, counts, stream);
+    PhaseTimer T(stream);
+    T.mark(0);
+    rc = cic(n, par->n_part, pos, delta_out, counts, stream);
     if (rc != MG_OK) return rc;
+    T.mark(1);
     // Newtonian potential with the rescaled particle mass, eq:kmf_Poission_eqn_codeunit
     const double A = std::exp(K.beta * K.phibar);
-    mg_poisson_params pp{1.5 * A * K.omega_m / par->a};
+    mg_poisson_params pp{1.5 * A * K.omega_m / a};
     mg_stats pst;
     rc = mg_solve_poisson(&par->mg, &pp, delta_out, phi_newton, solver_ws, solver_bytes, stream, &pst);
     if (rc < 0) return rc;
+    T.mark(2);
     // scalar field, eq:kmf_eqn_codeunit_final
     rc = mg_solve_kmouflage(&par->mg, &K, delta_out, phi, solver_ws, solver_bytes, stream, stats);
     if (rc < 0) return rc;
+    T.mark(3);
     // eq:force_Kmo1/2: kick with H0/adot = 1/(a E(a)) and the velocity term
-    // at a, drift with H0/(a^2 adot) at a + da/2; E from the background
+    // at a, drift with H0/(a^2 adot) at a + da/2.  d phibar/da follows from
+    // the conformal-time derivative: da/dtau = a^2 E in units of H0.
     const double ctil = (double)n / K.box_mpch * 2997.92458;
-    const double a = par->a, ah = a + 0.5 * par->da;
-    const double kick = par->da / (a * par->e_a);
-    const double drift = par->da / (ah * ah * ah * par->e_half);
-    const double damp = 1.0 - K.beta * par->dphibar_da * par->da;
+    const double dphibar_da = bg.dphibar_dtau / (a * a * bg.e_a);
+    const double kick = par->da / (a * bg.e_a);
+    const double drift = par->da / (ah * ah * ah * bg.e_half);
+    const double damp = 1.0 - K.beta * dphibar_da * par->da;
     const size_t np = (size_t)par->n_part * par->n_part * par->n_part;
     double *psi = reinterpret_cast<double *>(counts);
     k_total_potential<<<nb(ncell), PTPB, 0, stream>>>(phi_newton, phi, K.beta * ctil, psi, ncell);
     k_kick_drift<<<nb(np), PTPB, 0, stream>>>(pos, mom, np, ilog2(n), psi, damp, kick, drift);
+    T.mark(4);
     const mg_status hs = hip_status(stream, true);
     if (hs != MG_OK) return hs;
+    T.read(stats);
+    stats->pm_newton_cycles = pst.cycles;
     if (pst.status == MG_NOT_CONVERGED && rc == MG_OK) rc = MG_NOT_CONVERGED;
     return rc;
 }

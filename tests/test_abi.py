@@ -162,8 +162,89 @@ def test_pm_entry_points_reject_bad_arguments_with_a_message(L):
     st = mg.Stats()
     assert L.mg_pm_step(C.byref(par), d, d, d, d, d, d, 1 << 40, None, C.byref(st)) == mg.MG_ERR_ARG
     assert b"mg.n" in L.mg_last_error()
-    kp = mg.PmKmoParams(32, 16, 0.5, 0.01, mg.kmo_params(32, 64.0, a=0.7), 1.0, 1.0, 0.0,
-                        mg.make_opts(32))
+    bgp = mg.kmo_bg_params(2, 1.0, 0.2)
+    kp = mg.PmKmoParams(32, 16, 0.99, 0.04, 64.0, bgp, None, mg.make_opts(32))
     assert L.mg_pm_step_kmouflage(C.byref(kp), d, d, d, d, d, d, 1 << 40, None,
                                   C.byref(st)) == mg.MG_ERR_ARG
-    assert b"kmo parameters" in L.mg_last_error()
+    assert b"a + da/2 <= 1" in L.mg_last_error()
+    # a table must hold a and a + da/2; the lookup fails before any GPU work
+    import numpy as np
+    arr = [np.array([0.5, 0.6]), np.ones(2), np.zeros(2), np.zeros(2)]
+    tab = mg.KmoBgTable(2, *[x.ctypes.data for x in arr], 1.2)
+    kp = mg.PmKmoParams(32, 16, 0.5, 0.01, 64.0, bgp, C.pointer(tab), mg.make_opts(32))
+    assert L.mg_pm_step_kmouflage(C.byref(kp), d, d, d, d, d, d, 1 << 40, None,
+                                  C.byref(st)) == mg.MG_ERR_ARG
+    assert b"a + da/2" in L.mg_last_error()
+    bad = mg.KmoBgParams(2, 1.0, 0.2, 1.5, 0.0, 1e5, 1e-10)   # Omega_m > 1
+    kp = mg.PmKmoParams(32, 16, 0.5, 0.01, 64.0, bad, None, mg.make_opts(32))
+    assert L.mg_pm_step_kmouflage(C.byref(kp), d, d, d, d, d, d, 1 << 40, None,
+                                  C.byref(st)) == mg.MG_ERR_ARG
+    assert b"background parameters" in L.mg_last_error()
+
+
+def _cpu_pm_args(n_part=4, n_mesh=8):
+    import torch
+    pos = torch.zeros((n_part ** 3, 3), dtype=torch.float32)
+    return pos, pos.clone(), torch.zeros((n_mesh,) * 3, dtype=torch.float64), \
+        torch.zeros((n_mesh,) * 3, dtype=torch.float64)
+
+
+def test_pm_binding_rejects_bad_tensors_before_the_library(monkeypatch):
+    # every malformed argument raises in the binding, before any library call
+    import torch
+    monkeypatch.setattr(mg, "lib", lambda: pytest.fail("library reached"))
+    pos, mom, phi, phin = _cpu_pm_args()
+    assert mg._check_pm(pos, mom, phi, phin, 8, require_gpu=False) == 4
+    cases = [
+        (pos.double(), mom, phi, phin),                      # pos dtype
+        (pos, mom[:-1], phi, phin),                          # mom shape
+        (pos[:-1], mom[:-1], phi, phin),                     # not a cube
+        (pos.t().contiguous().t(), mom, phi, phin),          # non-contiguous
+        (pos, mom, phi.float(), phin),                       # phi dtype
+        (pos, mom, phi, torch.zeros((8, 8, 4), dtype=torch.float64)),   # phi_newton shape
+        (pos, mom, torch.zeros((16,) * 3, dtype=torch.float64), phin),  # phi size != n_mesh
+        (pos[:, :2].contiguous(), mom[:, :2].contiguous(), phi, phin),  # not [N, 3]
+    ]
+    for args in cases:
+        with pytest.raises((ValueError, TypeError)):
+            mg._check_pm(*args, 8, require_gpu=False)
+    # the public entry points refuse host tensors outright
+    for fn, extra in ((mg.pm_step, ()), (mg.pm_step_kmouflage, (64.0,))):
+        with pytest.raises(TypeError):
+            fn(pos, mom, phi, phin, 8, 0.5, 0.01, *extra)
+
+
+def test_autograd_refuses_an_unconverged_solve():
+    with pytest.raises(mg.MGError):
+        mg._require_converged({"status": mg.MG_NOT_CONVERGED, "eps": 1e-3, "cycles": 5}, "x")
+    mg._require_converged({"status": mg.MG_WARN_CLAMPED, "eps": 1e-12, "cycles": 5}, "x")
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    # sizes and field offsets of every ABI struct, compiled from
+    # include/mgglam.h by the host C compiler, against the ctypes mirrors
+    import os
+    import subprocess
+    pairs = {"mg_opts": mg.Opts, "mg_stats": mg.Stats, "mg_dgp_params": mg.DgpParams,
+             "mg_kmo_params": mg.KmoParams, "mg_kmo_bg_params": mg.KmoBgParams,
+             "mg_kmo_bg_info": mg.KmoBgInfo, "mg_poisson_params": mg.PoissonParams,
+             "mg_pm_params": mg.PmParams, "mg_kmo_bg_table": mg.KmoBgTable,
+             "mg_pm_kmo_params": mg.PmKmoParams}
+    lines, expect = [], []
+    for cname, py in pairs.items():
+        lines.append('printf("%%zu\\n", sizeof(%s));' % cname)
+        expect.append(C.sizeof(py))
+        for fname, _ in py._fields_:
+            cf = fname.rstrip("_")
+            lines.append('printf("%%zu\\n", offsetof(%s, %s));' % (cname, cf))
+            expect.append(getattr(py, fname).offset)
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"mgglam.h\"\n"
+                   "int main(void) {\n" + "\n".join(lines) + "\nreturn 0;\n}\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(mg.HEADER))
+    rocm = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "include")
+    subprocess.check_call(["gcc", "-D__HIP_PLATFORM_AMD__", "-I" + rocm, "-I" + inc, str(src),
+                           "-o", str(exe)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert got == expect

@@ -44,7 +44,9 @@ def test_linear_fifth_force_ratios_on_gpu():
     assert (0.5 * pf @ pn) / (pn @ pn) == pytest.approx(1 / (3 * beta), rel=1e-4)
     # Kmouflage: beta c~ phi = 2 beta^2 / K_X Phi_N, background from the library
     box, nk, k0, bk = 256.0, 2, 1.0, 0.2
-    v = mg.kmo_pm_background(nk, k0, bk, a, 0.0)
+    bgr = mg.kmo_background(nk, k0, bk, [a])
+    v = dict(lam=bgr["lambda"], phibar=float(bgr["phibar"][0]),
+             dphibar_dtau=float(bgr["dphibar_dtau"][0]))
     A = np.exp(bk * v["phibar"])
     d5 = g(sine(n, 1e-5))
     phin, _ = mg.solve_poisson(d5, 1.5 * A * OM / a, tol=1e-18, max_cycles=100)
@@ -123,6 +125,13 @@ def test_gpu_pm_runs_follow_linear_growth():
     tab = {bt: mg.kmo_background(nk, k0, bt, ap) for bt in (0.0, beta)}
     sp = {bt: {k: CubicSpline(ap, tab[bt][k]) for k in ("hubble", "phibar", "dphibar_dtau")}
           for bt in tab}
+    # the library's background table at every step's a and a + da/2 (the
+    # Kmouflage steps look their background values up in it)
+    steps_a, a = [], a0
+    for _ in range(nst):
+        steps_a += [a, a + 0.5 * da]
+        a += da
+    step_tab = {bt: mg.kmo_background(nk, k0, bt, sorted(set(steps_a))) for bt in (0.0, beta)}
     runs = {}
     for name in ("dgp", "kmo", "lcdm"):
         gp, gm = g(x0), g(p0)
@@ -133,8 +142,9 @@ def test_gpu_pm_runs_follow_linear_growth():
             if name == "dgp":
                 _, st = mg.pm_step(gp, gm, phi, phin, n, a, da, h0rc=h0rc)
             else:
-                _, st = mg.pm_step_kmouflage(gp, gm, phi, phin, n, a, da, box, nk, k0,
-                                             beta if name == "kmo" else 0.0)
+                bt = beta if name == "kmo" else 0.0
+                _, st = mg.pm_step_kmouflage(gp, gm, phi, phin, n, a, da, box, nk, k0, bt,
+                                             table=step_tab[bt])
             assert st["status"] in (0, 2)
             a += da
         runs[name] = mg.cic_delta(gp, n)
