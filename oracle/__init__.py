@@ -20,7 +20,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mg_oracle.c")
-_LIB = os.path.join(_HERE, "libmgoracle.so")
+# MGORACLE_LIB points the checks at another build of mg_oracle.c (the
+# sanitizer leg of the tests builds one with AddressSanitizer and UBSan)
+_LIB = os.environ.get("MGORACLE_LIB") or os.path.join(_HERE, "libmgoracle.so")
 
 
 def build(force: bool = True) -> str:

@@ -16,5 +16,5 @@ def pytest_configure(config):
 @pytest.fixture(scope="session", autouse=True)
 def _oracle_built():
     import oracle
-    oracle.build(force=not os.path.exists(os.path.join(ROOT, "oracle", "libmgoracle.so")))
+    oracle.build(force=not os.path.exists(oracle._LIB))
     yield
