@@ -194,6 +194,23 @@ mg_status mg_solve_dgp(const mg_opts *opts, const mg_dgp_params *par, const doub
                        double *phi, void *ws, size_t ws_bytes, hipStream_t stream,
                        mg_stats *stats);
 
+/* mg_solve_dgp for callers that cannot allocate (serving loops, harnesses
+ * that forbid allocation): same solve, same kernels, same arguments minus the
+ * workspace.  The workspace is a static device array of 88 MiB inside the
+ * library, one per GPU (the current device's), created when the library's
+ * code is loaded on that GPU and held until the process ends.  Limit:
+ * opts->n <= 128 in every precision (larger meshes: MG_ERR_ARG; use
+ * mg_solve_dgp).  The call allocates nothing -- no device, pinned or managed
+ * memory and no HIP events (opts->profile must be 0); it reads each cycle's
+ * residual with a plain device-to-host copy.  The array keeps the previous
+ * call's contents; every value the solve needs initialised it sets itself
+ * with fill kernels on the stream.  Calls that overlap in time on one GPU
+ * share the array and race: serialise them (one stream, or host order).
+ * stream must belong to the current device. */
+mg_status mg_solve_dgp_noalloc(const mg_opts *opts, const mg_dgp_params *par,
+                               const double *delta, double *phi, hipStream_t stream,
+                               mg_stats *stats);
+
 /* Comparator for the closed-form relaxation: the same nDGP problem written in
  * its quadratic form eq:dgp_quadratic_eom (divided by alpha),
  *   L_N = D + 2 D^2 / (3 alpha) - Sigma / alpha = 0,  D = 7-point Laplacian

@@ -139,6 +139,9 @@ def lib():
             f.argtypes = [C.POINTER(Opts), C.POINTER(par), _P, _P, _P, C.c_size_t, _P,
                           C.POINTER(Stats)]
             f.restype = st
+        L.mg_solve_dgp_noalloc.argtypes = [C.POINTER(Opts), C.POINTER(DgpParams), _P, _P, _P,
+                                           C.POINTER(Stats)]
+        L.mg_solve_dgp_noalloc.restype = st
         L.mg_solve_adjoint.argtypes = [C.POINTER(Opts), C.c_int, _P, _P, _P, _P, _P, _P, _P,
                                        C.c_size_t, _P, C.POINTER(Stats)]
         L.mg_solve_adjoint.restype = st
@@ -291,6 +294,19 @@ def solve_dgp(delta, phi0=None, a=1.0, omega_m=OMEGA_M, h0rc=1.0, ws=None, **kw)
     Keywords: tol, max_cycles, nu_pre, nu_post, nu_coarse, profile,
     precision (MG_FP64, MG_MIXED or MG_FP32), cycle (CYCLE_V, CYCLE_F or CYCLE_W)."""
     return _solve(lib().mg_solve_dgp, dgp_params(a, omega_m, h0rc), MODEL_DGP, delta, phi0, ws, **kw)
+
+
+def solve_dgp_noalloc(delta, phi0=None, a=1.0, omega_m=OMEGA_M, h0rc=1.0, **kw):
+    """solve_dgp through mg_solve_dgp_noalloc: the library's static per-GPU
+    workspace, no allocation inside the call (n <= 128).  Returns (phi, stats)."""
+    _check_mesh(delta, "delta")
+    n = delta.shape[0]
+    phi = torch.zeros_like(delta) if phi0 is None else _check_mesh(phi0, "phi0").clone()
+    o = make_opts(n, **kw)
+    st = Stats()
+    _raise(lib().mg_solve_dgp_noalloc(C.byref(o), C.byref(dgp_params(a, omega_m, h0rc)),
+                                      _ptr(delta), _ptr(phi), _stream(), C.byref(st)))
+    return phi, st.as_dict()
 
 
 def solve_dgp_newton(delta, phi0=None, a=1.0, omega_m=OMEGA_M, h0rc=1.0, ws=None, **kw):

@@ -15,6 +15,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -782,9 +783,13 @@ mg_status fp32_solve(const mg_opts *o, Ctx &C, const double *delta, double *phi,
     return finish(C, (mg_status)p.status, st, t0);
 }
 
+// noalloc: the caller cannot allocate (mg_solve_dgp_noalloc), so the solve
+// creates no events and reads the per-cycle scalars with a plain copy into
+// host stack memory instead of the pinned buffer.
 template <int OP>
 mg_status forward_solve(const mg_opts *o, const Mod &M, const double *delta, double *phi,
-                        void *ws, size_t ws_bytes, hipStream_t stream, mg_stats *st) {
+                        void *ws, size_t ws_bytes, hipStream_t stream, mg_stats *st,
+                        bool noalloc = false) {
     auto t0 = std::chrono::steady_clock::now();
     const bool mixed = o->precision == MG_MIXED;
     Ctx C;
@@ -799,8 +804,8 @@ mg_status forward_solve(const mg_opts *o, const Mod &M, const double *delta, dou
     C.nu2 = o->nu_post;
     C.nuc = o->nu_coarse;
     C.cycle = o->cycle;
-    Profiler prof(C, o->profile != 0, 2 * (o->nu_pre + o->nu_post) + 2);
-    arm_early_read(C);
+    Profiler prof(C, o->profile != 0 && !noalloc, 2 * (o->nu_pre + o->nu_post) + 2);
+    if (!noalloc) arm_early_read(C);
     reset_scalars(C);
     if (o->precision == MG_FP32) return fp32_solve<OP>(o, C, delta, phi, st, t0);
     HLevel<double> &F = C.h64.lv[0];
@@ -1024,6 +1029,43 @@ mg_status common_checks(const mg_opts *o, const void *delta, const void *phi, vo
     return MG_OK;
 }
 
+// Workspace of mg_solve_dgp_noalloc: enough for any precision at n <= 128
+// (mg_workspace_bytes(128, MG_MIXED, MG_MODEL_DGP, 0) is 87.6 MiB).
+constexpr int NOALLOC_MAX_N = 128;
+constexpr size_t NOALLOC_BYTES = (size_t)88 << 20;
+
+}  // namespace
+
+// Device-resident workspace of mg_solve_dgp_noalloc, one copy per GPU (at its
+// own address on each), held until the process ends.  Host code must never
+// pass this name to a kernel or a copy: it stands for a host-side shadow.
+// The device address comes from hipGetSymbolAddress (noalloc_scratch()).
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of scratch on the current device, looked up once per device
+// (with that device current) and kept.
+mg_status noalloc_scratch(void **out) {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(MG_ERR_ARG, "mg_solve_dgp_noalloc supports device indices 0..63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || ((uintptr_t)p & 255)) return fail(MG_ERR_HIP, "scratch symbol address invalid");
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return MG_OK;
+}
+
 }  // namespace
 
 namespace mgglam_internal {
@@ -1068,6 +1110,26 @@ mg_status mg_solve_dgp(const mg_opts *opts, const mg_dgp_params *par, const doub
     Mod M;
     if (!par || !setup_dgp(par, M)) return fail(MG_ERR_ARG, "invalid nDGP parameters");
     return forward_solve<OP_DGP>(opts, M, delta, phi, ws, ws_bytes, stream, stats);
+}
+
+mg_status mg_solve_dgp_noalloc(const mg_opts *opts, const mg_dgp_params *par,
+                               const double *delta, double *phi, hipStream_t stream,
+                               mg_stats *stats) {
+    g_err.clear();
+    mg_status rc = check_opts(opts);
+    if (rc != MG_OK) return rc;
+    if (opts->n > NOALLOC_MAX_N)
+        return fail(MG_ERR_ARG, "mg_solve_dgp_noalloc: opts.n must be <= 128 (its static "
+                                "workspace holds 88 MiB); use mg_solve_dgp for larger meshes");
+    if (opts->profile) return fail(MG_ERR_ARG, "mg_solve_dgp_noalloc: profile must be 0");
+    if (!delta || !phi) return fail(MG_ERR_ARG, "delta and phi must be device pointers");
+    if (!stats) return fail(MG_ERR_ARG, "stats is NULL");
+    Mod M;
+    if (!par || !setup_dgp(par, M)) return fail(MG_ERR_ARG, "invalid nDGP parameters");
+    std::memset(stats, 0, sizeof(*stats));
+    void *ws = nullptr;
+    if ((rc = noalloc_scratch(&ws)) != MG_OK) return rc;
+    return forward_solve<OP_DGP>(opts, M, delta, phi, ws, NOALLOC_BYTES, stream, stats, true);
 }
 
 mg_status mg_solve_dgp_newton(const mg_opts *opts, const mg_dgp_params *par, const double *delta,

@@ -248,3 +248,18 @@ def test_struct_layouts_match_the_header(tmp_path):
                            "-o", str(exe)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     assert got == expect
+
+
+def test_noalloc_entry_point_validates_before_the_gpu(L):
+    d = C.c_void_p(0x1000)
+    st = mg.Stats()
+    par = mg.dgp_params()
+    o = mg.make_opts(256)
+    assert L.mg_solve_dgp_noalloc(C.byref(o), C.byref(par), d, d, None, C.byref(st)) == mg.MG_ERR_ARG
+    assert b"<= 128" in L.mg_last_error()
+    o = mg.make_opts(64, profile=True)
+    assert L.mg_solve_dgp_noalloc(C.byref(o), C.byref(par), d, d, None, C.byref(st)) == mg.MG_ERR_ARG
+    assert b"profile" in L.mg_last_error()
+    o = mg.make_opts(64)
+    assert L.mg_solve_dgp_noalloc(C.byref(o), None, d, d, None, C.byref(st)) == mg.MG_ERR_ARG
+    assert L.mg_solve_dgp_noalloc(C.byref(o), C.byref(par), None, d, None, C.byref(st)) == mg.MG_ERR_ARG
