@@ -1,0 +1,328 @@
+// LDS-tiled kernels of the adjoint solve (J^T mu = f by FAS-free linear
+// multigrid with the Jacobian coefficients stored per level), for levels with
+// at least 128 cells per side.
+//
+// (J^T mu)_p = lap(mu)_p - G_p with G_p = sum over the 18 neighbours q of p of
+// dK_q/dphi_p mu_q (the diagonal of J^T is exactly -6/h^2: no model term
+// depends on its own cell).  With the coefficient arrays of mg_adjoint.h:
+//   faces (colour 1-c): cf0(p-x) mu(p-x) + cf1(p+x) mu(p+x) + same for y
+//                       (cf2, cf3) and z (cf4, cf5),
+//   edges (colour c):   cf6 over the xy corners with signs (+ + at p-x-y and
+//                       p+x+y, - at p-x+y and p+x-y), cf7 (xz), cf8 (yz).
+//
+// A block owns a tile of 64 packed columns x 8 rows and marches through a
+// z-chunk, as the forward tiled kernels do, but holds ONE staged plane in
+// LDS at a time: mu of the face colour (for the Laplacian) and the products
+// coefficient x mu that the cells of the target colour read (face products
+// of the face colour, edge products of the target colour).  A plane k'
+// contributes to the target cells of planes k'-1 (their +z terms), k' (the
+// in-plane terms) and k'+1 (their -z terms); a thread keeps these partial
+// sums for its own column in registers, so a cell is complete once the plane
+// above it has been staged.  The z-face products of the thread's own column
+// come from direct loads.  32 KB of LDS (nDGP, Poisson), 42 KB (Kmouflage,
+// whose x+/x- face coefficients differ).
+//
+// One kernel, three modes, one colour c per launch:
+//   PASS   mu_c <- (faces - h^2 (G + f_c + fs)) / 6 into a fresh array;
+//          finest level: block sums of the new values (the colour's sum).
+//   RESID  r = (faces - 6 mu)/h^2 - G - f at colour c, and its restriction:
+//          the colour-0 launch writes the raw sums of its 4 children per
+//          coarse cell, the colour-1 launch adds its 4 and scales by 1/8
+//          (R mu and R r); finest level: block sums of r and r^2.
+//   CSRC   coarse FAS source S = (faces - 6 Ru)/h^2 - G(Ru) - Rd written over
+//          Rd, and u = Ru, at colour c (both launches: the whole level).
+#pragma once
+#include "mg_tiled.h"
+
+namespace mgk {
+
+enum { ADJ_PASS = 0, ADJ_RESID = 1, ADJ_CSRC = 2 };
+
+struct AdjLevel {
+    const double *u0, *u1;       // mu (CSRC: R mu of the finer level)
+    const double *c[9][2];       // coefficient arrays (minus faces alias plus for nDGP/Poisson)
+    const double *f0, *f1;       // right-hand side, never null (CSRC: R r, overwritten by S)
+    int n, logn, lognh;
+    double h2;
+};
+
+// Staging geometry of one FP64 plane (tile plus halo, 66 x 10 values) as in
+// Stage2<double>: 320 16-byte vectors and 20 halo values over 256 threads.
+struct SGeom {
+    unsigned g0, g1;   // byte offsets inside a plane
+    int l0, l1;        // value offsets inside a plane view
+    __device__ __forceinline__ void init(int tid, int j0, int m0, int logn, int lognh) {
+        const unsigned jm = (1u << logn) - 1, mm = (1u << lognh) - 1;
+        {
+            const int r = tid >> 5, i = tid & 31;
+            g0 = ((((unsigned)(j0 - 1 + r) & jm) << lognh) + (unsigned)(m0 + 2 * i)) * 8u;
+            l0 = r * TXH + 1 + 2 * i;
+        }
+        if (tid < 64) {
+            const int r = 8 + (tid >> 5), i = tid & 31;
+            g1 = ((((unsigned)(j0 - 1 + r) & jm) << lognh) + (unsigned)(m0 + 2 * i)) * 8u;
+            l1 = r * TXH + 1 + 2 * i;
+        } else {
+            const int h = tid < 64 + 2 * TYH ? tid - 64 : 0, r = h >> 1, side = h & 1;
+            const unsigned m = (unsigned)(side ? m0 + TX : m0 - 1) & mm;
+            g1 = ((((unsigned)(j0 - 1 + r) & jm) << lognh) + m) * 8u;
+            l1 = r * TXH + (side ? TXH - 1 : 0);
+        }
+    }
+};
+
+// One staged plane of one array in registers: a0 and a1 hold the thread's
+// vectors; threads 64..83 keep their halo value in a1.x (one register pair
+// for both uses, so the compiler keeps the struct in registers).
+struct SReg {
+    double2 a0, a1;
+    __device__ __forceinline__ void load(const double *A, size_t pl, const SGeom &g, int tid) {
+        const char *a = reinterpret_cast<const char *>(A) + pl;
+        a0 = *reinterpret_cast<const double2 *>(a + g.g0);
+        if (tid < 64)
+            a1 = *reinterpret_cast<const double2 *>(a + g.g1);
+        else if (tid < 64 + 2 * TYH)
+            a1.x = *reinterpret_cast<const double *>(a + g.g1);
+    }
+    __device__ __forceinline__ void store(double *s, const SGeom &g, int tid) const {
+        *reinterpret_cast<double2 *>(s + g.l0) = a0;
+        if (tid < 64)
+            *reinterpret_cast<double2 *>(s + g.l1) = a1;
+        else if (tid < 64 + 2 * TYH)
+            s[g.l1] = a1.x;
+    }
+    // s = this * y (element-wise)
+    __device__ __forceinline__ void store_prod(double *s, const SReg &y, const SGeom &g,
+                                               int tid) const {
+        *reinterpret_cast<double2 *>(s + g.l0) = make_double2(a0.x * y.a0.x, a0.y * y.a0.y);
+        if (tid < 64)
+            *reinterpret_cast<double2 *>(s + g.l1) = make_double2(a1.x * y.a1.x, a1.y * y.a1.y);
+        else if (tid < 64 + 2 * TYH)
+            s[g.l1] = a1.x * y.a1.x;
+    }
+};
+
+// SYM: the x+ and x- (y, z) face coefficients are one array (nDGP, Poisson);
+// COEF: the model has a non-Laplacian term (not Poisson).  REDUCE: block sums
+// into partials[2 blk ..] (PASS: the new values; RESID: r and r^2).
+template <bool SYM, bool COEF, int MODE, bool REDUCE>
+__global__ __launch_bounds__(TPB) void k_adj_tiled(AdjLevel L, int c, double *out, double *out2,
+                                                   const double *fptr,
+                                                   double fscale, double *ru0, double *ru1,
+                                                   double *rd0, double *rd1, double *partials,
+                                                   TileGeom G) {
+    constexpr int NF = SYM ? 2 : 4;   // staged in-plane face product arrays
+    __shared__ __align__(16) double sM[TSLOT];
+    __shared__ __align__(16) double sF[COEF ? NF : 1][TSLOT];
+    __shared__ __align__(16) double sE[COEF ? 3 : 1][TSLOT];
+    __shared__ double sX[MODE == ADJ_RESID ? 4 : 1][MODE == ADJ_RESID ? TPB : 1];
+    const size_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int bx = (int)(blk % G.ntx);
+    const int by = (int)((blk / G.ntx) % G.nty);
+    const int bz = (int)(blk / ((size_t)G.ntx * G.nty));
+    const int m0 = bx * TX, j0 = by * TY, k0 = bz * G.kz, k1 = k0 + G.kz;
+    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+    const int o = c ^ 1;
+    const double *Mo = o ? L.u1 : L.u0;   // face colour
+    const double *Mc = c ? L.u1 : L.u0;   // target colour
+    const double *F = c ? L.f1 : L.f0;
+    const double fs = fptr ? fscale * (*fptr) : 0.0;
+    const double inv_h2 = 1.0 / L.h2;
+
+    SGeom g;
+    g.init(tid, j0, m0, L.logn, L.lognh);
+    unsigned coff[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) coff[h] = cell_off<double>(j0 + ty + 4 * h, m0 + tx, L.lognh);
+
+    // staged raw values of the next plane
+    SReg rMo, rFx, rFy, rFx2, rFy2, rMc, rE6, rE7, rE8;
+    auto fetch = [&](int k) {
+        const size_t pl = plane_off<double>(k, L.logn, L.lognh);
+        rMo.load(Mo, pl, g, tid);
+        if constexpr (COEF) {
+            rFx.load(L.c[0][o], pl, g, tid);
+            rFy.load(L.c[2][o], pl, g, tid);
+            if constexpr (!SYM) {
+                rFx2.load(L.c[1][o], pl, g, tid);
+                rFy2.load(L.c[3][o], pl, g, tid);
+            }
+            rMc.load(Mc, pl, g, tid);
+            rE6.load(L.c[6][c], pl, g, tid);
+            rE7.load(L.c[7][c], pl, g, tid);
+            rE8.load(L.c[8][c], pl, g, tid);
+        }
+    };
+    auto store = [&]() {
+        rMo.store(sM + 1, g, tid);
+        if constexpr (COEF) {
+            rFx.store_prod(sF[0] + 1, rMo, g, tid);
+            rFy.store_prod(sF[1] + 1, rMo, g, tid);
+            if constexpr (!SYM) {
+                rFx2.store_prod(sF[NF - 2] + 1, rMo, g, tid);
+                rFy2.store_prod(sF[NF - 1] + 1, rMo, g, tid);
+            }
+            rE6.store_prod(sE[0] + 1, rMc, g, tid);
+            rE7.store_prod(sE[COEF ? 1 : 0] + 1, rMc, g, tid);
+            rE8.store_prod(sE[COEF ? 2 : 0] + 1, rMc, g, tid);
+        }
+    };
+    // own-column values one plane ahead: the z-face coefficients (x+ ... z-
+    // order: 4 = z+, 5 = z-) of the face-colour cell, and f (and mu) of the
+    // target cell
+    double z4n[2] = {0.0, 0.0}, z5n[2] = {0.0, 0.0}, fn[2] = {0.0, 0.0}, un[2] = {0.0, 0.0};
+    auto fetch_cells = [&](int k) {
+        const size_t pl = plane_off<double>(k, L.logn, L.lognh);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if constexpr (COEF) {
+                z4n[h] = ld(L.c[4][o], pl, coff[h]);
+                z5n[h] = SYM ? z4n[h] : ld(L.c[5][o], pl, coff[h]);
+            }
+            // (also at the two planes outside the chunk, where they are unused:
+            // plane_off wraps, so the loads stay inside the level)
+            fn[h] = ld_once(F, pl, coff[h]);
+            if constexpr (MODE != ADJ_PASS) un[h] = ld_once(Mc, pl, coff[h]);
+        }
+    };
+
+    // partial sums (Laplacian neighbours, G) of the target cells in the
+    // thread's column: pF/pG at plane kp - 1 (completed by plane kp), cF/cG at
+    // plane kp (its -z terms so far)
+    double pF[2] = {0.0, 0.0}, pG[2] = {0.0, 0.0}, cF[2] = {0.0, 0.0}, cG[2] = {0.0, 0.0};
+    double fc[2] = {0.0, 0.0}, uc[2] = {0.0, 0.0};   // f, mu of the cells at plane kp
+    double fp[2] = {0.0, 0.0}, up[2] = {0.0, 0.0};   // ... at plane kp - 1
+    double bs1 = 0.0, bs2 = 0.0;                     // block sums
+    double rr[2] = {0.0, 0.0}, rm_[2] = {0.0, 0.0};  // restriction sums over a plane pair
+    int pair_K = -1;                                 // pair waiting for its combine
+
+    // combine a completed plane pair with the sibling row (ty ^ 1) and write
+    // the coarse cells (even ty): rows j0 + ty + 4h and j0 + ty + 1 + 4h form
+    // coarse row (j0 + ty + 4h) / 2
+    auto pair_combine = [&](int K) {
+        if (ty & 1) return;
+        const int lnc = L.logn - 1, I = m0 + tx;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const double sr = sX[2 * h][tid] + sX[2 * h][tid + 64];
+            const double su = sX[2 * h + 1][tid] + sX[2 * h + 1][tid + 64];
+            const int J = (j0 + ty + 4 * h) >> 1;
+            const size_t cidx =
+                ((size_t)K << (2 * lnc - 1)) + ((size_t)J << (lnc - 1)) + (size_t)(I >> 1);
+            const bool odd = (I + J + K) & 1;
+            double *pr = odd ? rd1 : rd0, *pu = odd ? ru1 : ru0;
+            if (c == 0) {   // raw sums of the 4 colour-0 children
+                pr[cidx] = sr;
+                pu[cidx] = su;
+            } else {        // add the 4 colour-1 children: the 8-cell mean
+                pr[cidx] = 0.125 * (pr[cidx] + sr);
+                pu[cidx] = 0.125 * (pu[cidx] + su);
+            }
+        }
+    };
+
+    fetch(k0 - 1);
+    fetch_cells(k0 - 1);
+    for (int kp = k0 - 1; kp <= k1; ++kp) {
+        store();
+        const double z4[2] = {z4n[0], z4n[1]}, z5[2] = {z5n[0], z5n[1]};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            fp[h] = fc[h];
+            up[h] = uc[h];
+            fc[h] = fn[h];
+            uc[h] = un[h];
+        }
+        __syncthreads();
+        if (kp + 1 <= k1) {
+            fetch(kp + 1);
+            fetch_cells(kp + 1);
+        }
+        if constexpr (MODE == ADJ_RESID) {
+            if (pair_K >= 0) {
+                pair_combine(pair_K);
+                pair_K = -1;
+            }
+        }
+        const bool mid = kp >= k0 && kp < k1;
+        const bool fin = kp - 1 >= k0;
+        const double *Mv = sM + 1;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int row = ty + 4 * h, j = j0 + row;
+            const int r = row + 1, q = tx + 1;
+            const int ro = r * TXH, rp = (r + 1) * TXH, rm = (r - 1) * TXH;
+            // x parity of the target cell of row j: p at plane kp, p ^ 1 at
+            // planes kp - 1 and kp + 1
+            const int p = (j + kp + c) & 1, pz = p ^ 1;
+            // this plane's face-colour value under/over the target cells of
+            // planes kp + 1 / kp - 1, and their xz, yz edge terms
+            const double mz = Mv[ro + q];
+            double gup = 0.0, gdn = 0.0;
+            if constexpr (COEF) {
+                const double *Exz = sE[1] + 1, *Eyz = sE[2] + 1;
+                const double exm = Exz[ro + q + pz - 1], exq = Exz[ro + q + pz];
+                const double eym = Eyz[rm + q], eyq = Eyz[rp + q];
+                gup = z4[h] * mz + ((exm - exq) + (eym - eyq));   // to plane kp + 1
+                gdn = z5[h] * mz + ((exq - exm) + (eyq - eym));   // to plane kp - 1
+            }
+            if (fin) {   // the cell of plane kp - 1 is complete
+                const double Ft = pF[h] + mz, Gt = pG[h] + gdn;
+                const size_t pl = plane_off<double>(kp - 1, L.logn, L.lognh);
+                if constexpr (MODE == ADJ_PASS) {
+                    const double nv = (Ft - L.h2 * (Gt + fp[h] + fs)) * (1.0 / 6.0);
+                    __builtin_nontemporal_store(nv, ptr(out, pl, coff[h]));
+                    if (REDUCE) bs1 += nv;
+                } else if constexpr (MODE == ADJ_RESID) {
+                    const double d = (Ft - 6.0 * up[h]) * inv_h2 - Gt - fp[h];
+                    if (REDUCE) {
+                        bs1 += d;
+                        bs2 += d * d;
+                    }
+                    rr[h] += d;
+                    rm_[h] += up[h];
+                } else {
+                    *ptr(out, pl, coff[h]) = (Ft - 6.0 * up[h]) * inv_h2 - Gt - fp[h];
+                    *ptr(out2, pl, coff[h]) = up[h];
+                }
+            }
+            double fin_f = 0.0, fin_g = 0.0;   // in-plane terms of the cell of plane kp
+            if (mid) {
+                const int qp = q + p, qm = q + p - 1;
+                fin_f = (Mv[ro + qp] + Mv[ro + qm]) + (Mv[rp + q] + Mv[rm + q]);
+                if constexpr (COEF) {
+                    const double *Px = sF[0] + 1, *Py = sF[1] + 1;
+                    const double *Px2 = sF[NF - 2] + 1, *Py2 = sF[NF - 1] + 1;   // x-, y- faces
+                    const double *Exy = sE[0] + 1;
+                    // p - x carries its x+ coefficient, p + x its x- one (y alike)
+                    fin_g = (Px[ro + qm] + Px2[ro + qp]) + (Py[rm + q] + Py2[rp + q]);
+                    fin_g += (Exy[rm + qm] + Exy[rp + qp]) - (Exy[rp + qm] + Exy[rm + qp]);
+                }
+            }
+            pF[h] = cF[h] + fin_f;
+            pG[h] = cG[h] + fin_g;
+            cF[h] = mz;
+            cG[h] = gup;
+        }
+        if constexpr (MODE == ADJ_RESID) {
+            // plane kp - 1 closed a plane pair: publish the row sums
+            if (fin && ((kp - 1) & 1)) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    sX[2 * h][tid] = rr[h];
+                    sX[2 * h + 1][tid] = rm_[h];
+                    rr[h] = 0.0;
+                    rm_[h] = 0.0;
+                }
+                pair_K = (kp - 1) >> 1;
+            }
+        }
+        __syncthreads();
+    }
+    if constexpr (MODE == ADJ_RESID) {
+        if (pair_K >= 0) pair_combine(pair_K);
+    }
+    if (REDUCE) block_sum2(bs1, bs2, partials, blk);
+}
+
+}  // namespace mgk

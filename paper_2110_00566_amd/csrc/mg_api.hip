@@ -20,8 +20,8 @@
 #include <vector>
 
 #include "../../include/mgglam.h"
+#include "mg_adj_tiled.h"
 #include "mg_adjoint.h"
-#include "mg_tiled.h"
 
 using namespace mgk;
 
@@ -99,6 +99,7 @@ struct Ctx {
     int nu1 = 1, nu2 = 1, nuc = 32;
     int cycle = 0;   // 0 V, 1 F, 2 W
     double kappa = 6.0;
+    int adj_model = MODEL_DGP;   // model of the adjoint's Jacobian (tiled kernel dispatch)
     bool profile = false;
     std::vector<hipEvent_t> ev;
     int ev_used = 0;
@@ -329,6 +330,46 @@ void launch_prolong(R *f0, R *f1, int logn, const R *uc0, const R *uc1, const R 
     }
 }
 
+AdjLevel adj_level(const HLevel<double> &H, const double *u0, const double *u1) {
+    AdjLevel A;
+    A.u0 = u0;
+    A.u1 = u1;
+    for (int q = 0; q < 9; ++q)
+        for (int c = 0; c < 2; ++c) A.c[q][c] = H.cf[q][c];
+    A.f0 = H.f[0];
+    A.f1 = H.f[1];
+    A.n = H.n;
+    A.logn = H.logn;
+    A.lognh = H.logn - 1;
+    A.h2 = H.h * H.h;
+    return A;
+}
+
+// One colour launch of the tiled adjoint kernel (levels >= 128^3); returns
+// the number of blocks (block sums land in partials[0 .. 2 nb)).
+template <int MODE, bool REDUCE>
+unsigned launch_adj_tiled(int model, const AdjLevel &A, int c, double *out, double *out2,
+                          const double *fptr, double fscale, double *ru0, double *ru1,
+                          double *rd0, double *rd1, double *partials, hipStream_t st) {
+    const TileGeom G = tile_geom(A.n, A.n);
+    const unsigned nb = tile_blocks(G, A.n);
+    switch (model) {
+        case MODEL_KMO:
+            k_adj_tiled<false, true, MODE, REDUCE><<<nb, TPB, 0, st>>>(
+                A, c, out, out2, fptr, fscale, ru0, ru1, rd0, rd1, partials, G);
+            break;
+        case MODEL_POISSON:
+            k_adj_tiled<true, false, MODE, REDUCE><<<nb, TPB, 0, st>>>(
+                A, c, out, out2, fptr, fscale, ru0, ru1, rd0, rd1, partials, G);
+            break;
+        default:
+            k_adj_tiled<true, true, MODE, REDUCE><<<nb, TPB, 0, st>>>(
+                A, c, out, out2, fptr, fscale, ru0, ru1, rd0, rd1, partials, G);
+            break;
+    }
+    return nb;
+}
+
 // ---------------------------------------------------------------- model set-up
 
 bool setup_dgp(const mg_dgp_params *p, Mod &M) {
@@ -407,13 +448,19 @@ struct Solver {
         k_finalize<<<1, 1024, 0, C.st>>>(C.partials, nb, (double)(2 * half), C.scal, 1, 0.0);
     }
 
+    // The adjoint on levels >= 128^3 runs the tiled adjoint kernels; on a
+    // tiled finest level the mean of mu that the bordered equation needs is
+    // kept from the colour sums that every kernel writing mu reports.
+    static constexpr bool ADJ = OP == OP_ADJ;
+    bool adj_tiled(int l) const { return ADJ && tiled_level(Hh.lv[l].n); }
+
     void pass(int l, int c) {
         HLevel<R> &H = Hh.lv[l];
         const double *fptr = nullptr;
         double fs = 0.0;
         if (l == 0) {
             if (OP == OP_ADJ) {
-                mean_of(H.u[0], H.u[1], H.half);
+                if (!adj_tiled(0)) mean_of(H.u[0], H.u[1], H.half);
                 fptr = C.scal + S_MEAN;
                 fs = C.kappa;
             } else {
@@ -423,6 +470,29 @@ struct Solver {
         }
         const bool timed = C.profile && l == 0 && C.ev_used + 2 <= (int)C.ev.size();
         if (timed) (void)hipEventRecord(C.ev[C.ev_used], C.st);
+        if constexpr (ADJ) {
+            if (adj_tiled(l)) {
+                const AdjLevel A = adj_level(H, H.u[0], H.u[1]);
+                double *sp = reinterpret_cast<double *>(H.spare);
+                if (l == 0) {
+                    const unsigned nb = launch_adj_tiled<ADJ_PASS, true>(
+                        C.adj_model, A, c, sp, nullptr, fptr, fs, nullptr, nullptr, nullptr,
+                        nullptr, C.partials, C.st);
+                    k_finalize<<<1, 1024, 0, C.st>>>(C.partials, nb, (double)H.n * H.n * H.n,
+                                                     C.scal, 3, 0.0, c);
+                } else {
+                    launch_adj_tiled<ADJ_PASS, false>(C.adj_model, A, c, sp, nullptr, fptr, fs,
+                                                      nullptr, nullptr, nullptr, nullptr, nullptr,
+                                                      C.st);
+                }
+                if (timed) {
+                    (void)hipEventRecord(C.ev[C.ev_used + 1], C.st);
+                    C.ev_used += 2;
+                }
+                std::swap(H.u[c], H.spare);
+                return;
+            }
+        }
         launch_pass<OP, R>(C.M, view(H, l > 0 || OP == OP_ADJ), coefs(H), c, H.spare, fptr, fs,
                            C.clamp, C.st);
         if (timed) {
@@ -442,6 +512,31 @@ struct Solver {
         HLevel<R> &H = Hh.lv[l], &Hc = Hh.lv[l + 1];
         const bool with_f = l > 0 || OP == OP_ADJ;
         const double *fptr = (l == 0 && OP != OP_ADJ) ? C.scal + S_MU : nullptr;
+        if constexpr (ADJ) {
+            if (adj_tiled(l)) {
+                // colour 0 writes the raw sums of its children, colour 1
+                // completes the 8-cell means; the finest level reduces r
+                const AdjLevel A = adj_level(H, H.u[0], H.u[1]);
+                double *q[4] = {(double *)Hc.ru[0], (double *)Hc.ru[1], (double *)Hc.f[0],
+                                (double *)Hc.f[1]};
+                if (l == 0) {
+                    const unsigned nb = launch_adj_tiled<ADJ_RESID, true>(
+                        C.adj_model, A, 0, nullptr, nullptr, nullptr, 0.0, q[0], q[1], q[2],
+                        q[3], C.partials, C.st);
+                    launch_adj_tiled<ADJ_RESID, true>(C.adj_model, A, 1, nullptr, nullptr,
+                                                      nullptr, 0.0, q[0], q[1], q[2], q[3],
+                                                      C.partials + 2 * nb, C.st);
+                    k_finalize<<<1, 1024, 0, C.st>>>(C.partials, 2 * nb,
+                                                     (double)H.n * H.n * H.n, C.scal, 2, C.kappa);
+                } else {
+                    for (int c = 0; c < 2; ++c)
+                        launch_adj_tiled<ADJ_RESID, false>(C.adj_model, A, c, nullptr, nullptr,
+                                                           nullptr, 0.0, q[0], q[1], q[2], q[3],
+                                                           nullptr, C.st);
+                }
+                return;
+            }
+        }
         if (l == 0) {
             if (OP == OP_ADJ) mean_of(H.u[0], H.u[1], H.half);
             const unsigned nb = launch_resid_restrict<OP, true, R>(
@@ -462,6 +557,16 @@ struct Solver {
         L.u0 = Hc.ru[0];
         L.u1 = Hc.ru[1];
         const double *shift = (lc == 1 && OP != OP_ADJ) ? C.scal + S_SHIFT : nullptr;
+        if constexpr (ADJ) {
+            if (adj_tiled(lc)) {
+                const AdjLevel A = adj_level(Hc, Hc.ru[0], Hc.ru[1]);
+                for (int c = 0; c < 2; ++c)
+                    launch_adj_tiled<ADJ_CSRC, false>(C.adj_model, A, c, (double *)Hc.f[c],
+                                                      (double *)Hc.u[c], nullptr, 0.0, nullptr,
+                                                      nullptr, nullptr, nullptr, nullptr, C.st);
+                return;
+            }
+        }
         if (tiled_op(OP) && tiled_level(Hc.n)) {
             const TileGeom G = tile_geom(Hc.n, Hc.n);
             k_coarse_source_tiled<fwd_op(OP), R><<<tile_blocks(G, Hc.n), TPB, 0, C.st>>>(
@@ -474,6 +579,17 @@ struct Solver {
 
     void prolong(int l) {
         HLevel<R> &H = Hh.lv[l], &Hc = Hh.lv[l + 1];
+        if (l == 0 && adj_tiled(0)) {
+            // the colour sums of the corrected finest field
+            const TileGeom G = tile_geom(H.n, H.n / 2);
+            const unsigned nb = tile_blocks(G, H.n / 2);
+            k_prolong_tiled<R, true><<<nb, TPB, 0, C.st>>>(H.u[0], H.u[1], H.logn, Hc.u[0],
+                                                          Hc.u[1], Hc.ru[0], Hc.ru[1], G,
+                                                          C.partials);
+            k_finalize<<<1, 1024, 0, C.st>>>(C.partials, nb, (double)H.n * H.n * H.n, C.scal, 4,
+                                             0.0);
+            return;
+        }
         launch_prolong<R>(H.u[0], H.u[1], H.logn, Hc.u[0], Hc.u[1], Hc.ru[0], Hc.ru[1], C.st);
     }
 
@@ -901,6 +1017,7 @@ mg_status adjoint_solve(const mg_opts *o, const Mod &M, const double *delta, con
     C.nu2 = o->nu_post;
     C.nuc = o->nu_coarse;
     C.kappa = 6.0;   // 6/h^2 on the finest level: removes the mean of mu in one pass
+    C.adj_model = MODEL;
     Profiler prof(C, false, 0);
     arm_early_read(C);
     reset_scalars(C);
@@ -916,6 +1033,15 @@ mg_status adjoint_solve(const mg_opts *o, const Mod &M, const double *delta, con
                                                                   C.scal + S_MEAN);
     k_pack<double, double><<<nblocks(2 * F.half), TPB, 0, C.st>>>(mu, F.logn, F.u[0], F.u[1],
                                                                   nullptr);
+    if (tiled_level(F.n)) {
+        // colour sums of the starting field (later kept by the kernels that write mu)
+        const unsigned nb = (unsigned)std::min<size_t>(nblocks(F.half), 2048);
+        for (int c = 0; c < 2; ++c) {
+            k_sum<double><<<nb, TPB, 0, C.st>>>(F.u[c], nullptr, F.half, C.partials);
+            k_finalize<<<1, 1024, 0, C.st>>>(C.partials, nb, (double)F.n * F.n * F.n, C.scal, 3,
+                                             0.0, c);
+        }
+    }
     PhaseResult pr;
     mg_status rc = S.run(o->tol, o->max_cycles, 0.0, st, 0, pr);
     if (rc != MG_OK) return rc;

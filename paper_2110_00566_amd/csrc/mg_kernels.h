@@ -17,6 +17,8 @@ enum {
     S_SHIFT = 1,   // mean change of the finest residual since mu was last set
     S_EPS2 = 2,    // squared RMS of the last reduced residual
     S_MEAN = 3,    // mean of the last summed field
+    S_CSUM0 = 4,   // adjoint, tiled finest level: sum of mu over colour 0
+    S_CSUM1 = 5,   // ... over colour 1 (each refreshed by the last kernel that wrote the colour)
     S_NSCAL = 16
 };
 
@@ -373,10 +375,13 @@ __global__ __launch_bounds__(TPB) void k_sum(const R *a0, const R *a1, size_t nh
 // Finalise a reduction.  mode 0: residual of the finest level with lagged mu
 // (mu += mean, shift = mean, eps2 = variance); mode 1: plain mean into
 // S_MEAN; mode 2: adjoint residual r = d - kappa*mean(mu) with mean(mu) in
-// S_MEAN (shift = 0, eps2 = mean r^2).  Summation order is fixed.
+// S_MEAN (shift = 0, eps2 = mean r^2); mode 3: the sum of one colour (colour)
+// of the adjoint field into S_CSUM0 + colour, and S_MEAN = the mean of both
+// colours' sums; mode 4: both colours' sums at once (first and second
+// components).  Summation order is fixed.
 __global__ __launch_bounds__(1024) void k_finalize(const double *partials, size_t nblocks,
                                                    double ncells, double *scal, int mode,
-                                                   double kappa) {
+                                                   double kappa, int colour = 0) {
     __shared__ double sa[16], sb[16];
     double a = 0.0, b = 0.0;
     for (size_t q = threadIdx.x; q < nblocks; q += 1024) {
@@ -406,6 +411,13 @@ __global__ __launch_bounds__(1024) void k_finalize(const double *partials, size_
             scal[S_EPS2] = v < 0.0 ? 0.0 : v;   // keeps NaN
         } else if (mode == 1) {
             scal[S_MEAN] = mean;
+        } else if (mode == 3) {
+            scal[S_CSUM0 + colour] = x;
+            scal[S_MEAN] = (scal[S_CSUM0] + scal[S_CSUM1]) / ncells;
+        } else if (mode == 4) {
+            scal[S_CSUM0] = x;
+            scal[S_CSUM1] = y;
+            scal[S_MEAN] = (x + y) / ncells;
         } else {
             const double km = kappa * scal[S_MEAN];
             scal[S_SHIFT] = 0.0;

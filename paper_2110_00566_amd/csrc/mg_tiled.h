@@ -419,11 +419,12 @@ __global__ __launch_bounds__(TPB) void k_resid_restrict_tiled(Mod M, LvlT<R> L, 
 }
 
 // u_fine += P(uc - rc) (see k_prolong) with the coarse difference staged in
-// LDS: 66 coarse columns x 6 coarse rows, ring of 3 coarse planes.
-template <typename R>
+// LDS: 66 coarse columns x 6 coarse rows, ring of 3 coarse planes.  REDUCE:
+// block sums of the corrected colour-0 and colour-1 values into partials.
+template <typename R, bool REDUCE = false>
 __global__ __launch_bounds__(TPB) void k_prolong_tiled(R *f0, R *f1, int logn, const R *uc0,
                                                        const R *uc1, const R *rc0, const R *rc1,
-                                                       TileGeom G) {
+                                                       TileGeom G, double *partials = nullptr) {
     constexpr int CR = TY / 2 + 2;   // coarse rows staged
     constexpr int CPL = TXH * CR;    // 396 values per coarse plane
     __shared__ double sE[3][CPL];
@@ -464,6 +465,7 @@ __global__ __launch_bounds__(TPB) void k_prolong_tiled(R *f0, R *f1, int logn, c
     fetch(K0);
     store(1);
     fetch(K0 + 1);
+    double bsum[2] = {0.0, 0.0};
     for (int K = K0; K < K0 + G.kz; ++K) {
         store((K - K0 + 2) % 3);
         __syncthreads();
@@ -487,10 +489,13 @@ __global__ __launch_bounds__(TPB) void k_prolong_tiled(R *f0, R *f1, int logn, c
             }
             const size_t idx = prow(j, k, logn, lognh) + m;
             R *f = c ? f1 : f0;
-            f[idx] = (R)((double)f[idx] + acc * (1.0 / 64.0));
+            const R nv = (R)((double)f[idx] + acc * (1.0 / 64.0));
+            f[idx] = nv;
+            if (REDUCE) bsum[c] += (double)nv;
         }
         __syncthreads();
     }
+    if (REDUCE) block_sum2(bsum[0], bsum[1], partials, blk);
 }
 
 // Prolongation of the coarse correction fused with the first post-smoothing

@@ -404,6 +404,34 @@ def test_adjoint_parity(name, n):
     assert rel(c(grad2), r2.grad) <= 1e-9
 
 
+@pytest.mark.parametrize("name,n,converge", [("dgp", 128, True), ("kmo3", 128, True),
+                                             ("poisson", 128, False), ("dgp", 256, False),
+                                             ("kmo2", 256, False)])
+def test_tiled_adjoint_parity(name, n, converge):
+    # levels >= 128^3 run the LDS-tiled adjoint kernels (pass, residual +
+    # restriction, coarse source) and keep the mean of mu from colour sums;
+    # fixed cycles and (128^3) the converged solve against the oracle adjoint
+    gp, om = models(n)[name]
+    delta = inputs.lognormal_delta(n, 6) * (1.0 if "kmo" not in name else 2.0)
+    w = inputs.gaussian_weights(n, 7)
+    print("tiled adjoint %s n=%d" % (name, n), flush=True)
+    phi = oracle.solve(om, delta, tol=1e-12, max_cycles=60).phi
+    model = {"dgp": 0, "kmo3": 1, "kmo2": 1, "poisson": 2}[name]
+    r = oracle.adjoint(om, delta, phi, w, tol=0.0, max_cycles=3)
+    grad, mu, st = mg.solve_adjoint(model, gp, g(delta), g(phi), g(w), tol=0.0, max_cycles=3)
+    assert st["cycles"] == 3
+    assert rel(c(mu), r.mu) <= 1e-10
+    assert rel(c(grad), r.grad) <= 1e-10
+    np.testing.assert_allclose(st["eps_hist"], r.hist[:3], rtol=1e-9)
+    if converge:
+        r2 = oracle.adjoint(om, delta, phi, w, tol=1e-10, max_cycles=60)
+        grad2, mu2, st2 = mg.solve_adjoint(model, gp, g(delta), g(phi), g(w), tol=1e-10,
+                                           max_cycles=60)
+        assert st2["status"] == 0 and st2["cycles"] == r2.cycles
+        assert rel(c(grad2), r2.grad) <= 1e-9
+        assert abs(float(mu2.mean())) <= 1e-12 * float(mu2.abs().max())
+
+
 def test_autograd_matches_finite_differences():
     n = 32
     delta = g(inputs.lognormal_delta(n, 1)).requires_grad_(True)
