@@ -46,76 +46,147 @@ struct AdjLevel {
     double h2;
 };
 
-// Staging geometry of one FP64 plane (tile plus halo, 66 x 10 values) as in
-// Stage2<double>: 320 16-byte vectors and 20 halo values over 256 threads.
+// Staging geometry of one FP64 plane (tile plus halo, 66 x 10 values): 320
+// 16-byte vectors and 20 halo values.  NT = 256 threads: every thread takes
+// one vector, threads 0..63 a second one and threads 64..83 a halo value;
+// NT = 512: threads 0..319 one vector, 320..339 a halo value.
+template <int NT>
 struct SGeom {
+    static constexpr int NV = TYH * (TX / 2);   // 320 vectors
+    static_assert(NT == 256 || NT == 512, "staging split");
+    static constexpr int V2 = NT == 256 ? NV - NT : 0;   // threads with a second vector
+    static constexpr int H0 = NT == 256 ? V2 : NV;       // first halo thread
     unsigned g0, g1;   // byte offsets inside a plane
     int l0, l1;        // value offsets inside a plane view
     __device__ __forceinline__ void init(int tid, int j0, int m0, int logn, int lognh) {
         const unsigned jm = (1u << logn) - 1, mm = (1u << lognh) - 1;
-        {
-            const int r = tid >> 5, i = tid & 31;
-            g0 = ((((unsigned)(j0 - 1 + r) & jm) << lognh) + (unsigned)(m0 + 2 * i)) * 8u;
-            l0 = r * TXH + 1 + 2 * i;
-        }
-        if (tid < 64) {
-            const int r = 8 + (tid >> 5), i = tid & 31;
-            g1 = ((((unsigned)(j0 - 1 + r) & jm) << lognh) + (unsigned)(m0 + 2 * i)) * 8u;
-            l1 = r * TXH + 1 + 2 * i;
-        } else {
-            const int h = tid < 64 + 2 * TYH ? tid - 64 : 0, r = h >> 1, side = h & 1;
+        auto vec = [&](int v, unsigned &g, int &l) {
+            const int r = v >> 5, i = v & 31;
+            g = ((((unsigned)(j0 - 1 + r) & jm) << lognh) + (unsigned)(m0 + 2 * i)) * 8u;
+            l = r * TXH + 1 + 2 * i;
+        };
+        auto halo = [&](int t, unsigned &g, int &l) {
+            const int h = (t >= H0 && t < H0 + 2 * TYH) ? t - H0 : 0, r = h >> 1, side = h & 1;
             const unsigned m = (unsigned)(side ? m0 + TX : m0 - 1) & mm;
-            g1 = ((((unsigned)(j0 - 1 + r) & jm) << lognh) + m) * 8u;
-            l1 = r * TXH + (side ? TXH - 1 : 0);
+            g = ((((unsigned)(j0 - 1 + r) & jm) << lognh) + m) * 8u;
+            l = r * TXH + (side ? TXH - 1 : 0);
+        };
+        if (NT == 256) {
+            vec(tid, g0, l0);
+            if (tid < V2)
+                vec(NT + tid, g1, l1);
+            else
+                halo(tid, g1, l1);
+        } else {
+            if (tid < NV)
+                vec(tid, g0, l0);
+            else
+                halo(tid, g0, l0);
+            g1 = g0;
+            l1 = l0;
         }
     }
 };
 
-// One staged plane of one array in registers: a0 and a1 hold the thread's
-// vectors; threads 64..83 keep their halo value in a1.x (one register pair
-// for both uses, so the compiler keeps the struct in registers).
+// One staged plane of one array in registers.  NT = 256: a0 and a1 hold the
+// thread's vectors and threads 64..83 keep their halo value in a1.x; NT =
+// 512: a0 (a halo value in a0.x).  One register pair per use keeps the
+// struct in registers.
+template <int NT>
 struct SReg {
+    using G = SGeom<NT>;
     double2 a0, a1;
-    __device__ __forceinline__ void load(const double *A, size_t pl, const SGeom &g, int tid) {
+    __device__ __forceinline__ void load(const double *A, size_t pl, const G &g, int tid) {
         const char *a = reinterpret_cast<const char *>(A) + pl;
-        a0 = *reinterpret_cast<const double2 *>(a + g.g0);
-        if (tid < 64)
-            a1 = *reinterpret_cast<const double2 *>(a + g.g1);
-        else if (tid < 64 + 2 * TYH)
-            a1.x = *reinterpret_cast<const double *>(a + g.g1);
+        if (NT == 256) {
+            a0 = *reinterpret_cast<const double2 *>(a + g.g0);
+            if (tid < G::V2)
+                a1 = *reinterpret_cast<const double2 *>(a + g.g1);
+            else if (tid < G::H0 + 2 * TYH)
+                a1.x = *reinterpret_cast<const double *>(a + g.g1);
+        } else {
+            if (tid < G::NV)
+                a0 = *reinterpret_cast<const double2 *>(a + g.g0);
+            else if (tid < G::H0 + 2 * TYH)
+                a0.x = *reinterpret_cast<const double *>(a + g.g0);
+        }
     }
-    __device__ __forceinline__ void store(double *s, const SGeom &g, int tid) const {
-        *reinterpret_cast<double2 *>(s + g.l0) = a0;
-        if (tid < 64)
-            *reinterpret_cast<double2 *>(s + g.l1) = a1;
-        else if (tid < 64 + 2 * TYH)
-            s[g.l1] = a1.x;
+    __device__ __forceinline__ void store(double *s, const G &g, int tid) const {
+        if (NT == 256) {
+            *reinterpret_cast<double2 *>(s + g.l0) = a0;
+            if (tid < G::V2)
+                *reinterpret_cast<double2 *>(s + g.l1) = a1;
+            else if (tid < G::H0 + 2 * TYH)
+                s[g.l1] = a1.x;
+        } else {
+            if (tid < G::NV)
+                *reinterpret_cast<double2 *>(s + g.l0) = a0;
+            else if (tid < G::H0 + 2 * TYH)
+                s[g.l0] = a0.x;
+        }
     }
     // s = this * y (element-wise)
-    __device__ __forceinline__ void store_prod(double *s, const SReg &y, const SGeom &g,
+    __device__ __forceinline__ void store_prod(double *s, const SReg &y, const G &g,
                                                int tid) const {
-        *reinterpret_cast<double2 *>(s + g.l0) = make_double2(a0.x * y.a0.x, a0.y * y.a0.y);
-        if (tid < 64)
-            *reinterpret_cast<double2 *>(s + g.l1) = make_double2(a1.x * y.a1.x, a1.y * y.a1.y);
-        else if (tid < 64 + 2 * TYH)
-            s[g.l1] = a1.x * y.a1.x;
+        if (NT == 256) {
+            *reinterpret_cast<double2 *>(s + g.l0) = make_double2(a0.x * y.a0.x, a0.y * y.a0.y);
+            if (tid < G::V2)
+                *reinterpret_cast<double2 *>(s + g.l1) =
+                    make_double2(a1.x * y.a1.x, a1.y * y.a1.y);
+            else if (tid < G::H0 + 2 * TYH)
+                s[g.l1] = a1.x * y.a1.x;
+        } else {
+            if (tid < G::NV)
+                *reinterpret_cast<double2 *>(s + g.l0) =
+                    make_double2(a0.x * y.a0.x, a0.y * y.a0.y);
+            else if (tid < G::H0 + 2 * TYH)
+                s[g.l0] = a0.x * y.a0.x;
+        }
     }
 };
+
+// Deterministic block sum of two values over NT threads into
+// partials[2 blk .. 2 blk + 1].
+template <int NT>
+__device__ __forceinline__ void block_sum2_nt(double a, double b, double *partials, size_t blk) {
+    __shared__ double sa[NT / 64], sb[NT / 64];
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_down(a, off, 64);
+        b += __shfl_down(b, off, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sa[w] = a;
+        sb[w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double x = 0.0, y = 0.0;
+        for (int q = 0; q < NT / 64; ++q) {
+            x += sa[q];
+            y += sb[q];
+        }
+        partials[2 * blk] = x;
+        partials[2 * blk + 1] = y;
+    }
+}
 
 // SYM: the x+ and x- (y, z) face coefficients are one array (nDGP, Poisson);
 // COEF: the model has a non-Laplacian term (not Poisson).  REDUCE: block sums
 // into partials[2 blk ..] (PASS: the new values; RESID: r and r^2).
-template <bool SYM, bool COEF, int MODE, bool REDUCE>
-__global__ __launch_bounds__(TPB) void k_adj_tiled(AdjLevel L, int c, double *out, double *out2,
+template <int NT, bool SYM, bool COEF, int MODE, bool REDUCE>
+__global__ __launch_bounds__(NT) void k_adj_tiled(AdjLevel L, int c, double *out, double *out2,
                                                    const double *fptr,
                                                    double fscale, double *ru0, double *ru1,
                                                    double *rd0, double *rd1, double *partials,
                                                    TileGeom G) {
     constexpr int NF = SYM ? 2 : 4;   // staged in-plane face product arrays
+    constexpr int W = NT / 64;        // waves = rows per row group
+    constexpr int RPT = TY / W;       // rows per thread
     __shared__ __align__(16) double sM[TSLOT];
     __shared__ __align__(16) double sF[COEF ? NF : 1][TSLOT];
     __shared__ __align__(16) double sE[COEF ? 3 : 1][TSLOT];
-    __shared__ double sX[MODE == ADJ_RESID ? 4 : 1][MODE == ADJ_RESID ? TPB : 1];
+    __shared__ double sX[MODE == ADJ_RESID ? 2 * RPT : 1][MODE == ADJ_RESID ? NT : 1];
     const size_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int bx = (int)(blk % G.ntx);
     const int by = (int)((blk / G.ntx) % G.nty);
@@ -129,14 +200,14 @@ __global__ __launch_bounds__(TPB) void k_adj_tiled(AdjLevel L, int c, double *ou
     const double fs = fptr ? fscale * (*fptr) : 0.0;
     const double inv_h2 = 1.0 / L.h2;
 
-    SGeom g;
+    SGeom<NT> g;
     g.init(tid, j0, m0, L.logn, L.lognh);
-    unsigned coff[2];
+    unsigned coff[RPT];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) coff[h] = cell_off<double>(j0 + ty + 4 * h, m0 + tx, L.lognh);
+    for (int h = 0; h < RPT; ++h) coff[h] = cell_off<double>(j0 + ty + W * h, m0 + tx, L.lognh);
 
     // staged raw values of the next plane
-    SReg rMo, rFx, rFy, rFx2, rFy2, rMc, rE6, rE7, rE8;
+    SReg<NT> rMo, rFx, rFy, rFx2, rFy2, rMc, rE6, rE7, rE8;
     auto fetch = [&](int k) {
         const size_t pl = plane_off<double>(k, L.logn, L.lognh);
         rMo.load(Mo, pl, g, tid);
@@ -170,11 +241,11 @@ __global__ __launch_bounds__(TPB) void k_adj_tiled(AdjLevel L, int c, double *ou
     // own-column values one plane ahead: the z-face coefficients (x+ ... z-
     // order: 4 = z+, 5 = z-) of the face-colour cell, and f (and mu) of the
     // target cell
-    double z4n[2] = {0.0, 0.0}, z5n[2] = {0.0, 0.0}, fn[2] = {0.0, 0.0}, un[2] = {0.0, 0.0};
+    double z4n[RPT] = {}, z5n[RPT] = {}, fn[RPT] = {}, un[RPT] = {};
     auto fetch_cells = [&](int k) {
         const size_t pl = plane_off<double>(k, L.logn, L.lognh);
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < RPT; ++h) {
             if constexpr (COEF) {
                 z4n[h] = ld(L.c[4][o], pl, coff[h]);
                 z5n[h] = SYM ? z4n[h] : ld(L.c[5][o], pl, coff[h]);
@@ -189,24 +260,24 @@ __global__ __launch_bounds__(TPB) void k_adj_tiled(AdjLevel L, int c, double *ou
     // partial sums (Laplacian neighbours, G) of the target cells in the
     // thread's column: pF/pG at plane kp - 1 (completed by plane kp), cF/cG at
     // plane kp (its -z terms so far)
-    double pF[2] = {0.0, 0.0}, pG[2] = {0.0, 0.0}, cF[2] = {0.0, 0.0}, cG[2] = {0.0, 0.0};
-    double fc[2] = {0.0, 0.0}, uc[2] = {0.0, 0.0};   // f, mu of the cells at plane kp
-    double fp[2] = {0.0, 0.0}, up[2] = {0.0, 0.0};   // ... at plane kp - 1
-    double bs1 = 0.0, bs2 = 0.0;                     // block sums
-    double rr[2] = {0.0, 0.0}, rm_[2] = {0.0, 0.0};  // restriction sums over a plane pair
+    double pF[RPT] = {}, pG[RPT] = {}, cF[RPT] = {}, cG[RPT] = {};
+    double fc[RPT] = {}, uc[RPT] = {};   // f, mu of the cells at plane kp
+    double fp[RPT] = {}, up[RPT] = {};   // ... at plane kp - 1
+    double bs1 = 0.0, bs2 = 0.0;         // block sums
+    double rr[RPT] = {}, rm_[RPT] = {};  // restriction sums over a plane pair
     int pair_K = -1;                                 // pair waiting for its combine
 
     // combine a completed plane pair with the sibling row (ty ^ 1) and write
-    // the coarse cells (even ty): rows j0 + ty + 4h and j0 + ty + 1 + 4h form
-    // coarse row (j0 + ty + 4h) / 2
+    // the coarse cells (even ty): rows j0 + ty + W h and j0 + ty + 1 + W h
+    // form coarse row (j0 + ty + W h) / 2
     auto pair_combine = [&](int K) {
         if (ty & 1) return;
         const int lnc = L.logn - 1, I = m0 + tx;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < RPT; ++h) {
             const double sr = sX[2 * h][tid] + sX[2 * h][tid + 64];
             const double su = sX[2 * h + 1][tid] + sX[2 * h + 1][tid + 64];
-            const int J = (j0 + ty + 4 * h) >> 1;
+            const int J = (j0 + ty + W * h) >> 1;
             const size_t cidx =
                 ((size_t)K << (2 * lnc - 1)) + ((size_t)J << (lnc - 1)) + (size_t)(I >> 1);
             const bool odd = (I + J + K) & 1;
@@ -225,9 +296,11 @@ __global__ __launch_bounds__(TPB) void k_adj_tiled(AdjLevel L, int c, double *ou
     fetch_cells(k0 - 1);
     for (int kp = k0 - 1; kp <= k1; ++kp) {
         store();
-        const double z4[2] = {z4n[0], z4n[1]}, z5[2] = {z5n[0], z5n[1]};
+        double z4[RPT], z5[RPT];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < RPT; ++h) {
+            z4[h] = z4n[h];
+            z5[h] = z5n[h];
             fp[h] = fc[h];
             up[h] = uc[h];
             fc[h] = fn[h];
@@ -248,8 +321,8 @@ __global__ __launch_bounds__(TPB) void k_adj_tiled(AdjLevel L, int c, double *ou
         const bool fin = kp - 1 >= k0;
         const double *Mv = sM + 1;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int row = ty + 4 * h, j = j0 + row;
+        for (int h = 0; h < RPT; ++h) {
+            const int row = ty + W * h, j = j0 + row;
             const int r = row + 1, q = tx + 1;
             const int ro = r * TXH, rp = (r + 1) * TXH, rm = (r - 1) * TXH;
             // x parity of the target cell of row j: p at plane kp, p ^ 1 at
@@ -308,7 +381,7 @@ __global__ __launch_bounds__(TPB) void k_adj_tiled(AdjLevel L, int c, double *ou
             // plane kp - 1 closed a plane pair: publish the row sums
             if (fin && ((kp - 1) & 1)) {
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
+                for (int h = 0; h < RPT; ++h) {
                     sX[2 * h][tid] = rr[h];
                     sX[2 * h + 1][tid] = rm_[h];
                     rr[h] = 0.0;
@@ -322,7 +395,7 @@ __global__ __launch_bounds__(TPB) void k_adj_tiled(AdjLevel L, int c, double *ou
     if constexpr (MODE == ADJ_RESID) {
         if (pair_K >= 0) pair_combine(pair_K);
     }
-    if (REDUCE) block_sum2(bs1, bs2, partials, blk);
+    if (REDUCE) block_sum2_nt<NT>(bs1, bs2, partials, blk);
 }
 
 }  // namespace mgk

@@ -345,6 +345,12 @@ AdjLevel adj_level(const HLevel<double> &H, const double *u0, const double *u1) 
     return A;
 }
 
+// Threads per block of the tiled adjoint kernels (256: two rows per thread).
+#ifndef MG_ADJ_NT
+#define MG_ADJ_NT 512
+#endif
+constexpr int ADJ_NT = MG_ADJ_NT;
+
 // One colour launch of the tiled adjoint kernel (levels >= 128^3); returns
 // the number of blocks (block sums land in partials[0 .. 2 nb)).
 template <int MODE, bool REDUCE>
@@ -355,15 +361,15 @@ unsigned launch_adj_tiled(int model, const AdjLevel &A, int c, double *out, doub
     const unsigned nb = tile_blocks(G, A.n);
     switch (model) {
         case MODEL_KMO:
-            k_adj_tiled<false, true, MODE, REDUCE><<<nb, TPB, 0, st>>>(
+            k_adj_tiled<ADJ_NT, false, true, MODE, REDUCE><<<nb, ADJ_NT, 0, st>>>(
                 A, c, out, out2, fptr, fscale, ru0, ru1, rd0, rd1, partials, G);
             break;
         case MODEL_POISSON:
-            k_adj_tiled<true, false, MODE, REDUCE><<<nb, TPB, 0, st>>>(
+            k_adj_tiled<ADJ_NT, true, false, MODE, REDUCE><<<nb, ADJ_NT, 0, st>>>(
                 A, c, out, out2, fptr, fscale, ru0, ru1, rd0, rd1, partials, G);
             break;
         default:
-            k_adj_tiled<true, true, MODE, REDUCE><<<nb, TPB, 0, st>>>(
+            k_adj_tiled<ADJ_NT, true, true, MODE, REDUCE><<<nb, ADJ_NT, 0, st>>>(
                 A, c, out, out2, fptr, fscale, ru0, ru1, rd0, rd1, partials, G);
             break;
     }
