@@ -46,7 +46,7 @@ typedef enum {
     MG_ERR_WORKSPACE = -5   /* workspace null, smaller than required or not 256-byte aligned */
 } mg_status;
 
-typedef enum { MG_FP64 = 0, MG_MIXED = 1, MG_FP32 = 2 } mg_precision;
+typedef enum { MG_FP64 = 0, MG_MIXED = 1, MG_FP32 = 2, MG_MIXED_DC = 3 } mg_precision;
 typedef enum {
     MG_MODEL_DGP = 0,
     MG_MODEL_KMOUFLAGE = 1,
@@ -83,8 +83,17 @@ typedef struct {
                          the FP32-storage cycles alone (every multigrid array in FP32,
                          as the single-precision arrays of Sec. 3.2.2), stopping at tol,
                          max_cycles or the FP32 floor (a cycle that no longer halves
-                         the residual: MG_NOT_CONVERGED, phi valid).  Forward solves
-                         only; the adjoint and the Newton-GS comparator are FP64 */
+                         the residual: MG_NOT_CONVERGED, phi valid); or MG_MIXED_DC =
+                         the FP32-storage cycles to their floor, then defect correction:
+                         each outer step evaluates the FP64 finest residual r of the
+                         FP64 field, runs one FP32 cycle for a correction e of the
+                         frozen background fl32(phi) -- finest-level sweeps in FP32 on
+                         the correction form of the operator (model-term difference
+                         without cancellation), coarse levels in FP64 -- and
+                         accumulates phi += e in FP64; stats.eps_hist then holds the
+                         FP64 residual before each outer step (nDGP and Poisson,
+                         n >= 128).  Forward solves only; the adjoint and the Newton-GS
+                         comparator are FP64 */
     int cycle;        /* mg_cycle: MG_CYCLE_V (default), MG_CYCLE_F or MG_CYCLE_W;
                          mg_solve_adjoint accepts MG_CYCLE_V only */
     int profile;      /* 1: time every finest-level colour pass with HIP events

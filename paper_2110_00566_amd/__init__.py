@@ -211,7 +211,7 @@ def _check_mesh(t, name, dtype=torch.float64):
     return t
 
 
-MG_FP64, MG_MIXED, MG_FP32 = 0, 1, 2
+MG_FP64, MG_MIXED, MG_FP32, MG_MIXED_DC = 0, 1, 2, 3
 
 
 def workspace(n: int, model: int = MODEL_DGP, adjoint: bool = False, device=None,
@@ -292,7 +292,8 @@ def _solve(fn, par, model, delta, phi0, ws, **kw):
 def solve_dgp(delta, phi0=None, a=1.0, omega_m=OMEGA_M, h0rc=1.0, ws=None, **kw):
     """nDGP field (eq:dgp_eom_code); returns (zero-mean phi, stats).
     Keywords: tol, max_cycles, nu_pre, nu_post, nu_coarse, profile,
-    precision (MG_FP64, MG_MIXED or MG_FP32), cycle (CYCLE_V, CYCLE_F or CYCLE_W)."""
+    precision (MG_FP64, MG_MIXED, MG_FP32 or MG_MIXED_DC), cycle (CYCLE_V, CYCLE_F or
+    CYCLE_W)."""
     return _solve(lib().mg_solve_dgp, dgp_params(a, omega_m, h0rc), MODEL_DGP, delta, phi0, ws, **kw)
 
 

@@ -22,6 +22,7 @@
 #include "../../include/mgglam.h"
 #include "mg_adj_tiled.h"
 #include "mg_adjoint.h"
+#include "mg_dc.h"
 
 using namespace mgk;
 
@@ -79,6 +80,7 @@ struct HLevel {
     R *ru[2] = {nullptr, nullptr};
     double *lin[2] = {nullptr, nullptr};
     double *cf[9][2] = {};
+    R *pb[2] = {nullptr, nullptr};   // defect correction (FP32 finest level): background
 };
 
 template <typename R>
@@ -162,8 +164,11 @@ Hier<double> &hier<double>(Ctx &C) { return C.h64; }
 template <>
 Hier<float> &hier<float>(Ctx &C) { return C.h32; }
 
+// dc_fine: the finest level also holds the right-hand side array and the
+// frozen background of the defect-correction cycles
 template <typename R>
-void layout_hier(Hier<R> &Hh, Carve &cv, int n, bool adjoint, bool sym_coefs) {
+void layout_hier(Hier<R> &Hh, Carve &cv, int n, bool adjoint, bool sym_coefs,
+                 bool dc_fine = false) {
     int L = 0;
     for (int m = n; m >= 4; m >>= 1) {
         HLevel<R> &H = Hh.lv[L];
@@ -177,9 +182,13 @@ void layout_hier(Hier<R> &Hh, Carve &cv, int n, bool adjoint, bool sym_coefs) {
         if (!adjoint && m >= 128) H.spare2 = cv.take<R>(H.half);
         H.d[0] = cv.take<R>(H.half);
         H.d[1] = cv.take<R>(H.half);
-        if (L > 0 || adjoint) {
+        if (L > 0 || adjoint || dc_fine) {
             H.f[0] = cv.take<R>(H.half);
             H.f[1] = cv.take<R>(H.half);
+        }
+        if (L == 0 && dc_fine) {
+            H.pb[0] = cv.take<R>(H.half);
+            H.pb[1] = cv.take<R>(H.half);
         }
         if (L > 0) {
             H.ru[0] = cv.take<R>(H.half);
@@ -203,7 +212,8 @@ void layout_hier(Hier<R> &Hh, Carve &cv, int n, bool adjoint, bool sym_coefs) {
 // unless precision is MG_FP32, the FP32 one unless it is MG_FP64.
 void layout(Ctx &C, Carve &cv, int n, bool adjoint, int precision, bool sym_coefs = false) {
     if (precision != MG_FP32) layout_hier(C.h64, cv, n, adjoint, sym_coefs);
-    if (precision != MG_FP64) layout_hier(C.h32, cv, n, false, false);
+    if (precision != MG_FP64)
+        layout_hier(C.h32, cv, n, false, false, precision == MG_MIXED_DC);
     C.npartials = std::max<size_t>((size_t)n * n * n / TPB + 1, 1024);
     C.partials = cv.take<double>(2 * C.npartials);
     C.scal = cv.take<double>(S_NSCAL);
@@ -427,8 +437,12 @@ mg_status check_opts(const mg_opts *o) {
     if (o->nu_pre < 0 || o->nu_post < 0 || o->nu_coarse < 1 || o->nu_pre > 64 || o->nu_post > 64 ||
         o->nu_coarse > 4096)
         return fail(MG_ERR_ARG, "sweep counts out of range");
-    if (o->precision != MG_FP64 && o->precision != MG_MIXED && o->precision != MG_FP32)
-        return fail(MG_ERR_ARG, "opts.precision must be MG_FP64, MG_MIXED or MG_FP32");
+    if (o->precision != MG_FP64 && o->precision != MG_MIXED && o->precision != MG_FP32 &&
+        o->precision != MG_MIXED_DC)
+        return fail(MG_ERR_ARG,
+                    "opts.precision must be MG_FP64, MG_MIXED, MG_FP32 or MG_MIXED_DC");
+    if (o->precision == MG_MIXED_DC && o->n < 128)
+        return fail(MG_ERR_ARG, "MG_MIXED_DC needs opts.n >= 128");
     if (o->cycle < MG_CYCLE_V || o->cycle > MG_CYCLE_W)
         return fail(MG_ERR_ARG, "opts.cycle must be MG_CYCLE_V, MG_CYCLE_F or MG_CYCLE_W");
     return MG_OK;
@@ -905,6 +919,99 @@ mg_status fp32_solve(const mg_opts *o, Ctx &C, const double *delta, double *phi,
     return finish(C, (mg_status)p.status, st, t0);
 }
 
+// Defect-correction finish of MG_MIXED_DC (kernels and scheme: mg_dc.h).
+// The FP32 phase left its field in the FP32 finest level; that field becomes
+// the first background pb and the FP64 field phi64.  Each outer step: the
+// FP64 residual of phi64 (stored as g = -r in FP32; the stopping test), one
+// inner cycle for the correction e (FP32 finest sweeps on the correction
+// form, FP64 FAS on the coarse levels), then phi64 += e, pb = fl32(phi64).
+template <int OP>
+mg_status dc_finish(const mg_opts *o, Ctx &C, const double *delta, double *phi, mg_stats *st,
+                    const PhaseResult &p32, int cycles32,
+                    std::chrono::steady_clock::time_point t0) {
+    constexpr int MODEL = OP == OP_POISSON ? MODEL_POISSON : MODEL_DGP;
+    HLevel<double> &F = C.h64.lv[0], &Hc = C.h64.lv[1];
+    HLevel<float> &G = C.h32.lv[0];
+    const double ncell = (double)F.n * F.n * F.n;
+    density_hierarchy<double>(C, delta);
+    for (int c = 0; c < 2; ++c) {
+        k_convert<float, double><<<nblocks(G.half), TPB, 0, C.st>>>(G.u[c], F.u[c], G.half);
+        std::swap(G.pb[c], G.u[c]);
+        k_zero_f32<<<nblocks(G.half), TPB, 0, C.st>>>(G.u[c], G.half);
+    }
+    Solver<OP, double> S64(C);
+    const TileGeom Gf = tile_geom(F.n, F.n), Gr = tile_geom(F.n, F.n / 2);
+    const unsigned nbf = tile_blocks(Gf, F.n), nbr = tile_blocks(Gr, F.n / 2);
+    auto corr_pass = [&](int c) {
+        k_corr_pass_tiled<MODEL><<<nbf, TPB, 0, C.st>>>(C.M, view(G, true), G.pb[0], G.pb[1], c,
+                                                        G.spare, C.scal + S_MU, Gf);
+        std::swap(G.u[c], G.spare);
+    };
+    double hs[S_NSCAL] = {};
+    double best = INFINITY, eps = INFINITY;
+    int status = MG_NOT_CONVERGED, cyc = 0;
+    mg_status rc;
+    for (;;) {
+        // FP64 residual of phi64, g = -r in FP32 (its restriction is unused)
+        k_resid_restrict_tiled<OP, true, false, double, true><<<nbr, TPB, 0, C.st>>>(
+            C.M, view(F, false), C.scal + S_MU64, 1.0, Hc.ru[0], Hc.ru[1], Hc.f[0], Hc.f[1],
+            C.partials, C.clamp, Gr, G.f[0], G.f[1]);
+        k_finalize<<<1, 1024, 0, C.st>>>(C.partials, nbr, ncell, C.scal, 5, 0.0);
+        if ((rc = S64.read_scal(hs)) != MG_OK) return rc;
+        eps = std::sqrt(hs[S_EPS64]);
+        if (cycles32 + cyc < MG_HIST) st->eps_hist[cycles32 + cyc] = eps;
+        if (!std::isfinite(eps)) {
+            status = MG_ERR_NONFINITE;
+            break;
+        }
+        if (eps <= o->tol) {
+            status = MG_OK;
+            break;
+        }
+        if (eps > 1e3 * best) {
+            status = MG_ERR_DIVERGED;
+            break;
+        }
+        best = std::min(best, eps);
+        if (cycles32 + cyc >= o->max_cycles) break;
+        // one inner cycle for the correction, its bordering scalar from zero
+        k_fill<<<1, TPB, 0, C.st>>>(C.scal + S_MU, 1, 0.0);
+        for (int s = 0; s < C.nu1; ++s) {
+            corr_pass(0);
+            corr_pass(1);
+        }
+        k_corr_resid_restrict_tiled<MODEL><<<nbr, TPB, 0, C.st>>>(
+            C.M, view(G, true), G.pb[0], G.pb[1], C.scal + S_MU, Hc.ru[0], Hc.ru[1], Hc.f[0],
+            Hc.f[1], C.partials, Gr);
+        k_finalize<<<1, 1024, 0, C.st>>>(C.partials, nbr, ncell, C.scal, 0, 0.0);
+        S64.coarse_source(1);
+        S64.cycle(1, C.cycle);
+        k_prolong_tiled<float, false, double><<<nbr, TPB, 0, C.st>>>(
+            G.u[0], G.u[1], G.logn, Hc.u[0], Hc.u[1], Hc.ru[0], Hc.ru[1], Gr);
+        for (int s = 0; s < C.nu2; ++s) {
+            corr_pass(0);
+            corr_pass(1);
+        }
+        for (int c = 0; c < 2; ++c)
+            k_dc_accumulate<<<nblocks(G.half), TPB, 0, C.st>>>(F.u[c], G.u[c], G.pb[c], G.half);
+        ++cyc;
+    }
+    st->cycles = cycles32 + cyc;
+    st->eps0 = p32.eps0;
+    st->eps = eps;
+    st->lambda = -hs[S_MU64];
+    st->cell_updates = (long long)o->n * o->n * o->n * (o->nu_pre + o->nu_post) * st->cycles;
+    if (status < 0) {
+        st->status = status;
+        return (mg_status)status;
+    }
+    // zero-mean gauge
+    S64.mean_of(F.u[0], F.u[1], F.half);
+    k_unpack<double, double><<<nblocks(2 * F.half), TPB, 0, C.st>>>(F.u[0], F.u[1], F.logn, phi,
+                                                                    C.scal + S_MEAN);
+    return finish(C, (mg_status)status, st, t0);
+}
+
 // noalloc: the caller cannot allocate (mg_solve_dgp_noalloc), so the solve
 // creates no events and reads the per-cycle scalars with a plain copy into
 // host stack memory instead of the pinned buffer.
@@ -913,7 +1020,10 @@ mg_status forward_solve(const mg_opts *o, const Mod &M, const double *delta, dou
                         void *ws, size_t ws_bytes, hipStream_t stream, mg_stats *st,
                         bool noalloc = false) {
     auto t0 = std::chrono::steady_clock::now();
-    const bool mixed = o->precision == MG_MIXED;
+    const bool dc = o->precision == MG_MIXED_DC;
+    const bool mixed = o->precision == MG_MIXED || dc;
+    if (dc && OP != OP_DGP && OP != OP_POISSON)
+        return fail(MG_ERR_ARG, "MG_MIXED_DC is available for the nDGP and Poisson solves");
     Ctx C;
     Carve cv{static_cast<char *>(ws), 0};
     layout(C, cv, o->n, false, o->precision);
@@ -950,6 +1060,7 @@ mg_status forward_solve(const mg_opts *o, const Mod &M, const double *delta, dou
         cycles32 = p32.cycles;
         st->cycles_fp32 = cycles32;
         st->eps_fp32 = p32.eps;
+        if (dc) return dc_finish<OP>(o, C, delta, phi, st, p32, cycles32, t0);
         k_convert<float, double><<<nblocks(G.half), TPB, 0, C.st>>>(G.u[0], F.u[0], G.half);
         k_convert<float, double><<<nblocks(G.half), TPB, 0, C.st>>>(G.u[1], F.u[1], G.half);
     } else {
@@ -1211,7 +1322,10 @@ extern "C" {
 size_t mg_workspace_bytes(int n, int precision, int model, int adjoint) {
     if (!is_pow2(n) || n < 8 || n > 2048 || model < 0 || model > 3) return 0;
     if (model == MG_MODEL_DGP_NEWTON && (adjoint || precision != MG_FP64)) return 0;
-    if (precision != MG_FP64 && precision != MG_MIXED && precision != MG_FP32) return 0;
+    if (precision != MG_FP64 && precision != MG_MIXED && precision != MG_FP32 &&
+        precision != MG_MIXED_DC)
+        return 0;
+    if (precision == MG_MIXED_DC && n < 128) return 0;
     if (adjoint && precision != MG_FP64) return 0;
     Ctx C;
     Carve cv{nullptr, 0};

@@ -144,4 +144,36 @@ __device__ __forceinline__ T model_term(const Mod &M, const L_ &L, const NbT<T> 
     return (T)((M.src * (double)delta + sig2) / (M.ctil * sig1));
 }
 
+// Correction form of the nDGP model term, used by the defect-correction
+// cycles of the mixed-precision solve: the change of K between the field
+// pb + e and the background pb, evaluated without cancellation so that it
+// is accurate relative to itself when e is small.  With the stencil
+// combinations a (of pb) and b (of e), T(pb + e) - T(pb) = sum (2a + b) b
+// over the quadratic terms of T, and with D = alpha^2 + 8 Sigma / 3,
+//   K(pb + e) - K(pb) = (3/4) sign(alpha) (sqrt(D1) - sqrt(D0))
+//                     = 2 sign(alpha) dSigma / (sqrt(D1) + sqrt(D0)).
+// The Poisson model term does not depend on the field (the change is 0).
+template <int MODEL, typename T, typename L_>
+__device__ __forceinline__ T corr_term(const Mod &M, const L_ &L, const NbT<T> &a,
+                                       const NbT<T> &b, T delta) {
+    if (MODEL == MODEL_POISSON) return (T)0;
+    const T ax = a.xp + a.xm, ay = a.yp + a.ym, az = a.zp + a.zm;
+    const T bx = b.xp + b.xm, by = b.yp + b.ym, bz = b.zp + b.zm;
+    const T dxy = ax - ay, dxz = ax - az, dyz = ay - az;
+    const T exy = bx - by, exz = bx - bz, eyz = by - bz;
+    const T t3 = dxy * dxy + dxz * dxz + dyz * dyz;
+    const T t8 = a.nxy * a.nxy + a.nxz * a.nxz + a.nyz * a.nyz;
+    const T dt3 = ((T)2 * dxy + exy) * exy + ((T)2 * dxz + exz) * exz + ((T)2 * dyz + eyz) * eyz;
+    const T dt8 = ((T)2 * a.nxy + b.nxy) * b.nxy + ((T)2 * a.nxz + b.nxz) * b.nxz
+                + ((T)2 * a.nyz + b.nyz) * b.nyz;
+    const T sig0 = t3 * (T)L.c3h4 + t8 * (T)L.c8h4 + (T)M.s * delta;
+    const T dsig = dt3 * (T)L.c3h4 + dt8 * (T)L.c8h4;
+    T d0 = (T)(M.alpha * M.alpha) + (T)(8.0 / 3.0) * sig0;
+    T d1 = d0 + (T)(8.0 / 3.0) * dsig;
+    d0 = d0 > (T)0 ? d0 : (T)0;
+    d1 = d1 > (T)0 ? d1 : (T)0;
+    const T den = sqrt(d1) + sqrt(d0);
+    return den > (T)0 ? (T)(2.0 * M.sgn) * dsig / den : (T)0;
+}
+
 }  // namespace mgk

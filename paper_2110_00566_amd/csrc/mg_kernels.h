@@ -19,6 +19,8 @@ enum {
     S_MEAN = 3,    // mean of the last summed field
     S_CSUM0 = 4,   // adjoint, tiled finest level: sum of mu over colour 0
     S_CSUM1 = 5,   // ... over colour 1 (each refreshed by the last kernel that wrote the colour)
+    S_MU64 = 6,    // defect correction: the FP64 field's bordering scalar (S_MU is the inner one)
+    S_EPS64 = 7,   // defect correction: squared RMS of the FP64 finest residual
     S_NSCAL = 16
 };
 
@@ -378,7 +380,8 @@ __global__ __launch_bounds__(TPB) void k_sum(const R *a0, const R *a1, size_t nh
 // S_MEAN (shift = 0, eps2 = mean r^2); mode 3: the sum of one colour (colour)
 // of the adjoint field into S_CSUM0 + colour, and S_MEAN = the mean of both
 // colours' sums; mode 4: both colours' sums at once (first and second
-// components).  Summation order is fixed.
+// components); mode 5: mode 0 for the FP64 residual of the defect-correction
+// solve (S_MU64 and S_EPS64).  Summation order is fixed.
 __global__ __launch_bounds__(1024) void k_finalize(const double *partials, size_t nblocks,
                                                    double ncells, double *scal, int mode,
                                                    double kappa, int colour = 0) {
@@ -414,6 +417,10 @@ __global__ __launch_bounds__(1024) void k_finalize(const double *partials, size_
         } else if (mode == 3) {
             scal[S_CSUM0 + colour] = x;
             scal[S_MEAN] = (scal[S_CSUM0] + scal[S_CSUM1]) / ncells;
+        } else if (mode == 5) {
+            scal[S_MU64] += mean;
+            const double v = msq - mean * mean;
+            scal[S_EPS64] = v < 0.0 ? 0.0 : v;   // keeps NaN
         } else if (mode == 4) {
             scal[S_CSUM0] = x;
             scal[S_CSUM1] = y;

@@ -316,12 +316,15 @@ __global__ __launch_bounds__(TPB) void k_pass_tiled(Mod M, LvlT<R> L, int c, R *
 // 2ty+1, both colours), summing over the two fine planes of the coarse
 // plane.  kz counts coarse planes.  HASF: the level has a right-hand side f
 // (every level but the finest).
-template <int OP, bool REDUCE, bool HASF, typename R>
+// WG: also store g = -d of every fine cell in FP32 (g0/g1, the packed
+// colours; the outer step of the defect-correction solve).
+template <int OP, bool REDUCE, bool HASF, typename R, bool WG = false>
 __global__ __launch_bounds__(TPB) void k_resid_restrict_tiled(Mod M, LvlT<R> L, const double *fptr,
                                                               double fscale, R *ru0, R *ru1,
                                                               R *rd0, R *rd1, double *partials,
                                                               unsigned long long *clamp,
-                                                              TileGeom G) {
+                                                              TileGeom G, float *g0 = nullptr,
+                                                              float *g1 = nullptr) {
     __shared__ __align__(16) R s0[3][TSLOT], s1[3][TSLOT];
     const size_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int bx = (int)(blk % G.ntx);
@@ -402,6 +405,9 @@ __global__ __launch_bounds__(TPB) void k_resid_restrict_tiled(Mod M, LvlT<R> L, 
                     acc1 += d;
                     acc2 += d * d;
                 }
+                if (WG)
+                    *ptr(c ? g1 : g0, plane_off<float>(k, L.logn, L.lognh), cell_off<float>(j0 + row, m0 + tx, L.lognh)) =
+                        (float)(-d);
             }
         }
         if (k & 1) {
@@ -421,9 +427,11 @@ __global__ __launch_bounds__(TPB) void k_resid_restrict_tiled(Mod M, LvlT<R> L, 
 // u_fine += P(uc - rc) (see k_prolong) with the coarse difference staged in
 // LDS: 66 coarse columns x 6 coarse rows, ring of 3 coarse planes.  REDUCE:
 // block sums of the corrected colour-0 and colour-1 values into partials.
-template <typename R, bool REDUCE = false>
-__global__ __launch_bounds__(TPB) void k_prolong_tiled(R *f0, R *f1, int logn, const R *uc0,
-                                                       const R *uc1, const R *rc0, const R *rc1,
+// RC: storage type of the coarse level (the defect-correction cycles
+// prolong an FP64 coarse correction into an FP32 finest level).
+template <typename R, bool REDUCE = false, typename RC = R>
+__global__ __launch_bounds__(TPB) void k_prolong_tiled(R *f0, R *f1, int logn, const RC *uc0,
+                                                       const RC *uc1, const RC *rc0, const RC *rc1,
                                                        TileGeom G, double *partials = nullptr) {
     constexpr int CR = TY / 2 + 2;   // coarse rows staged
     constexpr int CPL = TXH * CR;    // 396 values per coarse plane

@@ -263,3 +263,22 @@ def test_noalloc_entry_point_validates_before_the_gpu(L):
     o = mg.make_opts(64)
     assert L.mg_solve_dgp_noalloc(C.byref(o), None, d, d, None, C.byref(st)) == mg.MG_ERR_ARG
     assert L.mg_solve_dgp_noalloc(C.byref(o), C.byref(par), None, d, None, C.byref(st)) == mg.MG_ERR_ARG
+
+
+def test_defect_correction_arguments(L):
+    # MG_MIXED_DC: n >= 128, nDGP and Poisson only (checked before the GPU)
+    assert L.mg_workspace_bytes(64, mg.MG_MIXED_DC, mg.MODEL_DGP, 0) == 0
+    assert L.mg_workspace_bytes(128, mg.MG_MIXED_DC, mg.MODEL_DGP, 0) > \
+        L.mg_workspace_bytes(128, mg.MG_MIXED, mg.MODEL_DGP, 0)
+    assert L.mg_workspace_bytes(128, mg.MG_MIXED_DC, mg.MODEL_DGP, 1) == 0
+    d = C.c_void_p(0x1000)
+    st = mg.Stats()
+    o = mg.make_opts(64, precision=mg.MG_MIXED_DC)
+    assert L.mg_solve_dgp(C.byref(o), C.byref(mg.dgp_params()), d, d, d, 1 << 40, None,
+                          C.byref(st)) == mg.MG_ERR_ARG
+    assert b"128" in L.mg_last_error()
+    o = mg.make_opts(128, precision=mg.MG_MIXED_DC)
+    kp = mg.kmo_params(128, 256.0)
+    assert L.mg_solve_kmouflage(C.byref(o), C.byref(kp), d, d, d, 1 << 40, None,
+                                C.byref(st)) == mg.MG_ERR_ARG
+    assert b"nDGP and Poisson" in L.mg_last_error()

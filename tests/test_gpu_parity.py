@@ -509,6 +509,45 @@ def test_mixed_precision_converges_to_fp64_accuracy(n, h0rc):
         assert rel(f_g, f_o) <= 1e-5
 
 
+@pytest.mark.parametrize("name,n", [("dgp", 128), ("dgp_h05", 256), ("poisson", 128)])
+def test_defect_correction_converges_to_the_oracle(name, n):
+    # MG_MIXED_DC: FP32 cycles to their floor, then outer steps of FP64
+    # residual + one FP32 correction-form cycle + FP64 accumulation; it must
+    # reach the FP64 tolerance (far below the FP32 floor) and the oracle's
+    # converged field
+    gp, om = models(n)[name]
+    pos = inputs.za_particles(n // 2, n, 9, amplitude=30.0)
+    _, delta = oracle.cic_density(pos, n)
+    print("defect correction %s n=%d" % (name, n), flush=True)
+    ref = oracle.solve(om, delta, tol=1e-12, max_cycles=80)
+    fn = {"dgp": mg.solve_dgp, "dgp_h05": mg.solve_dgp, "poisson": None}[name]
+    kw = dict(tol=1e-10, max_cycles=60, precision=mg.MG_MIXED_DC)
+    if name == "poisson":
+        phi, st = mg.solve_poisson(g(delta), gp.s, **kw)
+    else:
+        phi, st = fn(g(delta), a=gp.a, h0rc=gp.h0rc, **kw)
+    assert st["status"] == 0 and st["eps"] <= 1e-10, (st["status"], st["eps"])
+    assert st["cycles_fp32"] >= 1 and st["cycles"] > st["cycles_fp32"]
+    assert st["eps_fp32"] > 1e-9           # the FP32 phase alone stops far above the tolerance
+    dc = st["eps_hist"][st["cycles_fp32"]:st["cycles"] + 1]
+    assert all(b < 0.6 * a for a, b in zip(dc, dc[1:])), dc   # contraction, no floor
+    assert rel(c(phi), ref.phi) <= 1e-9
+    # the residual the solver reports is the oracle's residual of the field
+    r = oracle.residual(om, c(phi), delta)
+    assert np.sqrt(((r - r.mean()) ** 2).mean()) == pytest.approx(st["eps"], rel=1e-3, abs=1e-13)
+
+
+def test_defect_correction_matches_fp64_and_mixed():
+    # same field as the FP64 and the two-phase mixed solves at the same tolerance
+    n = 128
+    delta = g(inputs.lognormal_delta(n, 12))
+    ref, st64 = mg.solve_dgp(delta, tol=1e-11, max_cycles=60)
+    for prec in (mg.MG_MIXED, mg.MG_MIXED_DC):
+        phi, st = mg.solve_dgp(delta, tol=1e-11, max_cycles=60, precision=prec)
+        assert st["status"] == 0 and st["eps"] <= 1e-11
+        assert float((phi - ref).abs().max() / ref.abs().max()) <= 1e-9
+
+
 @pytest.mark.parametrize("name,n", [("dgp", 64), ("kmo3", 32), ("poisson", 32), ("dgp", 128)])
 def test_fp32_cycles_track_oracle(name, n):
     # three FP32-storage cycles (tol = 0 and the cycle cap spent in the FP32
