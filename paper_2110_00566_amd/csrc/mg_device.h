@@ -10,10 +10,11 @@
 // consecutive packed x positions, so every load and store is coalesced.
 //
 // Precision: the storage type R is double (FP64 solve) or float (the FP32
-// phase of the mixed solve).  With float storage a colour pass does its
-// stencil arithmetic in float but evaluates the discriminant, the square root
-// and the division of the closed-form update in double; residuals,
-// restriction sums and reductions are always evaluated in double.
+// phase of the mixed solve).  With float storage the nDGP colour pass runs in
+// float, with the closed-form root in its cancellation-free form (the
+// Kmouflage term keeps its sums and division in double); the residual
+// evaluates the Laplacian in double from the float values and the nDGP term
+// in float; restriction sums and reductions are always evaluated in double.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -120,6 +121,19 @@ __device__ __forceinline__ T model_term(const Mod &M, const L_ &L, const NbT<T> 
         const T dxy = ax - ay, dxz = ax - az, dyz = ay - az;
         const T t3 = dxy * dxy + dxz * dxz + dyz * dyz;
         const T t8 = s.nxy * s.nxy + s.nxz * s.nxz + s.nyz * s.nyz;
+        if constexpr (sizeof(T) == 4) {
+            // FP32 storage: the whole term in FP32, the root in the
+            // cancellation-free form 2 Sigma / (alpha + sign(alpha) sqrt(D))
+            // (equal to the printed one; accurate relative to K when
+            // Sigma << alpha^2).  A clamped D gives -3 alpha / 4 as above.
+            const float sig = t3 * (float)L.c3h4 + t8 * (float)L.c8h4 + (float)M.s * delta;
+            const float disc = (float)(M.alpha * M.alpha) + (8.0f / 3.0f) * sig;
+            if (disc < 0.0f) {
+                if (clamp) atomicAdd(clamp, 1ull);
+                return (T)(-0.75 * M.alpha);
+            }
+            return 2.0f * sig / ((float)M.alpha + (float)M.sgn * sqrtf(disc));
+        }
         const double sig = (double)t3 * L.c3h4 + (double)t8 * L.c8h4 + M.s * (double)delta;
         double disc = M.alpha * M.alpha + (8.0 / 3.0) * sig;
         if (disc < 0.0) {

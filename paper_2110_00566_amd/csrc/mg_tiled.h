@@ -392,13 +392,24 @@ __global__ __launch_bounds__(TPB) void k_resid_restrict_tiled(Mod M, LvlT<R> L, 
                 const R *B0 = (c ? s0[sz] : s1[sz]) + 1;
                 const R *Bp = (c ? s0[sp] : s1[sp]) + 1;
                 const int r = row + 1, q = tx + 1;
-                const Nb s = lds_nb<double, R>(Am, A0, Ap, B0, Bm, Bp, r, q, p);
                 const double u = (double)A0[r * TXH + q];
-                const double faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
                 const double f = (HASF ? (double)fc[2 * b + c] : 0.0) + fs;
-                const double d = (faces - 6.0 * u) * inv_h2 -
-                                 tiled_term<OP, double>(M, L, s, (double)dc[2 * b + c], faces, u,
-                                                        clamp) - f;
+                double d;
+                if constexpr (sizeof(R) == 4 && OP == OP_DGP) {
+                    // FP32 storage: the Laplacian in double, the nDGP term in float
+                    const NbT<float> s = lds_nb<float, R>(Am, A0, Ap, B0, Bm, Bp, r, q, p);
+                    const double faces = ((double)s.xp + (double)s.xm) +
+                                         ((double)s.yp + (double)s.ym) +
+                                         ((double)s.zp + (double)s.zm);
+                    d = (faces - 6.0 * u) * inv_h2 -
+                        (double)model_term<OP, float>(M, L, s, (float)dc[2 * b + c], clamp) - f;
+                } else {
+                    const Nb s = lds_nb<double, R>(Am, A0, Ap, B0, Bm, Bp, r, q, p);
+                    const double faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
+                    d = (faces - 6.0 * u) * inv_h2 -
+                        tiled_term<OP, double>(M, L, s, (double)dc[2 * b + c], faces, u, clamp) -
+                        f;
+                }
                 sd += d;
                 su += u;
                 if (REDUCE) {
@@ -406,8 +417,8 @@ __global__ __launch_bounds__(TPB) void k_resid_restrict_tiled(Mod M, LvlT<R> L, 
                     acc2 += d * d;
                 }
                 if (WG)
-                    *ptr(c ? g1 : g0, plane_off<float>(k, L.logn, L.lognh), cell_off<float>(j0 + row, m0 + tx, L.lognh)) =
-                        (float)(-d);
+                    *ptr(c ? g1 : g0, plane_off<float>(k, L.logn, L.lognh),
+                         cell_off<float>(j0 + row, m0 + tx, L.lognh)) = (float)(-d);
             }
         }
         if (k & 1) {
