@@ -234,19 +234,18 @@ def other_solves(mg, delta, phi_dgp):
 
 def pm_phases(sts):
     """Mean GPU time of a PM step's phases (HIP events in the library) and the
-    cycles of its two field solves."""
+    cycles of its scalar-field solve (the Newtonian potential is an FFT)."""
     import numpy as np
-    names = ("cic", "newtonian_solve", "scalar_solve", "potential_kick_drift")
+    names = ("cic", "newtonian_fft", "scalar_solve", "potential_kick_drift")
     return {"phase_ms": {k: float(np.mean([s["pm_ms"][q] for s in sts]))
                          for q, k in enumerate(names)},
-            "newtonian_cycles_per_step": float(np.mean([s["pm_newton_cycles"] for s in sts])),
             "scalar_cycles_per_step": float(np.mean([s["cycles"] for s in sts]))}
 
 
 def pm_steps(mg, pos0, dev, steps=3):
     """Particle-mesh steps of both models on the bench workload (512^3 mesh,
     256^3 particles, L = 512 Mpc/h) from a = 0.5, da = 0.01: CIC, Newtonian
-    potential, scalar field to 1e-8 (warm-started), kick and drift."""
+    potential by FFT, scalar field to 1e-8 (warm-started), kick and drift."""
     import numpy as np
     import torch
     res = {}
@@ -297,7 +296,8 @@ def vcycle_1024(mg, L, C, pos):
 def pm_step_1024(mg, dev, pos, steps=2):
     """nDGP PM steps on the full-size PM configuration: 1024^3 mesh, 512^3
     Zel'dovich particles (pos, moved in place), L = 1 Gpc/h, a = 1,
-    da = 0.0063, fields to 1e-8 (warm-started after the first step)."""
+    da = 0.0063, Newtonian potential by FFT, scalar field to 1e-8
+    (warm-started after the first step)."""
     import numpy as np
     import torch
     n = 1024

@@ -125,9 +125,9 @@ typedef struct {
                                    evaluations outside the cycles are not included */
     double pm_ms[4];            /* mg_pm_step, mg_pm_step_kmouflage: GPU time (HIP events on
                                    the stream) of the step's phases: CIC deposit, Newtonian
-                                   potential solve, scalar-field solve, total potential +
+                                   potential (FFT), scalar-field solve, total potential +
                                    force interpolation + kick-drift */
-    int pm_newton_cycles;       /* mg_pm_step*: cycles of the Newtonian potential solve */
+    int pm_newton_cycles;       /* mg_pm_step*: 0 (the Newtonian potential is solved by FFT) */
 } mg_stats;
 
 /* nDGP background (eq:beta_dgp with the LCDM expansion eq:H_lcdm, flat,
@@ -274,8 +274,22 @@ mg_status mg_solve_adjoint(const mg_opts *opts, int model, const void *params,
                            double *grad_delta, double *mu, void *ws, size_t ws_bytes,
                            hipStream_t stream, mg_stats *stats);
 
+/* Newtonian potential of the particle-mesh step by FFT (Sec. 3.1): phi =
+ * s lap7^{-1} (delta - mean delta), the exact solution of the 7-point
+ * discrete Poisson equation lap(phi) = s (delta - mean delta) with zero mean
+ * (the Green's function -1 / (4 sum_i sin^2(pi k_i / n)), 0 at k = 0).
+ * n^3 FP64 device arrays (delta and phi must not alias), n a power of two in
+ * [8, 2048]; ws: device workspace of mg_fft_poisson_workspace_bytes(n)
+ * (twiddle factors).  Computed as separable Hartley transforms (the Green's
+ * function is even in every axis), five passes over phi.  Returns after the
+ * stream has finished. */
+size_t mg_fft_poisson_workspace_bytes(int n);
+mg_status mg_fft_poisson(int n, double s, const double *delta, double *phi, void *ws,
+                         size_t ws_bytes, hipStream_t stream);
+
 /* One nDGP particle-mesh step (Sec. 3.1): CIC density from the particles,
- * Newtonian potential (eq:GR_poisson_codeunit), scalar field (warm start from
+ * Newtonian potential (eq:GR_poisson_codeunit, by mg_fft_poisson; phi_newton
+ * is overwritten), scalar field (warm start from
  * phi), total potential Phi_N + phi/2 (eq:poisson_nDGP), 3-point force
  * interpolated with CIC, kick dp/da = -(H0/adot) grad Phi at a, drift
  * dx/da = (H0/adot) p / a^2 at a + da/2.  pos in [0, n_mesh) is wrapped. */

@@ -142,6 +142,10 @@ def lib():
         L.mg_solve_dgp_noalloc.argtypes = [C.POINTER(Opts), C.POINTER(DgpParams), _P, _P, _P,
                                            C.POINTER(Stats)]
         L.mg_solve_dgp_noalloc.restype = st
+        L.mg_fft_poisson_workspace_bytes.argtypes = [C.c_int]
+        L.mg_fft_poisson_workspace_bytes.restype = C.c_size_t
+        L.mg_fft_poisson.argtypes = [C.c_int, C.c_double, _P, _P, _P, C.c_size_t, _P]
+        L.mg_fft_poisson.restype = st
         L.mg_solve_adjoint.argtypes = [C.POINTER(Opts), C.c_int, _P, _P, _P, _P, _P, _P, _P,
                                        C.c_size_t, _P, C.POINTER(Stats)]
         L.mg_solve_adjoint.restype = st
@@ -308,6 +312,24 @@ def solve_dgp_noalloc(delta, phi0=None, a=1.0, omega_m=OMEGA_M, h0rc=1.0, **kw):
     _raise(lib().mg_solve_dgp_noalloc(C.byref(o), C.byref(dgp_params(a, omega_m, h0rc)),
                                       _ptr(delta), _ptr(phi), _stream(), C.byref(st)))
     return phi, st.as_dict()
+
+
+def fft_poisson(delta, s=1.0, phi=None, ws=None):
+    """Zero-mean solution of lap7(phi) = s (delta - mean delta) by FFT
+    (mg_fft_poisson): the Newtonian potential of the particle-mesh step.
+    Returns phi (n^3 float64 on the device)."""
+    _check_mesh(delta, "delta")
+    n = delta.shape[0]
+    if phi is None:
+        phi = torch.empty_like(delta)
+    elif _check_mesh(phi, "phi").shape != delta.shape:
+        raise ValueError("phi and delta must have the same shape")
+    if ws is None:
+        ws = torch.empty(max(lib().mg_fft_poisson_workspace_bytes(n), 1), dtype=torch.uint8,
+                         device=delta.device)
+    _raise(lib().mg_fft_poisson(n, float(s), _ptr(delta), _ptr(phi), _ptr(ws), ws.numel(),
+                                _stream()))
+    return phi
 
 
 def solve_dgp_newton(delta, phi0=None, a=1.0, omega_m=OMEGA_M, h0rc=1.0, ws=None, **kw):

@@ -11,6 +11,9 @@
 
 namespace mgglam_internal {
 void set_error(const char *msg);   // mg_last_error() of the library
+// FFT Poisson solve (fft.hip): phi = s lap7^-1 (delta - mean), ws >= n/2 twiddles
+mg_status fft_poisson(int n, double s, const double *delta, double *phi, void *ws,
+                      hipStream_t stream);
 }
 
 namespace {
@@ -373,11 +376,11 @@ mg_status mg_pm_step(const mg_pm_params *par, float *pos, float *mom, double *ph
     mg_status rc = cic(n, par->n_part, pos, delta_out, counts, stream);
     if (rc != MG_OK) return rc;
     T.mark(1);
-    // Newtonian potential, eq:GR_poisson_codeunit
-    mg_poisson_params pp{1.5 * par->omega_m / par->a};
-    mg_stats pst;
-    rc = mg_solve_poisson(&par->mg, &pp, delta_out, phi_newton, solver_ws, solver_bytes, stream, &pst);
-    if (rc < 0) return rc;
+    // Newtonian potential, eq:GR_poisson_codeunit, by FFT with the Green's
+    // function of the 7-point Laplacian (Sec. 3.1)
+    rc = mgglam_internal::fft_poisson(n, 1.5 * par->omega_m / par->a, delta_out, phi_newton,
+                                      solver_ws, stream);
+    if (rc != MG_OK) return rc;
     T.mark(2);
     // scalar field, eq:dgp_eom_code
     mg_dgp_params dp{par->a, par->omega_m, par->h0rc};
@@ -401,8 +404,7 @@ mg_status mg_pm_step(const mg_pm_params *par, float *pos, float *mom, double *ph
     const mg_status hs = hip_status(stream, true);
     if (hs != MG_OK) return hs;
     T.read(stats);
-    stats->pm_newton_cycles = pst.cycles;
-    if (pst.status == MG_NOT_CONVERGED && rc == MG_OK) rc = MG_NOT_CONVERGED;
+    stats->pm_newton_cycles = 0;
     return rc;
 }
 
@@ -438,12 +440,12 @@ mg_status mg_pm_step_kmouflage(const mg_pm_kmo_params *par, float *pos, float *m
     rc = cic(n, par->n_part, pos, delta_out, counts, stream);
     if (rc != MG_OK) return rc;
     T.mark(1);
-    // Newtonian potential with the rescaled particle mass, eq:kmf_Poission_eqn_codeunit
+    // Newtonian potential with the rescaled particle mass,
+    // eq:kmf_Poission_eqn_codeunit, by FFT
     const double A = std::exp(K.beta * K.phibar);
-    mg_poisson_params pp{1.5 * A * K.omega_m / a};
-    mg_stats pst;
-    rc = mg_solve_poisson(&par->mg, &pp, delta_out, phi_newton, solver_ws, solver_bytes, stream, &pst);
-    if (rc < 0) return rc;
+    rc = mgglam_internal::fft_poisson(n, 1.5 * A * K.omega_m / a, delta_out, phi_newton,
+                                      solver_ws, stream);
+    if (rc != MG_OK) return rc;
     T.mark(2);
     // scalar field, eq:kmf_eqn_codeunit_final
     rc = mg_solve_kmouflage(&par->mg, &K, delta_out, phi, solver_ws, solver_bytes, stream, stats);
@@ -465,8 +467,7 @@ mg_status mg_pm_step_kmouflage(const mg_pm_kmo_params *par, float *pos, float *m
     const mg_status hs = hip_status(stream, true);
     if (hs != MG_OK) return hs;
     T.read(stats);
-    stats->pm_newton_cycles = pst.cycles;
-    if (pst.status == MG_NOT_CONVERGED && rc == MG_OK) rc = MG_NOT_CONVERGED;
+    stats->pm_newton_cycles = 0;
     return rc;
 }
 

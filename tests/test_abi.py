@@ -282,3 +282,20 @@ def test_defect_correction_arguments(L):
     assert L.mg_solve_kmouflage(C.byref(o), C.byref(kp), d, d, d, 1 << 40, None,
                                 C.byref(st)) == mg.MG_ERR_ARG
     assert b"nDGP and Poisson" in L.mg_last_error()
+
+
+def test_fft_poisson_validates_before_the_gpu(L):
+    assert L.mg_fft_poisson_workspace_bytes(12) == 0
+    assert L.mg_fft_poisson_workspace_bytes(4096) == 0
+    assert L.mg_fft_poisson_workspace_bytes(64) >= 32 * 16      # n / 2 complex twiddles
+    d, e, w = C.c_void_p(0x1000), C.c_void_p(0x2000), C.c_void_p(0x3000)
+    big = 1 << 20
+    assert L.mg_fft_poisson(48, 1.0, d, e, w, big, None) == mg.MG_ERR_ARG
+    assert b"power of two" in L.mg_last_error()
+    assert L.mg_fft_poisson(64, float("nan"), d, e, w, big, None) == mg.MG_ERR_ARG
+    assert L.mg_fft_poisson(64, 1.0, None, e, w, big, None) == mg.MG_ERR_ARG
+    assert L.mg_fft_poisson(64, 1.0, d, d, w, big, None) == mg.MG_ERR_ARG
+    assert b"alias" in L.mg_last_error()
+    assert L.mg_fft_poisson(64, 1.0, d, e, None, big, None) == mg.MG_ERR_WORKSPACE
+    assert L.mg_fft_poisson(64, 1.0, d, e, w, 16, None) == mg.MG_ERR_WORKSPACE
+    assert L.mg_fft_poisson(64, 1.0, d, e, C.c_void_p(0x3000 + 8), big, None) == mg.MG_ERR_WORKSPACE

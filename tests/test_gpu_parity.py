@@ -483,11 +483,85 @@ def test_pm_step_parity():
     delta, st = mg.pm_step(gpos, gmom, phi, phin, nm, 1.0, 0.0063, tol=1e-10)
     assert rel(c(delta), delta_o) <= 1e-8
     assert rel(c(phin), phin_o) <= 1e-8
+    # the FFT potential of the step's own density, to FFT rounding
+    assert rel(c(phin), oracle.fft_poisson(1.5 * OM * c(delta))) <= 1e-12
     assert rel(c(phi), phi_o) <= 1e-8
     assert rel(c(gmom), m_o) <= 1e-5
     dp = np.abs(c(gpos) - p_o)
     dp = np.minimum(dp, nm - dp)
     assert dp.max() <= 1e-4
+
+
+# ------------------------------------------------------ FFT Poisson solve
+
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 128])
+def test_fft_poisson_parity(n):
+    # element by element against the oracle's complex FFT solution; both
+    # round like an FFT (eps log n relative to the largest value)
+    d = field(n, 40 + n) + 0.3
+    s = 1.5 * OM / 0.7
+    ref = oracle.fft_poisson(s * d)
+    out = c(mg.fft_poisson(g(d), s))
+    assert rel(out, ref) <= 1e-12
+    assert abs(out.mean()) <= 1e-13 * np.abs(ref).max()
+
+
+def test_fft_poisson_edge_cases():
+    n = 32
+    ws = torch.empty(4096, dtype=torch.uint8, device=DEV)
+    # a uniform source has the zero solution
+    out = c(mg.fft_poisson(torch.full((n,) * 3, 2.5, dtype=torch.float64, device=DEV), 1.0, ws=ws))
+    assert np.abs(out).max() <= 1e-14
+    # a single spike: the lattice Green's function, symmetric under every
+    # axis reflection about the spike and under axis permutations
+    d = np.zeros((n,) * 3)
+    d[0, 0, 0] = 1.0
+    out = c(mg.fft_poisson(g(d), 1.0, ws=ws))
+    assert rel(out, oracle.fft_poisson(d)) <= 1e-12
+    assert np.abs(out - np.roll(out[::-1, ::-1, ::-1], 1, axis=(0, 1, 2))).max() <= 1e-15
+    assert np.abs(out - out.transpose(2, 1, 0)).max() <= 1e-15
+    # the output array is overwritten, whatever it held
+    phi = torch.full((n,) * 3, np.nan, dtype=torch.float64, device=DEV)
+    mg.fft_poisson(g(d), 1.0, phi=phi, ws=ws)
+    assert np.abs(c(phi) - out).max() == 0.0
+
+
+def _plane_waves(n, z0, z1, dev=DEV):
+    # cos of mode (3, 5, 7) plus 0.5 sin of mode (n/2 - 1, 1, n/4) on planes
+    # z0 .. z1-1 (index order z, y, x); both are eigenfunctions of the
+    # 7-point Laplacian with eigenvalue -4 sum_i sin^2(pi m_i / n)
+    x = torch.arange(n, dtype=torch.float64, device=dev)
+    z = torch.arange(z0, z1, dtype=torch.float64, device=dev)
+    t = 2 * np.pi / n
+    a = torch.cos(t * (3 * x[None, None, :] + 5 * x[None, :, None] + 7 * z[:, None, None]))
+    b = torch.sin(t * ((n // 2 - 1) * x[None, None, :] + x[None, :, None]
+                       + (n // 4) * z[:, None, None]))
+    return a, b
+
+
+def _eig(n, m):
+    return -4.0 * sum(np.sin(np.pi * k / n) ** 2 for k in m)
+
+
+@pytest.mark.parametrize("n", [1024, 2048])
+def test_fft_poisson_full_size_plane_waves(n):
+    # maximum sizes (16 and 8 lines per block): the exact discrete solution of
+    # a two-mode source, checked on the device plane block by plane block
+    s = 1.5 * OM
+    chunk = 64
+    d = torch.empty((n,) * 3, dtype=torch.float64, device=DEV)
+    for z0 in range(0, n, chunk):
+        a, b = _plane_waves(n, z0, z0 + chunk)
+        d[z0:z0 + chunk] = a + 0.5 * b
+    phi = mg.fft_poisson(d, s)
+    del d
+    ea, eb = _eig(n, (3, 5, 7)), _eig(n, (n // 2 - 1, 1, n // 4))
+    err = 0.0
+    for z0 in range(0, n, chunk):
+        a, b = _plane_waves(n, z0, z0 + chunk)
+        exp = s * (a / ea + 0.5 * b / eb)
+        err = max(err, (phi[z0:z0 + chunk] - exp).abs().max().item())
+    assert err <= 1e-12 * s / abs(ea)
 
 
 # --------------------------------------------------------- mixed precision
