@@ -278,11 +278,12 @@ mg_status mg_solve_adjoint(const mg_opts *opts, int model, const void *params,
  * s lap7^{-1} (delta - mean delta), the exact solution of the 7-point
  * discrete Poisson equation lap(phi) = s (delta - mean delta) with zero mean
  * (the Green's function -1 / (4 sum_i sin^2(pi k_i / n)), 0 at k = 0).
- * n^3 FP64 device arrays (delta and phi must not alias), n a power of two in
- * [8, 2048]; ws: device workspace of mg_fft_poisson_workspace_bytes(n)
+ * n^3 FP64 device arrays (16-byte aligned; delta and phi must not alias), n a
+ * power of two in [8, 2048]; ws: device workspace of mg_fft_poisson_workspace_bytes(n)
  * (twiddle factors).  Computed as separable Hartley transforms (the Green's
  * function is even in every axis), five passes over phi.  Returns after the
- * stream has finished. */
+ * stream has finished; MG_ERR_ARG / MG_ERR_WORKSPACE (nothing launched) for
+ * invalid arguments. */
 size_t mg_fft_poisson_workspace_bytes(int n);
 mg_status mg_fft_poisson(int n, double s, const double *delta, double *phi, void *ws,
                          size_t ws_bytes, hipStream_t stream);
@@ -292,11 +293,12 @@ mg_status mg_fft_poisson(int n, double s, const double *delta, double *phi, void
  * is overwritten), scalar field (warm start from
  * phi), total potential Phi_N + phi/2 (eq:poisson_nDGP), 3-point force
  * interpolated with CIC, kick dp/da = -(H0/adot) grad Phi at a, drift
- * dx/da = (H0/adot) p / a^2 at a + da/2.  pos in [0, n_mesh) is wrapped. */
+ * dx/da = (H0/adot) p / a^2 at a + da/2.  pos in [0, n_mesh) is wrapped.
+ * phi_newton and delta_out are 16-byte aligned (MG_ERR_ARG otherwise). */
 typedef struct {
     int n_mesh, n_part;
     double omega_m, h0rc, a, da;
-    mg_opts mg;   /* options of both field solves; mg.n must equal n_mesh */
+    mg_opts mg;   /* options of the scalar-field solve; mg.n must equal n_mesh */
 } mg_pm_params;
 size_t mg_pm_workspace_bytes(int n_mesh);
 mg_status mg_pm_step(const mg_pm_params *par, float *pos, float *mom, double *phi,
@@ -333,7 +335,7 @@ typedef struct {
     double box_mpch;
     mg_kmo_bg_params bg;           /* model (n_k, K0, beta) and background cosmology */
     const mg_kmo_bg_table *table;  /* HOST, optional (NULL: solve the background here) */
-    mg_opts mg;                    /* options of both field solves; mg.n must equal n_mesh */
+    mg_opts mg;                    /* options of the scalar-field solve; mg.n must equal n_mesh */
 } mg_pm_kmo_params;
 mg_status mg_pm_step_kmouflage(const mg_pm_kmo_params *par, float *pos, float *mom, double *phi,
                                double *phi_newton, double *delta_out, void *ws, size_t ws_bytes,

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmgglam.so")
 SOURCES = ["mg_api.hip", "pm.hip", "fft.hip", "kmo_background.cpp"]
-HEADERS = ["mg_device.h", "mg_kernels.h", "mg_adjoint.h"]
+HEADERS = ["mg_device.h", "mg_kernels.h", "mg_tiled.h", "mg_adjoint.h", "mg_adj_tiled.h", "mg_dc.h"]
 ARCH = os.environ.get("MGGLAM_ARCH", "gfx950")
 
 

@@ -363,6 +363,8 @@ mg_status mg_pm_step(const mg_pm_params *par, float *pos, float *mom, double *ph
     if (par->n_part < 1 || par->n_part > 2048 || !(par->a > 0.0) || !std::isfinite(par->da) ||
         !(par->omega_m > 0.0) || !(par->omega_m < 1.0))
         return fail(MG_ERR_ARG, "invalid n_part, a, da or omega_m");
+    if (((uintptr_t)phi_newton | (uintptr_t)delta_out) & 15)
+        return fail(MG_ERR_ARG, "phi_newton and delta_out must be 16-byte aligned");
     const size_t need = mg_pm_workspace_bytes(n);
     if (!ws || ws_bytes < need || ((uintptr_t)ws & 255))
         return fail(MG_ERR_WORKSPACE, "workspace is NULL, too small or not 256-byte aligned");
@@ -421,6 +423,8 @@ mg_status mg_pm_step_kmouflage(const mg_pm_kmo_params *par, float *pos, float *m
         !std::isfinite(par->da) || !(par->a + 0.5 * par->da <= 1.0) || !(par->box_mpch > 0.0) ||
         !std::isfinite(par->box_mpch))
         return fail(MG_ERR_ARG, "invalid n_part, a, da (need a + da/2 <= 1) or box_mpch");
+    if (((uintptr_t)phi_newton | (uintptr_t)delta_out) & 15)
+        return fail(MG_ERR_ARG, "phi_newton and delta_out must be 16-byte aligned");
     const size_t need = mg_pm_workspace_bytes(n);
     if (!ws || ws_bytes < need || ((uintptr_t)ws & 255))
         return fail(MG_ERR_WORKSPACE, "workspace is NULL, too small or not 256-byte aligned");

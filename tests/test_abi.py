@@ -299,3 +299,9 @@ def test_fft_poisson_validates_before_the_gpu(L):
     assert L.mg_fft_poisson(64, 1.0, d, e, None, big, None) == mg.MG_ERR_WORKSPACE
     assert L.mg_fft_poisson(64, 1.0, d, e, w, 16, None) == mg.MG_ERR_WORKSPACE
     assert L.mg_fft_poisson(64, 1.0, d, e, C.c_void_p(0x3000 + 8), big, None) == mg.MG_ERR_WORKSPACE
+
+
+def test_fft_poisson_requires_16_byte_alignment(L):
+    d, e, w = C.c_void_p(0x1008), C.c_void_p(0x2000), C.c_void_p(0x3000)
+    assert L.mg_fft_poisson(64, 1.0, d, e, w, 1 << 20, None) == mg.MG_ERR_ARG
+    assert b"16-byte" in L.mg_last_error()
