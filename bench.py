@@ -422,42 +422,49 @@ def main():
     if args.main_only:
         print(json.dumps(out), flush=True)
         return
-    # the same step with the mixed-precision solve (FP32 cycles to the FP32
-    # floor, FP64 cycles to the same FP64 tolerance)
+    # the same step with the two mixed-precision solves, to the same FP64
+    # tolerance: "mixed" (MG_MIXED: FP32 cycles to the FP32 floor, then FP64
+    # cycles) and "mixed_dc" (MG_MIXED_DC: the same FP32 cycles, then defect
+    # correction: FP64 residual, one FP32 correction cycle, FP64 accumulation)
     phi64 = phi.clone()
-    ws_mix = mg.workspace(N_MESH, mg.MODEL_DGP, False, dev, mg.MG_MIXED)
-    opts_mix = mg.make_opts(N_MESH, tol=TOL, max_cycles=60, precision=mg.MG_MIXED)
+    for key, prec in (("mixed", mg.MG_MIXED), ("mixed_dc", mg.MG_MIXED_DC)):
+        ws_mix = mg.workspace(N_MESH, mg.MODEL_DGP, False, dev, prec)
+        opts_mix = mg.make_opts(N_MESH, tol=TOL, max_cycles=60, precision=prec)
 
-    def step_mixed():
-        stream = mg._stream()
-        mg._raise(L.mg_cic_delta(N_MESH, N_PART, mg._ptr(pos), mg._ptr(delta), mg._ptr(ws_pm),
-                                 ws_pm.numel(), stream))
-        phi.zero_()
-        st = mg.Stats()
-        mg._raise(L.mg_solve_dgp(C.byref(opts_mix), C.byref(par), mg._ptr(delta), mg._ptr(phi),
-                                 mg._ptr(ws_mix), ws_mix.numel(), stream, C.byref(st)))
-        return st
+        def step_mixed():
+            stream = mg._stream()
+            mg._raise(L.mg_cic_delta(N_MESH, N_PART, mg._ptr(pos), mg._ptr(delta),
+                                     mg._ptr(ws_pm), ws_pm.numel(), stream))
+            phi.zero_()
+            st = mg.Stats()
+            mg._raise(L.mg_solve_dgp(C.byref(opts_mix), C.byref(par), mg._ptr(delta),
+                                     mg._ptr(phi), mg._ptr(ws_mix), ws_mix.numel(), stream,
+                                     C.byref(st)))
+            return st
 
-    step_mixed()
-    torch.cuda.synchronize()
-    mstats = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        mstats.append(step_mixed())
-    torch.cuda.synchronize()
-    dtm = time.perf_counter() - t0
-    assert all(s.status == 0 and s.eps <= TOL for s in mstats), [s.status for s in mstats]
-    err = float((phi - phi64).abs().max() / phi64.abs().max())
-    mix_solve_ms = 1e3 * float(np.mean([s.seconds for s in mstats]))
-    out["mixed"] = {"ms_per_step": 1e3 * dtm / args.steps, "time_to_tol_ms": mix_solve_ms,
-                    "cycles": int(mstats[-1].cycles), "cycles_fp32": int(mstats[-1].cycles_fp32),
+        step_mixed()
+        torch.cuda.synchronize()
+        mstats = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            mstats.append(step_mixed())
+        torch.cuda.synchronize()
+        dtm = time.perf_counter() - t0
+        assert all(s.status == 0 and s.eps <= TOL for s in mstats), [s.status for s in mstats]
+        err = float((phi - phi64).abs().max() / phi64.abs().max())
+        mix_solve_ms = 1e3 * float(np.mean([s.seconds for s in mstats]))
+        out[key] = {"ms_per_step": 1e3 * dtm / args.steps, "time_to_tol_ms": mix_solve_ms,
+                    "cycles": int(mstats[-1].cycles),
+                    "cycles_fp32": int(mstats[-1].cycles_fp32),
                     "eps_fp32": float(mstats[-1].eps_fp32), "eps": float(mstats[-1].eps),
                     "speedup_time_to_tol_vs_fp64": solve_ms / mix_solve_ms,
                     "max_rel_diff_phi_vs_fp64": err}
+        del ws_mix
+        torch.cuda.empty_cache()
     out["cycle_types"] = cycle_types(mg, L, C, delta, ws, par, phi64)
     out["comparators"] = comparators(mg, L, C, delta, ws, par, phi64)
     out["other_solves"] = other_solves(mg, delta, phi64)
-    del ws_mix, ws
+    del ws
     torch.cuda.empty_cache()
     out["vcycle_512"] = vcycle_time(mg, L, C, delta)
     out["pm_steps"] = pm_steps(mg, pos, dev)

@@ -98,6 +98,11 @@ typedef struct {
                          mg_solve_adjoint accepts MG_CYCLE_V only */
     int profile;      /* 1: time every finest-level colour pass with HIP events
                          on the caller's stream (stats.pass_ms_avg) */
+    int delta_fp32;   /* 0: the solves' delta is FP64 (double *); 1: FP32 (float *),
+                         any precision (it is widened or kept as the levels store
+                         it; half the bytes of the caller's array).  phi and every
+                         other array stay FP64.  The PM steps ignore it (their
+                         density is their own FP64 delta_out). */
 } mg_opts;
 
 #define MG_HIST 64
@@ -196,10 +201,11 @@ size_t mg_workspace_bytes(int n, int precision, int model, int adjoint);
 /* Solve the nDGP scalar-field equation eq:dgp_eom_code in the form of
  * eq:DGP, i.e. L(phi) = lap(phi) - (3/4)[-alpha + sign(alpha) sqrt(alpha^2 +
  * 8 Sigma / 3)] = 0 with Sigma from the discrete operator of Sec. 3.2.3.
- * delta: FP64 density contrast (n^3).  phi: in = initial guess, out = the
- * zero-mean solution.  The periodic discrete problem is solved in bordered
- * form L(phi) + lambda = 0 (lambda in stats). */
-mg_status mg_solve_dgp(const mg_opts *opts, const mg_dgp_params *par, const double *delta,
+ * delta: density contrast (n^3), FP64 or, with opts->delta_fp32 = 1, FP32.
+ * phi (FP64): in = initial guess, out = the zero-mean solution.  The periodic
+ * discrete problem is solved in bordered form L(phi) + lambda = 0 (lambda in
+ * stats). */
+mg_status mg_solve_dgp(const mg_opts *opts, const mg_dgp_params *par, const void *delta,
                        double *phi, void *ws, size_t ws_bytes, hipStream_t stream,
                        mg_stats *stats);
 
@@ -217,7 +223,7 @@ mg_status mg_solve_dgp(const mg_opts *opts, const mg_dgp_params *par, const doub
  * share the array and race: serialise them (one stream, or host order).
  * stream must belong to the current device. */
 mg_status mg_solve_dgp_noalloc(const mg_opts *opts, const mg_dgp_params *par,
-                               const double *delta, double *phi, hipStream_t stream,
+                               const void *delta, double *phi, hipStream_t stream,
                                mg_stats *stats);
 
 /* Comparator for the closed-form relaxation: the same nDGP problem written in
@@ -231,7 +237,7 @@ mg_status mg_solve_dgp_noalloc(const mg_opts *opts, const mg_dgp_params *par,
  * mg_solve_dgp residual to first order in Sigma/alpha^2).  FP64 only; the same
  * kernels as mg_solve_dgp (LDS-tiled on levels >= 128^3) with the Newton step
  * in place of the closed form; same arguments as mg_solve_dgp. */
-mg_status mg_solve_dgp_newton(const mg_opts *opts, const mg_dgp_params *par, const double *delta,
+mg_status mg_solve_dgp_newton(const mg_opts *opts, const mg_dgp_params *par, const void *delta,
                               double *phi, void *ws, size_t ws_bytes, hipStream_t stream,
                               mg_stats *stats);
 
@@ -239,7 +245,7 @@ mg_status mg_solve_dgp_newton(const mg_opts *opts, const mg_dgp_params *par, con
  * c~ lap(phi) = (3 beta A Omega_m delta / a + Sigma_2) / Sigma_1.
  * Same argument conventions as mg_solve_dgp. */
 mg_status mg_solve_kmouflage(const mg_opts *opts, const mg_kmo_params *par,
-                             const double *delta, double *phi, void *ws, size_t ws_bytes,
+                             const void *delta, double *phi, void *ws, size_t ws_bytes,
                              hipStream_t stream, mg_stats *stats);
 
 /* Comparator: coefficient s of the linearised field equation lap(phi) = s
@@ -259,7 +265,7 @@ mg_status mg_linear_source(int model, const void *params, int n, double *s);
  * delta) with the same multigrid (zero-mean phi).  Equals the FFT solution
  * with the discrete Green's function of the 7-point Laplacian. */
 mg_status mg_solve_poisson(const mg_opts *opts, const mg_poisson_params *par,
-                           const double *delta, double *phi, void *ws, size_t ws_bytes,
+                           const void *delta, double *phi, void *ws, size_t ws_bytes,
                            hipStream_t stream, mg_stats *stats);
 
 /* Gradient of loss = sum(phi * w) with respect to delta, phi being the
@@ -268,9 +274,11 @@ mg_status mg_solve_poisson(const mg_opts *opts, const mg_poisson_params *par,
  * J^T mu + nu 1 = w, sum(mu) = 0 (J = dL/dphi at phi) by multigrid with the
  * coarse-level linearisation points recomputed by restriction, then
  * grad_delta = -(dL/ddelta) mu.  opts->tol applies to the RMS of the adjoint
- * residual.  mu: in = warm start (zeros if unknown), out = adjoint field. */
+ * residual.  mu: in = warm start (zeros if unknown), out = adjoint field.
+ * delta as in mg_solve_dgp (FP64, or FP32 with opts->delta_fp32); the other
+ * arrays FP64. */
 mg_status mg_solve_adjoint(const mg_opts *opts, int model, const void *params,
-                           const double *delta, const double *phi, const double *w,
+                           const void *delta, const double *phi, const double *w,
                            double *grad_delta, double *mu, void *ws, size_t ws_bytes,
                            hipStream_t stream, mg_stats *stats);
 

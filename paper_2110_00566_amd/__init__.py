@@ -50,7 +50,8 @@ class MGError(RuntimeError):
 class Opts(C.Structure):
     _fields_ = [("n", C.c_int), ("max_cycles", C.c_int), ("tol", C.c_double),
                 ("nu_pre", C.c_int), ("nu_post", C.c_int), ("nu_coarse", C.c_int),
-                ("precision", C.c_int), ("cycle", C.c_int), ("profile", C.c_int)]
+                ("precision", C.c_int), ("cycle", C.c_int), ("profile", C.c_int),
+                ("delta_fp32", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -227,8 +228,9 @@ def workspace(n: int, model: int = MODEL_DGP, adjoint: bool = False, device=None
 
 
 def make_opts(n, tol=1e-8, max_cycles=50, nu_pre=1, nu_post=1, nu_coarse=32, profile=False,
-              precision=MG_FP64, cycle=CYCLE_V):
-    return Opts(n, max_cycles, tol, nu_pre, nu_post, nu_coarse, precision, cycle, int(profile))
+              precision=MG_FP64, cycle=CYCLE_V, delta_fp32=False):
+    return Opts(n, max_cycles, tol, nu_pre, nu_post, nu_coarse, precision, cycle, int(profile),
+                int(delta_fp32))
 
 
 def dgp_params(a=1.0, omega_m=OMEGA_M, h0rc=1.0):
@@ -279,13 +281,33 @@ def kmo_params_from_background(n_mesh, box_mpch, n_k, k0, beta, a, omega_m=OMEGA
                      float(bg["dphibar_dtau"][0]))
 
 
-def _solve(fn, par, model, delta, phi0, ws, **kw):
+def _check_delta(delta):
+    """delta may be float64 or float32 (mg_opts.delta_fp32); returns the flag."""
+    if isinstance(delta, torch.Tensor) and delta.dtype == torch.float32:
+        _check_mesh(delta, "delta", torch.float32)
+        return True
     _check_mesh(delta, "delta")
+    return False
+
+
+def _zeros64(like):
+    return torch.zeros(like.shape, dtype=torch.float64, device=like.device)
+
+
+def _same_shape(delta, *named):
+    for t, nm in named:
+        if t.shape != delta.shape:
+            raise ValueError("%s must have the shape of delta %s" % (nm, tuple(delta.shape)))
+
+
+def _solve(fn, par, model, delta, phi0, ws, **kw):
+    d32 = _check_delta(delta)
     n = delta.shape[0]
-    phi = torch.zeros_like(delta) if phi0 is None else _check_mesh(phi0, "phi0").clone()
+    phi = _zeros64(delta) if phi0 is None else _check_mesh(phi0, "phi0").clone()
+    _same_shape(delta, (phi, "phi0"))
     if ws is None:
         ws = workspace(n, model, False, delta.device, kw.get("precision", MG_FP64))
-    o = make_opts(n, **kw)
+    o = make_opts(n, delta_fp32=d32, **kw)
     st = Stats()
     rc = fn(C.byref(o), C.byref(par), _ptr(delta), _ptr(phi), _ptr(ws), ws.numel(), _stream(),
             C.byref(st))
@@ -304,10 +326,11 @@ def solve_dgp(delta, phi0=None, a=1.0, omega_m=OMEGA_M, h0rc=1.0, ws=None, **kw)
 def solve_dgp_noalloc(delta, phi0=None, a=1.0, omega_m=OMEGA_M, h0rc=1.0, **kw):
     """solve_dgp through mg_solve_dgp_noalloc: the library's static per-GPU
     workspace, no allocation inside the call (n <= 128).  Returns (phi, stats)."""
-    _check_mesh(delta, "delta")
+    d32 = _check_delta(delta)
     n = delta.shape[0]
-    phi = torch.zeros_like(delta) if phi0 is None else _check_mesh(phi0, "phi0").clone()
-    o = make_opts(n, **kw)
+    phi = _zeros64(delta) if phi0 is None else _check_mesh(phi0, "phi0").clone()
+    _same_shape(delta, (phi, "phi0"))
+    o = make_opts(n, delta_fp32=d32, **kw)
     st = Stats()
     _raise(lib().mg_solve_dgp_noalloc(C.byref(o), C.byref(dgp_params(a, omega_m, h0rc)),
                                       _ptr(delta), _ptr(phi), _stream(), C.byref(st)))
@@ -377,14 +400,16 @@ def solve_adjoint(model, par, delta, phi, w, mu0=None, ws=None, tol=1e-10, max_c
     """Gradient of sum(phi*w) w.r.t. delta at the converged phi.
     Returns (grad_delta, mu, stats)."""
     par = _params_for(model, par)
-    for t, nm in ((delta, "delta"), (phi, "phi"), (w, "w")):
+    d32 = _check_delta(delta)
+    for t, nm in ((phi, "phi"), (w, "w")):
         _check_mesh(t, nm)
     n = delta.shape[0]
-    mu = torch.zeros_like(delta) if mu0 is None else _check_mesh(mu0, "mu0").clone()
-    grad = torch.empty_like(delta)
+    mu = _zeros64(delta) if mu0 is None else _check_mesh(mu0, "mu0").clone()
+    _same_shape(delta, (phi, "phi"), (w, "w"), (mu, "mu0"))
+    grad = torch.empty(delta.shape, dtype=torch.float64, device=delta.device)
     if ws is None:
         ws = workspace(n, model, True, delta.device)
-    o = make_opts(n, tol=tol, max_cycles=max_cycles, **kw)
+    o = make_opts(n, tol=tol, max_cycles=max_cycles, delta_fp32=d32, **kw)
     st = Stats()
     rc = lib().mg_solve_adjoint(C.byref(o), model, C.byref(par), _ptr(delta), _ptr(phi), _ptr(w),
                                 _ptr(grad), _ptr(mu), _ptr(ws), ws.numel(), _stream(),

@@ -445,6 +445,8 @@ mg_status check_opts(const mg_opts *o) {
         return fail(MG_ERR_ARG, "MG_MIXED_DC needs opts.n >= 128");
     if (o->cycle < MG_CYCLE_V || o->cycle > MG_CYCLE_W)
         return fail(MG_ERR_ARG, "opts.cycle must be MG_CYCLE_V, MG_CYCLE_F or MG_CYCLE_W");
+    if (o->delta_fp32 != 0 && o->delta_fp32 != 1)
+        return fail(MG_ERR_ARG, "opts.delta_fp32 must be 0 (FP64 delta) or 1 (FP32 delta)");
     return MG_OK;
 }
 
@@ -834,13 +836,24 @@ struct Solver {
     }
 };
 
+// The caller's density: n^3 values in natural order, FP64 or FP32
+// (mg_opts.delta_fp32).
+struct DeltaIn {
+    const void *p;
+    bool f32;
+};
+
 // Pack delta into the finest level of hierarchy R and restrict it down.
 template <typename R>
-void density_hierarchy(Ctx &C, const double *delta) {
+void density_hierarchy(Ctx &C, DeltaIn delta) {
     Hier<R> &Hh = hier<R>(C);
     HLevel<R> &F = Hh.lv[0];
-    k_pack<double, R><<<nblocks(2 * F.half), TPB, 0, C.st>>>(delta, F.logn, F.d[0], F.d[1],
-                                                            nullptr);
+    if (delta.f32)
+        k_pack<float, R><<<nblocks(2 * F.half), TPB, 0, C.st>>>(
+            static_cast<const float *>(delta.p), F.logn, F.d[0], F.d[1], nullptr);
+    else
+        k_pack<double, R><<<nblocks(2 * F.half), TPB, 0, C.st>>>(
+            static_cast<const double *>(delta.p), F.logn, F.d[0], F.d[1], nullptr);
     for (int l = 0; l + 1 < Hh.nlev; ++l) {
         HLevel<R> &H = Hh.lv[l], &Hc = Hh.lv[l + 1];
         k_restrict<R><<<nblocks(2 * Hc.half), TPB, 0, C.st>>>(H.d[0], H.d[1], H.logn, Hc.d[0],
@@ -893,7 +906,7 @@ mg_status finish(Ctx &C, mg_status status, mg_stats *st,
 // at max_cycles, or when a cycle no longer halves the residual (the FP32
 // floor), which returns MG_NOT_CONVERGED with a valid phi.
 template <int OP>
-mg_status fp32_solve(const mg_opts *o, Ctx &C, const double *delta, double *phi, mg_stats *st,
+mg_status fp32_solve(const mg_opts *o, Ctx &C, DeltaIn delta, double *phi, mg_stats *st,
                      std::chrono::steady_clock::time_point t0) {
     density_hierarchy<float>(C, delta);
     HLevel<float> &G = C.h32.lv[0];
@@ -926,7 +939,7 @@ mg_status fp32_solve(const mg_opts *o, Ctx &C, const double *delta, double *phi,
 // inner cycle for the correction e (FP32 finest sweeps on the correction
 // form, FP64 FAS on the coarse levels), then phi64 += e, pb = fl32(phi64).
 template <int OP>
-mg_status dc_finish(const mg_opts *o, Ctx &C, const double *delta, double *phi, mg_stats *st,
+mg_status dc_finish(const mg_opts *o, Ctx &C, DeltaIn delta, double *phi, mg_stats *st,
                     const PhaseResult &p32, int cycles32,
                     std::chrono::steady_clock::time_point t0) {
     constexpr int MODEL = OP == OP_POISSON ? MODEL_POISSON : MODEL_DGP;
@@ -1016,10 +1029,11 @@ mg_status dc_finish(const mg_opts *o, Ctx &C, const double *delta, double *phi, 
 // creates no events and reads the per-cycle scalars with a plain copy into
 // host stack memory instead of the pinned buffer.
 template <int OP>
-mg_status forward_solve(const mg_opts *o, const Mod &M, const double *delta, double *phi,
+mg_status forward_solve(const mg_opts *o, const Mod &M, const void *delta_p, double *phi,
                         void *ws, size_t ws_bytes, hipStream_t stream, mg_stats *st,
                         bool noalloc = false) {
     auto t0 = std::chrono::steady_clock::now();
+    const DeltaIn delta{delta_p, o->delta_fp32 != 0};
     const bool dc = o->precision == MG_MIXED_DC;
     const bool mixed = o->precision == MG_MIXED || dc;
     if (dc && OP != OP_DGP && OP != OP_POISSON)
@@ -1118,10 +1132,11 @@ void adj_coefficients(Ctx &C, const double *phi) {
 }
 
 template <int MODEL>
-mg_status adjoint_solve(const mg_opts *o, const Mod &M, const double *delta, const double *phi,
+mg_status adjoint_solve(const mg_opts *o, const Mod &M, const void *delta_p, const double *phi,
                         const double *w, double *grad, double *mu, void *ws, size_t ws_bytes,
                         hipStream_t stream, mg_stats *st) {
     auto t0 = std::chrono::steady_clock::now();
+    const DeltaIn delta{delta_p, o->delta_fp32 != 0};
     Ctx C;
     Carve cv{static_cast<char *>(ws), 0};
     layout(C, cv, o->n, true, MG_FP64, MODEL != MODEL_KMO);
@@ -1348,7 +1363,7 @@ mg_status mg_linear_source(int model, const void *params, int n, double *s) {
     return MG_OK;
 }
 
-mg_status mg_solve_dgp(const mg_opts *opts, const mg_dgp_params *par, const double *delta,
+mg_status mg_solve_dgp(const mg_opts *opts, const mg_dgp_params *par, const void *delta,
                        double *phi, void *ws, size_t ws_bytes, hipStream_t stream,
                        mg_stats *stats) {
     mg_status rc = common_checks(opts, delta, phi, ws, stats);
@@ -1359,7 +1374,7 @@ mg_status mg_solve_dgp(const mg_opts *opts, const mg_dgp_params *par, const doub
 }
 
 mg_status mg_solve_dgp_noalloc(const mg_opts *opts, const mg_dgp_params *par,
-                               const double *delta, double *phi, hipStream_t stream,
+                               const void *delta, double *phi, hipStream_t stream,
                                mg_stats *stats) {
     g_err.clear();
     mg_status rc = check_opts(opts);
@@ -1378,7 +1393,7 @@ mg_status mg_solve_dgp_noalloc(const mg_opts *opts, const mg_dgp_params *par,
     return forward_solve<OP_DGP>(opts, M, delta, phi, ws, NOALLOC_BYTES, stream, stats, true);
 }
 
-mg_status mg_solve_dgp_newton(const mg_opts *opts, const mg_dgp_params *par, const double *delta,
+mg_status mg_solve_dgp_newton(const mg_opts *opts, const mg_dgp_params *par, const void *delta,
                               double *phi, void *ws, size_t ws_bytes, hipStream_t stream,
                               mg_stats *stats) {
     mg_status rc = common_checks(opts, delta, phi, ws, stats);
@@ -1389,7 +1404,7 @@ mg_status mg_solve_dgp_newton(const mg_opts *opts, const mg_dgp_params *par, con
     return forward_solve<OP_NEWTON>(opts, M, delta, phi, ws, ws_bytes, stream, stats);
 }
 
-mg_status mg_solve_kmouflage(const mg_opts *opts, const mg_kmo_params *par, const double *delta,
+mg_status mg_solve_kmouflage(const mg_opts *opts, const mg_kmo_params *par, const void *delta,
                              double *phi, void *ws, size_t ws_bytes, hipStream_t stream,
                              mg_stats *stats) {
     mg_status rc = common_checks(opts, delta, phi, ws, stats);
@@ -1399,7 +1414,7 @@ mg_status mg_solve_kmouflage(const mg_opts *opts, const mg_kmo_params *par, cons
     return forward_solve<OP_KMO>(opts, M, delta, phi, ws, ws_bytes, stream, stats);
 }
 
-mg_status mg_solve_poisson(const mg_opts *opts, const mg_poisson_params *par, const double *delta,
+mg_status mg_solve_poisson(const mg_opts *opts, const mg_poisson_params *par, const void *delta,
                            double *phi, void *ws, size_t ws_bytes, hipStream_t stream,
                            mg_stats *stats) {
     mg_status rc = common_checks(opts, delta, phi, ws, stats);
@@ -1411,7 +1426,7 @@ mg_status mg_solve_poisson(const mg_opts *opts, const mg_poisson_params *par, co
 }
 
 mg_status mg_solve_adjoint(const mg_opts *opts, int model, const void *params,
-                           const double *delta, const double *phi, const double *w,
+                           const void *delta, const double *phi, const double *w,
                            double *grad_delta, double *mu, void *ws, size_t ws_bytes,
                            hipStream_t stream, mg_stats *stats) {
     mg_status rc = common_checks(opts, delta, phi, ws, stats);

@@ -386,7 +386,9 @@ mg_status mg_pm_step(const mg_pm_params *par, float *pos, float *mom, double *ph
     T.mark(2);
     // scalar field, eq:dgp_eom_code
     mg_dgp_params dp{par->a, par->omega_m, par->h0rc};
-    rc = mg_solve_dgp(&par->mg, &dp, delta_out, phi, solver_ws, solver_bytes, stream, stats);
+    mg_opts so = par->mg;
+    so.delta_fp32 = 0;   // the step's own FP64 density
+    rc = mg_solve_dgp(&so, &dp, delta_out, phi, solver_ws, solver_bytes, stream, stats);
     if (rc < 0) return rc;
     T.mark(3);
     // leapfrog: kick with H0/adot = 1/(a E(a)) at a, drift with
@@ -452,7 +454,9 @@ mg_status mg_pm_step_kmouflage(const mg_pm_kmo_params *par, float *pos, float *m
     if (rc != MG_OK) return rc;
     T.mark(2);
     // scalar field, eq:kmf_eqn_codeunit_final
-    rc = mg_solve_kmouflage(&par->mg, &K, delta_out, phi, solver_ws, solver_bytes, stream, stats);
+    mg_opts so = par->mg;
+    so.delta_fp32 = 0;   // the step's own FP64 density
+    rc = mg_solve_kmouflage(&so, &K, delta_out, phi, solver_ws, solver_bytes, stream, stats);
     if (rc < 0) return rc;
     T.mark(3);
     // eq:force_Kmo1/2: kick with H0/adot = 1/(a E(a)) and the velocity term

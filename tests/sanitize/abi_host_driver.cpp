@@ -162,6 +162,20 @@ int main() {
     CHECK(mg_pm_step_kmouflage(&kpm, fp, fp, fake, fake, fake, ws_aligned, 1ull << 40, nullptr,
                                &st) == MG_ERR_ARG);
 
+    // FFT Poisson solve: size, aliasing, alignment and workspace checks
+    double *fake2 = fake + 2;
+    CHECK(mg_fft_poisson_workspace_bytes(48) == 0);
+    CHECK(mg_fft_poisson_workspace_bytes(64) >= 32 * 16);
+    CHECK(mg_fft_poisson(48, 1.0, fake, fake2, ws_aligned, 1 << 20, nullptr) == MG_ERR_ARG);
+    CHECK(mg_fft_poisson(64, 1.0, fake, fake, ws_aligned, 1 << 20, nullptr) == MG_ERR_ARG);
+    CHECK(mg_fft_poisson(64, 1.0, fake, fake + 1, ws_aligned, 1 << 20, nullptr) == MG_ERR_ARG);
+    CHECK(mg_fft_poisson(64, 1.0, fake, fake2, ws_aligned, 16, nullptr) == MG_ERR_WORKSPACE);
+
+    // the density-precision flag
+    mg_opts of = opts(32);
+    of.delta_fp32 = 3;
+    CHECK(mg_solve_dgp(&of, &dp, fake, fake, ws_aligned, 1ull << 40, nullptr, &st) == MG_ERR_ARG);
+
     for (int c = -6; c <= 3; ++c) CHECK(mg_status_string((mg_status)c) != nullptr);
     if (failures) {
         std::fprintf(stderr, "%d check(s) failed\n", failures);

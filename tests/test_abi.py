@@ -305,3 +305,13 @@ def test_fft_poisson_requires_16_byte_alignment(L):
     d, e, w = C.c_void_p(0x1008), C.c_void_p(0x2000), C.c_void_p(0x3000)
     assert L.mg_fft_poisson(64, 1.0, d, e, w, 1 << 20, None) == mg.MG_ERR_ARG
     assert b"16-byte" in L.mg_last_error()
+
+
+def test_delta_precision_flag_validated(L):
+    d = C.c_void_p(0x1000)
+    st = mg.Stats()
+    o = mg.make_opts(32)
+    o.delta_fp32 = 2
+    assert L.mg_solve_dgp(C.byref(o), C.byref(mg.dgp_params()), d, d, d, 1 << 40, None,
+                          C.byref(st)) == mg.MG_ERR_ARG
+    assert b"delta_fp32" in L.mg_last_error()

@@ -492,6 +492,46 @@ def test_pm_step_parity():
     assert dp.max() <= 1e-4
 
 
+# ------------------------------------------------------ FP32 density input
+
+@pytest.mark.parametrize("name,n,precision", [("dgp", 32, mg.MG_FP64), ("dgp", 128, mg.MG_MIXED),
+                                              ("kmo3", 128, mg.MG_FP64),
+                                              ("dgp_h05", 128, mg.MG_MIXED_DC),
+                                              ("poisson", 64, mg.MG_FP32)])
+def test_fp32_density_input_equals_the_widened_fp64_input(name, n, precision):
+    # delta_fp32 = 1: the levels receive the same values as from an FP64
+    # array holding the FP32 numbers, so the solves agree bit for bit
+    par, _ = models(n)[name]
+    d32 = g(field(n, 77)).float()
+    d64 = d32.double()
+    solve = {"dgp": mg.lib().mg_solve_dgp, "dgp_h05": mg.lib().mg_solve_dgp,
+             "kmo3": mg.lib().mg_solve_kmouflage, "poisson": mg.lib().mg_solve_poisson}[name]
+    model = {"dgp": mg.MODEL_DGP, "dgp_h05": mg.MODEL_DGP, "kmo3": mg.MODEL_KMOUFLAGE,
+             "poisson": mg.MODEL_POISSON}[name]
+    out = []
+    for d in (d64, d32):
+        phi, st = mg._solve(solve, par, model, d, None, None, tol=1e-9, max_cycles=12,
+                            precision=precision)
+        out.append((c(phi), st))
+    assert out[0][1]["cycles"] == out[1][1]["cycles"]
+    assert np.array_equal(out[0][0], out[1][0])
+
+
+def test_fp32_density_input_adjoint_and_noalloc():
+    n = 32
+    par = mg.dgp_params(1.0, OM, 1.0)
+    d32 = g(field(n, 78)).float()
+    d64 = d32.double()
+    phi, _ = mg.solve_dgp(d64, tol=1e-12, max_cycles=40)
+    w = g(inputs.gaussian_field(n, 79, lambda k: k ** -2.0))
+    g64, mu64, _ = mg.solve_adjoint(mg.MODEL_DGP, par, d64, phi, w)
+    g32, mu32, _ = mg.solve_adjoint(mg.MODEL_DGP, par, d32, phi, w)
+    assert torch.equal(g64, g32) and torch.equal(mu64, mu32)
+    p64, _ = mg.solve_dgp_noalloc(d64, tol=1e-9)
+    p32, _ = mg.solve_dgp_noalloc(d32, tol=1e-9)
+    assert torch.equal(p64, p32)
+
+
 # ------------------------------------------------------ FFT Poisson solve
 
 @pytest.mark.parametrize("n", [8, 16, 32, 64, 128])

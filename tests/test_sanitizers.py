@@ -16,6 +16,8 @@ import sys
 
 import pytest
 
+from paper_2110_00566_amd import build
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 pytestmark = pytest.mark.slow
 
@@ -56,9 +58,8 @@ def test_library_host_code_under_asan_and_ubsan(tmp_path):
            "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-I" + os.path.join(ROOT, "include"),
-           os.path.join(ROOT, "tests", "sanitize", "abi_host_driver.cpp"),
-           os.path.join(csrc, "mg_api.hip"), os.path.join(csrc, "pm.hip"),
-           os.path.join(csrc, "kmo_background.cpp"), "-o", str(exe)]
+           os.path.join(ROOT, "tests", "sanitize", "abi_host_driver.cpp")] + \
+          [os.path.join(csrc, f) for f in build.SOURCES] + ["-o", str(exe)]
     subprocess.run(cmd, check=True, capture_output=True, timeout=1200)
     r = subprocess.run([str(exe)], env=dict(os.environ, **SAN_ENV), capture_output=True,
                        text=True, timeout=300)
