@@ -322,6 +322,10 @@ def pm_step_1024(mg, dev, pos, steps=2):
             "config": "1024^3 mesh, 512^3 particles, L=1 Gpc/h, a=1, da=0.0063, tol=1e-8"}
 
 
+SECTIONS = ("mixed", "cycle_types", "comparators", "other_solves", "vcycle_512", "pm_steps",
+            "big", "cpu")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -331,7 +335,20 @@ def main():
     ap.add_argument("--no-big", action="store_true", help="skip the 1024^3 V-cycle timing")
     ap.add_argument("--main-only", action="store_true",
                     help="only the FP64 steps and the JSON line's core fields (for counter runs)")
+    ap.add_argument("--sections", default=",".join(SECTIONS),
+                    help="comma-separated sections after the FP64 steps (for profiler runs): "
+                         + ", ".join(SECTIONS))
     args = ap.parse_args()
+    sections = set(x for x in args.sections.split(",") if x)
+    unknown = sections - set(SECTIONS)
+    if unknown:
+        ap.error("unknown sections: %s" % ", ".join(sorted(unknown)))
+    if args.main_only:
+        sections = set()
+    if args.no_big:
+        sections.discard("big")
+    if args.no_cpu:
+        sections.discard("cpu")
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solver runs on a single MI355X "
               "(multi-GPU sharding is not built); use --gpus 1", file=sys.stderr)
@@ -419,15 +436,14 @@ def main():
                      "traffic": traffic, "pass_ms_avg": pass_ms,
                      "algorithmic_bytes_per_launch": PASS_BYTES_PER_CELL * N_MESH ** 3},
     }
-    if args.main_only:
-        print(json.dumps(out), flush=True)
-        return
     # the same step with the two mixed-precision solves, to the same FP64
     # tolerance: "mixed" (MG_MIXED: FP32 cycles to the FP32 floor, then FP64
     # cycles) and "mixed_dc" (MG_MIXED_DC: the same FP32 cycles, then defect
     # correction: FP64 residual, one FP32 correction cycle, FP64 accumulation)
     phi64 = phi.clone()
     for key, prec in (("mixed", mg.MG_MIXED), ("mixed_dc", mg.MG_MIXED_DC)):
+        if "mixed" not in sections:
+            break
         ws_mix = mg.workspace(N_MESH, mg.MODEL_DGP, False, dev, prec)
         opts_mix = mg.make_opts(N_MESH, tol=TOL, max_cycles=60, precision=prec)
 
@@ -461,19 +477,24 @@ def main():
                     "max_rel_diff_phi_vs_fp64": err}
         del ws_mix
         torch.cuda.empty_cache()
-    out["cycle_types"] = cycle_types(mg, L, C, delta, ws, par, phi64)
-    out["comparators"] = comparators(mg, L, C, delta, ws, par, phi64)
-    out["other_solves"] = other_solves(mg, delta, phi64)
+    if "cycle_types" in sections:
+        out["cycle_types"] = cycle_types(mg, L, C, delta, ws, par, phi64)
+    if "comparators" in sections:
+        out["comparators"] = comparators(mg, L, C, delta, ws, par, phi64)
+    if "other_solves" in sections:
+        out["other_solves"] = other_solves(mg, delta, phi64)
     del ws
     torch.cuda.empty_cache()
-    out["vcycle_512"] = vcycle_time(mg, L, C, delta)
-    out["pm_steps"] = pm_steps(mg, pos, dev)
-    if not args.no_big:
+    if "vcycle_512" in sections:
+        out["vcycle_512"] = vcycle_time(mg, L, C, delta)
+    if "pm_steps" in sections:
+        out["pm_steps"] = pm_steps(mg, pos, dev)
+    if "big" in sections:
         pos1024 = torch.from_numpy(inputs.za_particles(512, 1024, 5)).to(dev)
         out["vcycle_1024"] = vcycle_1024(mg, L, C, pos1024)
         out["pm_step_1024"] = pm_step_1024(mg, dev, pos1024)
         del pos1024
-    if not args.no_cpu:
+    if "cpu" in sections:
         out["cpu_baseline"] = cpu_baseline(pos_np)
     print(json.dumps(out), flush=True)
 

@@ -35,6 +35,17 @@ mg_status hip_status(hipStream_t stream, bool sync) {
 }
 
 constexpr int PTPB = 256;
+
+// Work-groups are dealt round-robin over the 8 XCDs, each with its own L2.
+// Launches whose neighbouring blocks share data (the particles of
+// neighbouring blocks gather from the same potential rows; neighbouring CIC
+// tiles share lists and particles) renumber block b so that each XCD takes
+// one contiguous eighth of the blocks (a bijection when the block count is
+// a multiple of 8, else the identity).
+__device__ __forceinline__ size_t xcd_chunk(unsigned b, unsigned nblk) {
+    if (nblk & 7u) return b;
+    return (size_t)(b & 7u) * (nblk >> 3) + (b >> 3);
+}
 constexpr double FIX_SCALE = 4294967296.0;   // 2^32 fixed-point units per particle
 
 __device__ __forceinline__ void cic_weights(const float *p, double f[3], int i0[3]) {
@@ -86,6 +97,71 @@ __global__ __launch_bounds__(PTPB) void k_cic_link(const float *__restrict__ pos
     next[t] = atomicExch(head + c, t);
 }
 
+// Block-wide exclusive prefix sum of v over the PTPB threads (every thread
+// calls it); *total receives the sum.
+__device__ __forceinline__ int block_scan(int v, int *total) {
+    __shared__ int wsum[PTPB / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    int base = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < PTPB / 64; ++k) {
+        if (k < w) base += wsum[k];
+        tot += wsum[k];
+    }
+    *total = tot;
+    __syncthreads();
+    return base + x - v;
+}
+
+// Every particle in the NL lists of a block (list l starts at head[cell(l)]),
+// handed to body(p, l) with all lanes busy: the lists are walked once to
+// count them, the counts are scanned, and the (particle, list) pairs go into
+// an LDS queue of KQ entries that all threads then drain; a tile with more
+// than KQ particles takes several rounds (each walks the lists again).  The
+// list, not the particle's position, says where it lies relative to the
+// tile: on a mesh one tile wide the halo list below x = 0 is the tile's own
+// last column.  With about
+// one particle per eight cells, walking the lists directly would run the
+// particle work once per list with most lanes idle.
+constexpr int KQ = 1024;
+
+template <int NL, class Cell, class Body>
+__device__ __forceinline__ void tile_particles(const int *__restrict__ head,
+                                               const int *__restrict__ next, Cell cell,
+                                               int2 *queue, Body body) {
+    constexpr int NR = (NL + PTPB - 1) / PTPB;
+    int hd[NR], cnt = 0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int l = threadIdx.x + r * PTPB;
+        hd[r] = l < NL ? head[cell(l)] : -1;
+    }
+#pragma unroll 1
+    for (int r = 0; r < NR; ++r)
+        for (int p = hd[r]; p >= 0; p = next[p]) ++cnt;
+    int total;
+    const int off = block_scan(cnt, &total);
+    for (int base = 0; base < total; base += KQ) {
+        int v = off;
+#pragma unroll 1
+        for (int r = 0; r < NR && v < base + KQ; ++r)
+            for (int p = hd[r]; p >= 0 && v < base + KQ; p = next[p], ++v)
+                if (v >= base) queue[v - base] = make_int2(p, threadIdx.x + r * PTPB);
+        __syncthreads();
+        const int m = total - base < KQ ? total - base : KQ;
+        for (int e = threadIdx.x; e < m; e += PTPB) body(queue[e].x, queue[e].y);
+        __syncthreads();
+    }
+}
+
 // A block owns a tile of CGX x CGY x CGZ cells and walks, once, the lists
 // of every corner cell whose particles reach the tile (the tile and one cell
 // below it in each axis), adding the fixed-point weights that land inside
@@ -102,48 +178,39 @@ __global__ __launch_bounds__(PTPB) void k_cic_gather(const float *__restrict__ p
                                                       const int *__restrict__ next, double scale,
                                                       double *__restrict__ delta) {
     __shared__ unsigned long long acc[CG_CELLS];
+    __shared__ int2 queue[KQ];
     const int nm1 = (1 << logn) - 1;
     const int ntx = (1 << logn) / CGX, nty = (1 << logn) / CGY;
-    const int bx = blockIdx.x % ntx, by = (blockIdx.x / ntx) % nty, bz = blockIdx.x / (ntx * nty);
+    const int blk = (int)xcd_chunk(blockIdx.x, gridDim.x);
+    const int bx = blk % ntx, by = (blk / ntx) % nty, bz = blk / (ntx * nty);
     const int x0 = bx * CGX, y0 = by * CGY, z0 = bz * CGZ;
     for (int q = threadIdx.x; q < CG_CELLS; q += PTPB) acc[q] = 0ull;
-    __syncthreads();
-    // the heads of a thread's lists are loaded together, then walked
-    constexpr int NR = (CG_LISTS + PTPB - 1) / PTPB;
-    int hd[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const int q = threadIdx.x + r * PTPB;
-        hd[r] = -1;
-        if (q < CG_LISTS) {
-            const int lx = q % (CGX + 1) - 1, ly = (q / (CGX + 1)) % (CGY + 1) - 1,
-                      lz = q / ((CGX + 1) * (CGY + 1)) - 1;
-            const size_t L = ((size_t)((z0 + lz) & nm1) << (2 * logn)) +
-                             ((size_t)((y0 + ly) & nm1) << logn) + (size_t)((x0 + lx) & nm1);
-            hd[r] = head[L];
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const int q = threadIdx.x + r * PTPB;
+    // lists of the corner cells whose clouds reach the tile: the tile and
+    // one cell below it in each axis
+    auto cell = [&](int q) {
         const int lx = q % (CGX + 1) - 1, ly = (q / (CGX + 1)) % (CGY + 1) - 1,
-                  lz = q / ((CGX + 1) * (CGY + 1)) - 1;   // corner in tile coordinates
-        for (int p = hd[r]; p >= 0; p = next[p]) {
-            double f[3];
-            int i0[3];
-            cic_weights(pos + 3 * (size_t)p, f, i0);
+                  lz = q / ((CGX + 1) * (CGY + 1)) - 1;
+        return ((size_t)((z0 + lz) & nm1) << (2 * logn)) + ((size_t)((y0 + ly) & nm1) << logn) +
+               (size_t)((x0 + lx) & nm1);
+    };
+    auto deposit = [&](int p, int q) {
+        double f[3];
+        int i0[3];
+        cic_weights(pos + 3 * (size_t)p, f, i0);
+        // the list's corner cell in tile coordinates (-1 .. CG-1)
+        const int lx = q % (CGX + 1) - 1, ly = (q / (CGX + 1)) % (CGY + 1) - 1,
+                  lz = q / ((CGX + 1) * (CGY + 1)) - 1;
 #pragma unroll
-            for (int o = 0; o < 8; ++o) {
-                const int a = o & 1, b = (o >> 1) & 1, c = o >> 2;
-                const int tx = lx + a, ty = ly + b, tz = lz + c;
-                if (tx < 0 || tx >= CGX || ty < 0 || ty >= CGY || tz < 0 || tz >= CGZ) continue;
-                const double w =
-                    ((a ? f[0] : 1.0 - f[0]) * (b ? f[1] : 1.0 - f[1])) * (c ? f[2] : 1.0 - f[2]);
-                atomicAdd(acc + (tz * CGY + ty) * CGX + tx, __double2ull_rn(w * FIX_SCALE));
-            }
+        for (int o = 0; o < 8; ++o) {
+            const int a = o & 1, b = (o >> 1) & 1, c = o >> 2;
+            const int tx = lx + a, ty = ly + b, tz = lz + c;
+            if (tx < 0 || tx >= CGX || ty < 0 || ty >= CGY || tz < 0 || tz >= CGZ) continue;
+            const double w =
+                ((a ? f[0] : 1.0 - f[0]) * (b ? f[1] : 1.0 - f[1])) * (c ? f[2] : 1.0 - f[2]);
+            atomicAdd(acc + (tz * CGY + ty) * CGX + tx, __double2ull_rn(w * FIX_SCALE));
         }
-    }
-    __syncthreads();
+    };
+    tile_particles<CG_LISTS>(head, next, cell, queue, deposit);
     for (int q = threadIdx.x; q < CG_CELLS; q += PTPB) {
         const int tx = q % CGX, ty = (q / CGX) % CGY, tz = q / (CGX * CGY);
         const size_t t = ((size_t)(z0 + tz) << (2 * logn)) + ((size_t)(y0 + ty) << logn) + (x0 + tx);
@@ -183,30 +250,20 @@ __global__ __launch_bounds__(PTPB) void k_total_potential(const double *__restri
 // g = -grad(psi) by 3-point differences at the 8 CIC cells, interpolated
 // with the CIC weights; p = damp p + g kick; x += p drift (periodic).
 // nDGP: damp = 1; Kmouflage: damp = 1 - beta (d phibar/da) da (the velocity
-// term of eq:force_Kmo2).
-__global__ __launch_bounds__(PTPB) void k_kick_drift(float *__restrict__ pos,
-                                                      float *__restrict__ mom, size_t np, int logn,
-                                                      const double *__restrict__ psi_mesh,
-                                                      double damp, double kick, double drift) {
-    const size_t t = (size_t)blockIdx.x * PTPB + threadIdx.x;
-    if (t >= np) return;
-    const int n = 1 << logn, nm1 = n - 1;
-    double f[3];
-    int i0[3];
-    cic_weights(pos + 3 * t, f, i0);
+// term of eq:force_Kmo2).  psi(i, j, k): the potential at corner + (i, j, k),
+// i, j, k in -1 .. 2.
+template <typename PSI>
+__device__ __forceinline__ void kick_particle(float *__restrict__ pos, float *__restrict__ mom,
+                                              size_t t, int n, const double f[3], PSI psi,
+                                              double damp, double kick, double drift) {
     double g[3] = {0.0, 0.0, 0.0};
-    auto psi = [&](int i, int j, int k) {
-        const size_t idx = ((size_t)(k & nm1) << (2 * logn)) + ((size_t)(j & nm1) << logn) + (i & nm1);
-        return psi_mesh[idx];
-    };
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int a = q & 1, b = (q >> 1) & 1, c = q >> 2;
         const double w = ((a ? f[0] : 1.0 - f[0]) * (b ? f[1] : 1.0 - f[1])) * (c ? f[2] : 1.0 - f[2]);
-        const int i = i0[0] + a, j = i0[1] + b, k = i0[2] + c;
-        g[0] -= w * (psi(i + 1, j, k) - psi(i - 1, j, k)) * 0.5;
-        g[1] -= w * (psi(i, j + 1, k) - psi(i, j - 1, k)) * 0.5;
-        g[2] -= w * (psi(i, j, k + 1) - psi(i, j, k - 1)) * 0.5;
+        g[0] -= w * (psi(a + 1, b, c) - psi(a - 1, b, c)) * 0.5;
+        g[1] -= w * (psi(a, b + 1, c) - psi(a, b - 1, c)) * 0.5;
+        g[2] -= w * (psi(a, b, c + 1) - psi(a, b, c - 1)) * 0.5;
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -220,6 +277,27 @@ __global__ __launch_bounds__(PTPB) void k_kick_drift(float *__restrict__ pos,
     }
 }
 
+// One thread per particle.  (A variant that staged the potential of a CIC
+// tile in LDS and walked the deposit's particle lists was no faster: about
+// 21 against 20 ms for 512^3 particles on a 1024^3 mesh.)
+__global__ __launch_bounds__(PTPB) void k_kick_drift(float *__restrict__ pos,
+                                                      float *__restrict__ mom, size_t np, int logn,
+                                                      const double *__restrict__ psi_mesh,
+                                                      double damp, double kick, double drift) {
+    const size_t t = xcd_chunk(blockIdx.x, gridDim.x) * PTPB + threadIdx.x;
+    if (t >= np) return;
+    const int n = 1 << logn, nm1 = n - 1;
+    double f[3];
+    int i0[3];
+    cic_weights(pos + 3 * t, f, i0);
+    auto psi = [&](int i, int j, int k) {
+        const size_t idx = ((size_t)((i0[2] + k) & nm1) << (2 * logn)) +
+                           ((size_t)((i0[1] + j) & nm1) << logn) + ((i0[0] + i) & nm1);
+        return psi_mesh[idx];
+    };
+    kick_particle(pos, mom, t, n, f, psi, damp, kick, drift);
+}
+
 unsigned nb(size_t threads) { return (unsigned)((threads + PTPB - 1) / PTPB); }
 
 bool pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
@@ -229,14 +307,22 @@ int ilog2(int n) {
     return l;
 }
 
-// counts: workspace of ncell 64-bit words
+// The deposit's gather form (particle lists in the CIC workspace) applies:
+// no more particles than cells, 32-bit particle indices, tiles that fit.
+bool cic_lists(int n_mesh, size_t np) {
+    const size_t ncell = (size_t)n_mesh * n_mesh * n_mesh;
+    return np <= ncell && np < ((size_t)1 << 31) && n_mesh >= CGX;
+}
+
+// counts: workspace of ncell 64-bit words (the gather form keeps its lists
+// there: heads of the ncell cells, then the np links)
 mg_status cic(int n_mesh, int n_part, const float *pos, double *delta, unsigned long long *counts,
               hipStream_t s) {
     const size_t ncell = (size_t)n_mesh * n_mesh * n_mesh;
     const size_t np = (size_t)n_part * n_part * n_part;
     const int logn = ilog2(n_mesh);
     const double scale = (1.0 / FIX_SCALE) * ((double)ncell / (double)np);
-    if (np <= ncell && np < ((size_t)1 << 31) && n_mesh >= CGX) {
+    if (cic_lists(n_mesh, np)) {
         // gather form: heads and links fit in the ncell 64-bit words
         int *head = reinterpret_cast<int *>(counts);
         int *next = head + ncell;
@@ -253,6 +339,18 @@ mg_status cic(int n_mesh, int n_part, const float *pos, double *delta, unsigned 
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Total potential psi = Phi_N + cphi phi (written over the CIC workspace,
+// free again), then kick and drift of every particle.
+void potential_kick_drift(int n, int n_part, float *pos, float *mom, const double *phi_newton,
+                          const double *phi, double cphi, unsigned long long *counts,
+                          double damp, double kick, double drift, hipStream_t stream) {
+    const size_t ncell = (size_t)n * n * n;
+    const size_t np = (size_t)n_part * n_part * n_part;
+    double *psi = reinterpret_cast<double *>(counts);
+    k_total_potential<<<nb(ncell), PTPB, 0, stream>>>(phi_newton, phi, cphi, psi, ncell);
+    k_kick_drift<<<nb(np), PTPB, 0, stream>>>(pos, mom, np, ilog2(n), psi, damp, kick, drift);
+}
 
 // GPU time of the phases of a PM step (CIC, Newtonian potential, scalar
 // field, total potential + kick-drift): HIP events on the step's stream at
@@ -399,11 +497,8 @@ mg_status mg_pm_step(const mg_pm_params *par, float *pos, float *mom, double *ph
     const double Eh = std::sqrt(om / (ah * ah * ah) + 1.0 - om);
     const double kick = par->da / (a * E);
     const double drift = par->da / (ah * ah * ah * Eh);
-    const size_t np = (size_t)par->n_part * par->n_part * par->n_part;
-    // the CIC workspace (ncell 64-bit words) holds the total potential now
-    double *psi = reinterpret_cast<double *>(counts);
-    k_total_potential<<<nb(ncell), PTPB, 0, stream>>>(phi_newton, phi, 0.5, psi, ncell);
-    k_kick_drift<<<nb(np), PTPB, 0, stream>>>(pos, mom, np, ilog2(n), psi, 1.0, kick, drift);
+    potential_kick_drift(n, par->n_part, pos, mom, phi_newton, phi, 0.5, counts, 1.0, kick,
+                         drift, stream);
     T.mark(4);
     const mg_status hs = hip_status(stream, true);
     if (hs != MG_OK) return hs;
@@ -467,10 +562,8 @@ mg_status mg_pm_step_kmouflage(const mg_pm_kmo_params *par, float *pos, float *m
     const double kick = par->da / (a * bg.e_a);
     const double drift = par->da / (ah * ah * ah * bg.e_half);
     const double damp = 1.0 - K.beta * dphibar_da * par->da;
-    const size_t np = (size_t)par->n_part * par->n_part * par->n_part;
-    double *psi = reinterpret_cast<double *>(counts);
-    k_total_potential<<<nb(ncell), PTPB, 0, stream>>>(phi_newton, phi, K.beta * ctil, psi, ncell);
-    k_kick_drift<<<nb(np), PTPB, 0, stream>>>(pos, mom, np, ilog2(n), psi, damp, kick, drift);
+    potential_kick_drift(n, par->n_part, pos, mom, phi_newton, phi, K.beta * ctil, counts, damp,
+                         kick, drift, stream);
     T.mark(4);
     const mg_status hs = hip_status(stream, true);
     if (hs != MG_OK) return hs;

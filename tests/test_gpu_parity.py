@@ -472,8 +472,11 @@ def test_cic_lattice_is_exactly_uniform():
     assert np.abs(c(mg.cic_delta(g(pos), 32))).max() == 0.0
 
 
-def test_pm_step_parity():
-    nm, np_ = 32, 16
+@pytest.mark.parametrize("nm,np_", [(32, 16), (64, 32), (16, 16), (32, 40)])
+def test_pm_step_parity(nm, np_):
+    # (32, 16), (64, 32): deposit from particle lists (a mesh one tile wide
+    # at 32); (16, 16) (mesh below one tile) and (32, 40) (more particles
+    # than cells): scatter deposit
     pos = inputs.za_particles(np_, nm, 2, amplitude=30.0)
     mom = np.zeros_like(pos)
     p_o, m_o, phi_o, delta_o, phin_o = oracle.pm_step(pos, mom, nm, 1.0, 0.0063, tol=1e-10)
