@@ -355,6 +355,10 @@ mg_status mg_pm_step_kmouflage(const mg_pm_kmo_params *par, float *pos, float *m
  * mg_pm_workspace_bytes(n_mesh) bytes. */
 mg_status mg_cic_delta(int n_mesh, int n_part, const float *pos, double *delta, void *ws,
                        size_t ws_bytes, hipStream_t stream);
+/* The same deposit with an FP32 delta (each value the FP64 one rounded once),
+ * for solves with opts.delta_fp32 = 1. */
+mg_status mg_cic_delta_f32(int n_mesh, int n_part, const float *pos, float *delta, void *ws,
+                           size_t ws_bytes, hipStream_t stream);
 
 /* ---- single operations of the solve, for parity tests ------------------
  * Natural-layout device arrays of n^3 FP64; level spacing h; model/params

@@ -156,8 +156,9 @@ def lib():
         L.mg_pm_step_kmouflage.argtypes = [C.POINTER(PmKmoParams), _P, _P, _P, _P, _P, _P,
                                            C.c_size_t, _P, C.POINTER(Stats)]
         L.mg_pm_step_kmouflage.restype = st
-        L.mg_cic_delta.argtypes = [C.c_int, C.c_int, _P, _P, _P, C.c_size_t, _P]
-        L.mg_cic_delta.restype = st
+        for name in ("mg_cic_delta", "mg_cic_delta_f32"):
+            getattr(L, name).argtypes = [C.c_int, C.c_int, _P, _P, _P, C.c_size_t, _P]
+            getattr(L, name).restype = st
         L.mg_op_residual.argtypes = [C.c_int, _P, C.c_int, C.c_double, _P, _P, _P, C.c_double,
                                      _P, _P, C.c_size_t, _P]
         L.mg_op_residual.restype = st
@@ -448,18 +449,22 @@ class DGPSolve(torch.autograd.Function):
         return g, None, None, None, None
 
 
-def cic_delta(pos, n_mesh: int, ws=None):
-    """CIC density contrast (float64 n_mesh^3) of float32 [n_part^3, 3] positions."""
+def cic_delta(pos, n_mesh: int, ws=None, dtype=torch.float64):
+    """CIC density contrast (n_mesh^3, float64 or float32) of float32
+    [n_part^3, 3] positions."""
+    if dtype not in (torch.float64, torch.float32):
+        raise ValueError("dtype must be torch.float64 or torch.float32")
     if not pos.is_cuda or pos.dtype != torch.float32 or pos.dim() != 2 or pos.shape[1] != 3:
         raise ValueError("pos must be a GPU float32 [n_part^3, 3] tensor")
     n_part = round(pos.shape[0] ** (1.0 / 3.0))
     if n_part ** 3 != pos.shape[0]:
         raise ValueError("number of particles must be a cube")
-    delta = torch.empty((n_mesh,) * 3, dtype=torch.float64, device=pos.device)
+    delta = torch.empty((n_mesh,) * 3, dtype=dtype, device=pos.device)
     if ws is None:
         ws = torch.empty(lib().mg_pm_workspace_bytes(n_mesh), dtype=torch.uint8, device=pos.device)
-    _raise(lib().mg_cic_delta(n_mesh, n_part, _ptr(pos.contiguous()), _ptr(delta), _ptr(ws),
-                              ws.numel(), _stream()))
+    fn = lib().mg_cic_delta if dtype == torch.float64 else lib().mg_cic_delta_f32
+    _raise(fn(n_mesh, n_part, _ptr(pos.contiguous()), _ptr(delta), _ptr(ws), ws.numel(),
+              _stream()))
     return delta
 
 

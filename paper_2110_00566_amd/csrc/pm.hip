@@ -173,10 +173,11 @@ constexpr int CGX = 32, CGY = 8, CGZ = 8;
 constexpr int CG_CELLS = CGX * CGY * CGZ;                      // 2048
 constexpr int CG_LISTS = (CGX + 1) * (CGY + 1) * (CGZ + 1);    // 2673
 
+template <typename T>
 __global__ __launch_bounds__(PTPB) void k_cic_gather(const float *__restrict__ pos, int logn,
                                                       const int *__restrict__ head,
                                                       const int *__restrict__ next, double scale,
-                                                      double *__restrict__ delta) {
+                                                      T *__restrict__ delta) {
     __shared__ unsigned long long acc[CG_CELLS];
     __shared__ int2 queue[KQ];
     const int nm1 = (1 << logn) - 1;
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(PTPB) void k_cic_gather(const float *__restrict__ p
     for (int q = threadIdx.x; q < CG_CELLS; q += PTPB) {
         const int tx = q % CGX, ty = (q / CGX) % CGY, tz = q / (CGX * CGY);
         const size_t t = ((size_t)(z0 + tz) << (2 * logn)) + ((size_t)(y0 + ty) << logn) + (x0 + tx);
-        delta[t] = (double)acc[q] * scale - 1.0;
+        delta[t] = (T)((double)acc[q] * scale - 1.0);
     }
 }
 
@@ -223,12 +224,12 @@ __global__ void k_fill_i32(int *a, size_t n, int v) {
     if (t < n) a[t] = v;
 }
 
+template <typename T>
 __global__ __launch_bounds__(PTPB) void k_counts_to_delta(const unsigned long long *counts,
-                                                           size_t ncell, double scale,
-                                                           double *delta) {
+                                                           size_t ncell, double scale, T *delta) {
     const size_t t = (size_t)blockIdx.x * PTPB + threadIdx.x;
     if (t >= ncell) return;
-    delta[t] = (double)counts[t] * scale - 1.0;
+    delta[t] = (T)((double)counts[t] * scale - 1.0);
 }
 
 __global__ void k_zero_u64(unsigned long long *a, size_t n) {
@@ -315,8 +316,10 @@ bool cic_lists(int n_mesh, size_t np) {
 }
 
 // counts: workspace of ncell 64-bit words (the gather form keeps its lists
-// there: heads of the ncell cells, then the np links)
-mg_status cic(int n_mesh, int n_part, const float *pos, double *delta, unsigned long long *counts,
+// there: heads of the ncell cells, then the np links).  T: FP64 or FP32
+// delta (the FP64 value rounded once).
+template <typename T>
+mg_status cic(int n_mesh, int n_part, const float *pos, T *delta, unsigned long long *counts,
               hipStream_t s) {
     const size_t ncell = (size_t)n_mesh * n_mesh * n_mesh;
     const size_t np = (size_t)n_part * n_part * n_part;
@@ -328,13 +331,13 @@ mg_status cic(int n_mesh, int n_part, const float *pos, double *delta, unsigned 
         int *next = head + ncell;
         k_fill_i32<<<nb(ncell), PTPB, 0, s>>>(head, ncell, -1);
         k_cic_link<<<nb(np), PTPB, 0, s>>>(pos, (int)np, logn, head, next);
-        k_cic_gather<<<(unsigned)(ncell / CG_CELLS), PTPB, 0, s>>>(pos, logn, head, next, scale,
-                                                                  delta);
+        k_cic_gather<T><<<(unsigned)(ncell / CG_CELLS), PTPB, 0, s>>>(pos, logn, head, next,
+                                                                     scale, delta);
         return hip_status(s, false);
     }
     k_zero_u64<<<nb(ncell), PTPB, 0, s>>>(counts, ncell);
     k_cic<<<nb(np), PTPB, 0, s>>>(pos, np, logn, counts);
-    k_counts_to_delta<<<nb(ncell), PTPB, 0, s>>>(counts, ncell, scale, delta);
+    k_counts_to_delta<T><<<nb(ncell), PTPB, 0, s>>>(counts, ncell, scale, delta);
     return hip_status(s, false);
 }
 
@@ -434,8 +437,12 @@ size_t mg_pm_workspace_bytes(int n_mesh) {
            mg_workspace_bytes(n_mesh, MG_FP64, MG_MODEL_DGP, 0) + 256;
 }
 
-mg_status mg_cic_delta(int n_mesh, int n_part, const float *pos, double *delta, void *ws,
-                       size_t ws_bytes, hipStream_t stream) {
+}  // extern "C"
+
+namespace {
+template <typename T>
+mg_status cic_entry(int n_mesh, int n_part, const float *pos, T *delta, void *ws, size_t ws_bytes,
+                    hipStream_t stream) {
     mgglam_internal::set_error("");
     if (!pow2(n_mesh) || n_mesh < 8 || n_mesh > 2048)
         return fail(MG_ERR_ARG, "n_mesh must be a power of two in [8, 2048]");
@@ -447,6 +454,19 @@ mg_status mg_cic_delta(int n_mesh, int n_part, const float *pos, double *delta, 
     mg_status rc = cic(n_mesh, n_part, pos, delta, (unsigned long long *)ws, stream);
     if (rc != MG_OK) return rc;
     return hip_status(stream, true);
+}
+}  // namespace
+
+extern "C" {
+
+mg_status mg_cic_delta(int n_mesh, int n_part, const float *pos, double *delta, void *ws,
+                       size_t ws_bytes, hipStream_t stream) {
+    return cic_entry(n_mesh, n_part, pos, delta, ws, ws_bytes, stream);
+}
+
+mg_status mg_cic_delta_f32(int n_mesh, int n_part, const float *pos, float *delta, void *ws,
+                           size_t ws_bytes, hipStream_t stream) {
+    return cic_entry(n_mesh, n_part, pos, delta, ws, ws_bytes, stream);
 }
 
 mg_status mg_pm_step(const mg_pm_params *par, float *pos, float *mom, double *phi,

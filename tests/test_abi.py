@@ -114,6 +114,8 @@ def test_null_pointers_and_workspace(L):
     assert b"aligned" in L.mg_last_error()
     assert L.mg_cic_delta(32, 16, d, d, odd, 1 << 40, None) == mg.MG_ERR_WORKSPACE
     assert b"aligned" in L.mg_last_error()
+    assert L.mg_cic_delta_f32(32, 16, d, d, odd, 1 << 40, None) == mg.MG_ERR_WORKSPACE
+    assert L.mg_cic_delta_f32(24, 16, d, d, d, 1 << 40, None) == mg.MG_ERR_ARG
 
 
 def test_adjoint_accepts_v_cycles_only(L):

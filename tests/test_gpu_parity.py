@@ -467,6 +467,14 @@ def test_cic_parity(np_, nm):
     assert abs(out.mean()) <= 1e-9
 
 
+@pytest.mark.parametrize("np_,nm", [(16, 32), (8, 16)])
+def test_cic_fp32_output_is_the_rounded_fp64_one(np_, nm):
+    pos = g(inputs.za_particles(np_, nm, 3, amplitude=30.0))
+    d64 = mg.cic_delta(pos, nm)
+    d32 = mg.cic_delta(pos, nm, dtype=torch.float32)
+    assert d32.dtype == torch.float32 and torch.equal(d32, d64.float())
+
+
 def test_cic_lattice_is_exactly_uniform():
     pos = inputs.lattice_positions(16, 32).astype(np.float32)
     assert np.abs(c(mg.cic_delta(g(pos), 32))).max() == 0.0
