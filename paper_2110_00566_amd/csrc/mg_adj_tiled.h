@@ -41,9 +41,12 @@ enum { ADJ_PASS = 0, ADJ_RESID = 1, ADJ_CSRC = 2 };
 struct AdjLevel {
     const double *u0, *u1;       // mu (CSRC: R mu of the finer level)
     const double *c[9][2];       // coefficient arrays (minus faces alias plus for nDGP/Poisson)
+    const double *lin[2];        // RC: linearisation point phi of the level
+    const double *kp[2];         // RC: dK/dSigma at every cell
     const double *f0, *f1;       // right-hand side, never null (CSRC: R r, overwritten by S)
     int n, logn, lognh;
     double h2;
+    double c3h4, c8h4;           // 1/(3 h^4), 1/(8 h^4)
 };
 
 // Staging geometry of one FP64 plane (tile plus halo, 66 x 10 values): 320
@@ -174,8 +177,22 @@ __device__ __forceinline__ void block_sum2_nt(double a, double b, double *partia
 // SYM: the x+ and x- (y, z) face coefficients are one array (nDGP, Poisson);
 // COEF: the model has a non-Laplacian term (not Poisson).  REDUCE: block sums
 // into partials[2 blk ..] (PASS: the new values; RESID: r and r^2).
-template <int NT, bool SYM, bool COEF, int MODE, bool REDUCE>
-__global__ __launch_bounds__(NT) void k_adj_tiled(AdjLevel L, int c, double *out, double *out2,
+//
+// RC (nDGP): the products are rebuilt from the linearisation point instead
+// of read from coefficient arrays.  With F' = dK/dSigma of a cell (the one
+// array kept per level), the face coefficient of a face-colour cell is
+// 2 F' (2A_x - A_y - A_z)/(3h^4) and the edge coefficient of a target-colour
+// cell 2 F' N_xy/(8h^4) (y, z alike, as in k_adj_coefs); both read only the
+// target colour's phi (the face neighbours of a face-colour cell and the
+// edge neighbours of a target-colour cell have the target colour).  phi_c is
+// staged on the tile with a 2-cell halo (68 x 12 values per plane) in a ring
+// of 4 planes, two planes ahead of the products, so a plane's products see
+// phi at k - 1, k and k + 1.  Per cell and pass: mu of both colours, phi of
+// the target colour, F' of both colours, f and the new value (28 B against
+// 40 B with the stored coefficients).
+template <int NT, bool SYM, bool COEF, int MODE, bool REDUCE, bool RC = false>
+__global__ __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu(RC ? 4 : 1))) void k_adj_tiled(AdjLevel L, int c, double *out, double *out2,
                                                    const double *fptr,
                                                    double fscale, double *ru0, double *ru1,
                                                    double *rd0, double *rd1, double *partials,
@@ -187,6 +204,10 @@ __global__ __launch_bounds__(NT) void k_adj_tiled(AdjLevel L, int c, double *out
     __shared__ __align__(16) double sF[COEF ? NF : 1][TSLOT];
     __shared__ __align__(16) double sE[COEF ? 3 : 1][TSLOT];
     __shared__ double sX[MODE == ADJ_RESID ? 2 * RPT : 1][MODE == ADJ_RESID ? NT : 1];
+    constexpr int PW = TX + 4, PH = TY + 4;        // RC: phi_c plane with a 2-cell halo
+    constexpr int PSLOT = PW * PH, PNV = PH * (PW / 2);
+    static_assert(!RC || (SYM && COEF && NT >= PNV), "RC: nDGP, one phi vector per thread");
+    __shared__ __align__(16) double sP[RC ? 4 : 1][RC ? PSLOT : 2];
     const size_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int bx = (int)(blk % G.ntx);
     const int by = (int)((blk / G.ntx) % G.nty);
@@ -207,11 +228,37 @@ __global__ __launch_bounds__(NT) void k_adj_tiled(AdjLevel L, int c, double *out
     for (int h = 0; h < RPT; ++h) coff[h] = cell_off<double>(j0 + ty + W * h, m0 + tx, L.lognh);
 
     // staged raw values of the next plane
-    SReg<NT> rMo, rFx, rFy, rFx2, rFy2, rMc, rE6, rE7, rE8;
+    SReg<NT> rMo, rFx, rFy, rFx2, rFy2, rMc, rE6, rE7, rE8, rKo, rKc;
+    // RC: phi_c of a plane (vector tid of 408: row tid / 34, packed columns
+    // m0 - 2 + 2 (tid % 34) and the next), two planes ahead of the products
+    unsigned pg = 0;
+    int plds = 0;
+    if constexpr (RC) {
+        const int v = tid < PNV ? tid : 0;
+        const int r = v / (PW / 2), i = v - r * (PW / 2);
+        const unsigned jm = (1u << L.logn) - 1, mm = (1u << L.lognh) - 1;
+        pg = ((((unsigned)(j0 - 2 + r) & jm) << L.lognh) + ((unsigned)(m0 - 2 + 2 * i) & mm)) * 8u;
+        plds = r * PW + 2 * i;
+    }
+    const double *Pc = L.lin[c];
+    double2 rP = make_double2(0.0, 0.0);
+    auto pfetch = [&](int k) {
+        if (RC && tid < PNV)
+            rP = *reinterpret_cast<const double2 *>(
+                reinterpret_cast<const char *>(Pc) + plane_off<double>(k, L.logn, L.lognh) + pg);
+    };
+    auto pstore = [&](int k) {
+        if (RC && tid < PNV) *reinterpret_cast<double2 *>(sP[(k + 4) & 3] + plds) = rP;
+    };
     auto fetch = [&](int k) {
         const size_t pl = plane_off<double>(k, L.logn, L.lognh);
         rMo.load(Mo, pl, g, tid);
-        if constexpr (COEF) {
+        if constexpr (RC) {
+            rMc.load(Mc, pl, g, tid);
+            rKo.load(L.kp[o], pl, g, tid);
+            rKc.load(L.kp[c], pl, g, tid);
+            pfetch(k + 2);
+        } else if constexpr (COEF) {
             rFx.load(L.c[0][o], pl, g, tid);
             rFy.load(L.c[2][o], pl, g, tid);
             if constexpr (!SYM) {
@@ -224,9 +271,52 @@ __global__ __launch_bounds__(NT) void k_adj_tiled(AdjLevel L, int c, double *out
             rE8.load(L.c[8][c], pl, g, tid);
         }
     };
-    auto store = [&]() {
+    // RC: face sums of the face-colour cell and cross differences of the
+    // target-colour cell at staged position (r, ci) of plane kp (r: row
+    // j0 - 1 + r, ci: packed column m0 - 1 + ci) from the phi_c ring
+    auto faces_at = [&](int r, int ci, int kp, double &ax, double &ay, double &az) {
+        const int po = (o + j0 - 1 + r + kp) & 1;
+        const double *P0 = sP[(kp + 4) & 3], *Pm = sP[(kp + 3) & 3], *Pp = sP[(kp + 5) & 3];
+        const int r0 = (r + 1) * PW, rp = (r + 2) * PW, rm = r * PW, x0 = ci + 1;
+        ax = P0[r0 + x0 + po] + P0[r0 + ci + po];
+        ay = P0[rp + x0] + P0[rm + x0];
+        az = Pp[r0 + x0] + Pm[r0 + x0];
+    };
+    auto prod = [&](int r, int ci, int kp, int l, double mo, double ko, double mc, double kc) {
+        double ax, ay, az;
+        faces_at(r, ci, kp, ax, ay, az);
+        const double w = 2.0 * ko * L.c3h4;
+        sF[0][1 + l] = w * (2.0 * ax - ay - az) * mo;
+        sF[1][1 + l] = w * (2.0 * ay - ax - az) * mo;
+        const int pc = (c + j0 - 1 + r + kp) & 1;
+        const double *P0 = sP[(kp + 4) & 3], *Pm = sP[(kp + 3) & 3], *Pp = sP[(kp + 5) & 3];
+        const int r0 = (r + 1) * PW, rp = (r + 2) * PW, rm = r * PW, x0 = ci + 1;
+        const int xp = x0 + pc, xm = ci + pc;
+        const double nxy = (P0[rp + xp] + P0[rm + xm]) - (P0[rm + xp] + P0[rp + xm]);
+        const double nxz = (Pp[r0 + xp] + Pm[r0 + xm]) - (Pm[r0 + xp] + Pp[r0 + xm]);
+        const double nyz = (Pp[rp + x0] + Pm[rm + x0]) - (Pm[rp + x0] + Pp[rm + x0]);
+        const double e = 2.0 * kc * L.c8h4;
+        sE[0][1 + l] = e * nxy * mc;
+        sE[COEF ? 1 : 0][1 + l] = e * nxz * mc;
+        sE[COEF ? 2 : 0][1 + l] = e * nyz * mc;
+    };
+    auto store = [&](int kp) {
         rMo.store(sM + 1, g, tid);
-        if constexpr (COEF) {
+        if constexpr (RC) {
+            pstore(kp + 2);
+            using SG = SGeom<NT>;
+            if (tid < SG::NV) {
+                const int r = tid >> 5, ci = 1 + 2 * (tid & 31);
+                prod(r, ci, kp, g.l0, rMo.a0.x, rKo.a0.x, rMc.a0.x, rKc.a0.x);
+                // residual and coarse source: one position at a time
+                // (interleaved, they spill); the pass is faster interleaved
+                if constexpr (MODE != ADJ_PASS) __builtin_amdgcn_sched_barrier(0);
+                prod(r, ci + 1, kp, g.l0 + 1, rMo.a0.y, rKo.a0.y, rMc.a0.y, rKc.a0.y);
+            } else if (tid < SG::H0 + 2 * TYH) {
+                const int hh = tid - SG::H0, r = hh >> 1, ci = (hh & 1) ? TXH - 1 : 0;
+                prod(r, ci, kp, g.l0, rMo.a0.x, rKo.a0.x, rMc.a0.x, rKc.a0.x);
+            }
+        } else if constexpr (COEF) {
             rFx.store_prod(sF[0] + 1, rMo, g, tid);
             rFy.store_prod(sF[1] + 1, rMo, g, tid);
             if constexpr (!SYM) {
@@ -246,7 +336,9 @@ __global__ __launch_bounds__(NT) void k_adj_tiled(AdjLevel L, int c, double *out
         const size_t pl = plane_off<double>(k, L.logn, L.lognh);
 #pragma unroll
         for (int h = 0; h < RPT; ++h) {
-            if constexpr (COEF) {
+            if constexpr (RC) {
+                z4n[h] = ld(L.kp[o], pl, coff[h]);   // F' of the face-colour cell
+            } else if constexpr (COEF) {
                 z4n[h] = ld(L.c[4][o], pl, coff[h]);
                 z5n[h] = SYM ? z4n[h] : ld(L.c[5][o], pl, coff[h]);
             }
@@ -292,15 +384,28 @@ __global__ __launch_bounds__(NT) void k_adj_tiled(AdjLevel L, int c, double *out
         }
     };
 
+    if constexpr (RC) {   // phi_c planes k0 - 2 .. k0 (the products of k0 - 1 need them)
+        for (int kk = k0 - 2; kk <= k0; ++kk) {
+            pfetch(kk);
+            pstore(kk);
+        }
+    }
     fetch(k0 - 1);
     fetch_cells(k0 - 1);
+    if constexpr (RC) __syncthreads();
     for (int kp = k0 - 1; kp <= k1; ++kp) {
-        store();
+        store(kp);
         double z4[RPT], z5[RPT];
 #pragma unroll
         for (int h = 0; h < RPT; ++h) {
-            z4[h] = z4n[h];
-            z5[h] = z5n[h];
+            if constexpr (RC) {
+                double ax, ay, az;
+                faces_at(ty + W * h + 1, tx + 1, kp, ax, ay, az);
+                z4[h] = 2.0 * z4n[h] * L.c3h4 * (2.0 * az - ax - ay);
+            } else {
+                z4[h] = z4n[h];
+            }
+            z5[h] = SYM ? z4[h] : z5n[h];
             fp[h] = fc[h];
             up[h] = uc[h];
             fc[h] = fn[h];

@@ -104,6 +104,31 @@ __global__ __launch_bounds__(TPB) void k_adj_coefs(Mod M, Lvl L, CoefsW W, doubl
     for (int q = 0; q < 3; ++q) W.c[6 + q][c][tt] = e[q];
 }
 
+// F' = dK/dSigma of the nDGP term at every cell of a level (sign(alpha)/sqrt(D),
+// 0 on the clamped branch), the one per-cell array the tiled adjoint kernels
+// keep: they rebuild the coefficients of k_adj_coefs from it and the staged
+// linearisation point.
+__global__ __launch_bounds__(TPB) void k_adj_kprime(Mod M, Lvl L, double *kp0, double *kp1) {
+    const size_t t = xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
+    const size_t half = (size_t)1 << (3 * L.logn - 1);
+    if (t >= 2 * half) return;
+    const int c = t >= half;
+    const size_t tt = t - (c ? half : 0);
+    const int m = (int)(tt & ((1u << L.lognh) - 1));
+    const int j = (int)((tt >> L.lognh) & (L.n - 1));
+    const int k = (int)(tt >> (L.lognh + L.logn));
+    const double *A = c ? L.u1 : L.u0;
+    const double *B = c ? L.u0 : L.u1;
+    const Nb s = load_nb<double, double>(A, B, c, m, j, k, L.n, L.logn, L.lognh);
+    const double delta = (c ? L.d1 : L.d0)[tt];
+    const double ax = s.xp + s.xm, ay = s.yp + s.ym, az = s.zp + s.zm;
+    const double dxy = ax - ay, dxz = ax - az, dyz = ay - az;
+    const double sig = (dxy * dxy + dxz * dxz + dyz * dyz) * L.c3h4
+                     + (s.nxy * s.nxy + s.nxz * s.nxz + s.nyz * s.nyz) * L.c8h4 + M.s * delta;
+    const double disc = M.alpha * M.alpha + (8.0 / 3.0) * sig;
+    (c ? kp1 : kp0)[tt] = disc > 0.0 ? M.sgn / sqrt(disc) : 0.0;
+}
+
 // grad_delta = (dK/ddelta) mu on the finest level, written in natural layout.
 template <int MODEL>
 __global__ __launch_bounds__(TPB) void k_adj_grad(Mod M, Lvl L, const double *mu0,

@@ -80,6 +80,7 @@ struct HLevel {
     R *ru[2] = {nullptr, nullptr};
     double *lin[2] = {nullptr, nullptr};
     double *cf[9][2] = {};
+    double *kp[2] = {nullptr, nullptr};   // nDGP adjoint on tiled levels: dK/dSigma (no cf)
     R *pb[2] = {nullptr, nullptr};   // defect correction (FP32 finest level): background
 };
 
@@ -165,10 +166,12 @@ template <>
 Hier<float> &hier<float>(Ctx &C) { return C.h32; }
 
 // dc_fine: the finest level also holds the right-hand side array and the
-// frozen background of the defect-correction cycles
+// frozen background of the defect-correction cycles.  rc (nDGP adjoint):
+// levels >= 128^3 keep dK/dSigma instead of the coefficient arrays (the
+// tiled adjoint kernels rebuild the coefficients from it).
 template <typename R>
 void layout_hier(Hier<R> &Hh, Carve &cv, int n, bool adjoint, bool sym_coefs,
-                 bool dc_fine = false) {
+                 bool dc_fine = false, bool rc = false) {
     int L = 0;
     for (int m = n; m >= 4; m >>= 1) {
         HLevel<R> &H = Hh.lv[L];
@@ -194,7 +197,12 @@ void layout_hier(Hier<R> &Hh, Carve &cv, int n, bool adjoint, bool sym_coefs,
             H.ru[0] = cv.take<R>(H.half);
             H.ru[1] = cv.take<R>(H.half);
         }
-        if (adjoint) {
+        if (adjoint && rc && m >= 128) {
+            H.lin[0] = cv.take<double>(H.half);
+            H.lin[1] = cv.take<double>(H.half);
+            H.kp[0] = cv.take<double>(H.half);
+            H.kp[1] = cv.take<double>(H.half);
+        } else if (adjoint) {
             H.lin[0] = cv.take<double>(H.half);
             H.lin[1] = cv.take<double>(H.half);
             // nDGP and Poisson: the minus face arrays alias the plus ones
@@ -210,8 +218,9 @@ void layout_hier(Hier<R> &Hh, Carve &cv, int n, bool adjoint, bool sym_coefs,
 
 // Lay the workspace out (base == nullptr: only measure): the FP64 hierarchy
 // unless precision is MG_FP32, the FP32 one unless it is MG_FP64.
-void layout(Ctx &C, Carve &cv, int n, bool adjoint, int precision, bool sym_coefs = false) {
-    if (precision != MG_FP32) layout_hier(C.h64, cv, n, adjoint, sym_coefs);
+void layout(Ctx &C, Carve &cv, int n, bool adjoint, int precision, bool sym_coefs = false,
+            bool rc = false) {
+    if (precision != MG_FP32) layout_hier(C.h64, cv, n, adjoint, sym_coefs, false, rc);
     if (precision != MG_FP64)
         layout_hier(C.h32, cv, n, false, false, precision == MG_MIXED_DC);
     C.npartials = std::max<size_t>((size_t)n * n * n / TPB + 1, 1024);
@@ -247,7 +256,7 @@ LvlT<R> view(const HLevel<R> &H, bool with_f) {
 // arrays instead of 9 and an adjoint pass reads 3 face arrays instead of 6.
 template <typename R>
 void alias_face_coefs(HLevel<R> &H, bool symmetric) {
-    if (!symmetric) return;
+    if (!symmetric || H.kp[0]) return;
     for (int q = 1; q < 6; q += 2)
         for (int c = 0; c < 2; ++c) H.cf[q][c] = H.cf[q - 1][c];
 }
@@ -346,12 +355,19 @@ AdjLevel adj_level(const HLevel<double> &H, const double *u0, const double *u1) 
     A.u1 = u1;
     for (int q = 0; q < 9; ++q)
         for (int c = 0; c < 2; ++c) A.c[q][c] = H.cf[q][c];
+    for (int c = 0; c < 2; ++c) {
+        A.lin[c] = H.lin[c];
+        A.kp[c] = H.kp[c];
+    }
     A.f0 = H.f[0];
     A.f1 = H.f[1];
     A.n = H.n;
     A.logn = H.logn;
     A.lognh = H.logn - 1;
     A.h2 = H.h * H.h;
+    const double h4 = A.h2 * A.h2;
+    A.c3h4 = 1.0 / (3.0 * h4);
+    A.c8h4 = 1.0 / (8.0 * h4);
     return A;
 }
 
@@ -378,8 +394,8 @@ unsigned launch_adj_tiled(int model, const AdjLevel &A, int c, double *out, doub
             k_adj_tiled<ADJ_NT, true, false, MODE, REDUCE><<<nb, ADJ_NT, 0, st>>>(
                 A, c, out, out2, fptr, fscale, ru0, ru1, rd0, rd1, partials, G);
             break;
-        default:
-            k_adj_tiled<ADJ_NT, true, true, MODE, REDUCE><<<nb, ADJ_NT, 0, st>>>(
+        default:   // nDGP: coefficients rebuilt from dK/dSigma and phi
+            k_adj_tiled<ADJ_NT, true, true, MODE, REDUCE, true><<<nb, ADJ_NT, 0, st>>>(
                 A, c, out, out2, fptr, fscale, ru0, ru1, rd0, rd1, partials, G);
             break;
     }
@@ -1124,6 +1140,10 @@ void adj_coefficients(Ctx &C, const double *phi) {
         Lvl L = view(H, false);
         L.u0 = H.lin[0];
         L.u1 = H.lin[1];
+        if (H.kp[0]) {   // nDGP, tiled level: dK/dSigma only
+            k_adj_kprime<<<nblocks(2 * H.half), TPB, 0, C.st>>>(C.M, L, H.kp[0], H.kp[1]);
+            continue;
+        }
         CoefsW W;
         for (int q = 0; q < 9; ++q)
             for (int c = 0; c < 2; ++c) W.c[q][c] = H.cf[q][c];
@@ -1139,7 +1159,7 @@ mg_status adjoint_solve(const mg_opts *o, const Mod &M, const void *delta_p, con
     const DeltaIn delta{delta_p, o->delta_fp32 != 0};
     Ctx C;
     Carve cv{static_cast<char *>(ws), 0};
-    layout(C, cv, o->n, true, MG_FP64, MODEL != MODEL_KMO);
+    layout(C, cv, o->n, true, MG_FP64, MODEL != MODEL_KMO, MODEL == MODEL_DGP);
     if (!ws || ws_bytes < cv.off || ((uintptr_t)ws & 255))
         return fail(MG_ERR_WORKSPACE, "workspace too small (need " + std::to_string(cv.off) +
                                           " bytes) or not 256-byte aligned");
@@ -1344,7 +1364,8 @@ size_t mg_workspace_bytes(int n, int precision, int model, int adjoint) {
     if (adjoint && precision != MG_FP64) return 0;
     Ctx C;
     Carve cv{nullptr, 0};
-    layout(C, cv, n, adjoint != 0, precision, model != MG_MODEL_KMOUFLAGE);
+    layout(C, cv, n, adjoint != 0, precision, model != MG_MODEL_KMOUFLAGE,
+           adjoint != 0 && model == MG_MODEL_DGP);
     return cv.off + 256;
 }
 
