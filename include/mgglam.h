@@ -187,15 +187,17 @@ mg_status mg_kmo_background(const mg_kmo_bg_params *par, int n_table, const doub
                             double *hubble, double *hubble_dot, double *phibar,
                             double *dphibar_dtau, mg_kmo_bg_info *info);
 
-/* Linear Poisson model lap(phi) = s * delta (used for the Newtonian
- * potential, eq:GR_poisson_codeunit with s = 1.5 Omega_m / a). */
+/* Linear Poisson model lap(phi) = s * delta (the linearised comparators;
+ * the PM steps take the Newtonian potential from mg_fft_poisson). */
 typedef struct { double s; } mg_poisson_params;
 
 /* Bytes of device workspace needed by a solve on an n^3 mesh.  precision is
  * an mg_precision, model an mg_model; adjoint != 0 sizes mg_solve_adjoint
- * (FP64 only), whose Kmouflage workspace is larger than the nDGP and Poisson
- * one (9 Jacobian coefficient arrays per level instead of 6).  Returns 0 for
- * invalid arguments. */
+ * (FP64 only): per level the linearisation point and the Jacobian's
+ * coefficient arrays (9 for Kmouflage, 6 for Poisson), except that the nDGP
+ * adjoint keeps only dK/dSigma on levels >= 128^3 (about 52 B per finest
+ * cell in all, against 125 for Kmouflage).  Returns 0 for invalid
+ * arguments. */
 size_t mg_workspace_bytes(int n, int precision, int model, int adjoint);
 
 /* Solve the nDGP scalar-field equation eq:dgp_eom_code in the form of
