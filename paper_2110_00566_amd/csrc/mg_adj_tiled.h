@@ -283,11 +283,12 @@ __attribute__((amdgpu_waves_per_eu(RC ? 4 : 1))) void k_adj_tiled(AdjLevel L, in
         az = Pp[r0 + x0] + Pm[r0 + x0];
     };
     auto prod = [&](int r, int ci, int kp, int l, double mo, double ko, double mc, double kc) {
+        if constexpr (!RC) return;
         double ax, ay, az;
         faces_at(r, ci, kp, ax, ay, az);
         const double w = 2.0 * ko * L.c3h4;
         sF[0][1 + l] = w * (2.0 * ax - ay - az) * mo;
-        sF[1][1 + l] = w * (2.0 * ay - ax - az) * mo;
+        sF[COEF ? 1 : 0][1 + l] = w * (2.0 * ay - ax - az) * mo;
         const int pc = (c + j0 - 1 + r + kp) & 1;
         const double *P0 = sP[(kp + 4) & 3], *Pm = sP[(kp + 3) & 3], *Pp = sP[(kp + 5) & 3];
         const int r0 = (r + 1) * PW, rp = (r + 2) * PW, rm = r * PW, x0 = ci + 1;

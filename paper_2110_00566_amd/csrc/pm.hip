@@ -37,11 +37,10 @@ mg_status hip_status(hipStream_t stream, bool sync) {
 constexpr int PTPB = 256;
 
 // Work-groups are dealt round-robin over the 8 XCDs, each with its own L2.
-// Launches whose neighbouring blocks share data (the particles of
-// neighbouring blocks gather from the same potential rows; neighbouring CIC
-// tiles share lists and particles) renumber block b so that each XCD takes
-// one contiguous eighth of the blocks (a bijection when the block count is
-// a multiple of 8, else the identity).
+// The CIC gather, whose neighbouring tiles share lists and particles,
+// renumbers block b so that each XCD takes one contiguous eighth of the
+// blocks (a bijection when the block count is a multiple of 8, else the
+// identity).
 __device__ __forceinline__ size_t xcd_chunk(unsigned b, unsigned nblk) {
     if (nblk & 7u) return b;
     return (size_t)(b & 7u) * (nblk >> 3) + (b >> 3);
@@ -278,14 +277,17 @@ __device__ __forceinline__ void kick_particle(float *__restrict__ pos, float *__
     }
 }
 
-// One thread per particle.  (A variant that staged the potential of a CIC
-// tile in LDS and walked the deposit's particle lists was no faster: about
-// 21 against 20 ms for 512^3 particles on a 1024^3 mesh.)
+// One thread per particle, blocks in launch order.  (For 512^3 particles on
+// a 1024^3 mesh: a variant that staged the potential of a CIC tile in LDS and
+// walked the deposit's particle lists took about 21 against 20 ms; giving
+// each XCD a contiguous eighth of the blocks cut the HBM fetch from 127 to
+// 50 GB but took 22 ms.  The kick is bound by the cache requests of its 48
+// scattered loads per particle.)
 __global__ __launch_bounds__(PTPB) void k_kick_drift(float *__restrict__ pos,
                                                       float *__restrict__ mom, size_t np, int logn,
                                                       const double *__restrict__ psi_mesh,
                                                       double damp, double kick, double drift) {
-    const size_t t = xcd_chunk(blockIdx.x, gridDim.x) * PTPB + threadIdx.x;
+    const size_t t = (size_t)blockIdx.x * PTPB + threadIdx.x;
     if (t >= np) return;
     const int n = 1 << logn, nm1 = n - 1;
     double f[3];
