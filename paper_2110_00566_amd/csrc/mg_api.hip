@@ -647,12 +647,13 @@ struct Solver {
 
     template <int NL>
     void launch_tail(const TailArgs<R> &A, size_t lds) {
-        static bool attr_set = false;   // per instantiation, process-wide
-        if (!attr_set) {
+        // once per instantiation and process (thread-safe); a failure stays
+        // in the HIP error state and is reported with the solve's launches
+        static std::once_flag once;
+        std::call_once(once, [] {
             (void)hipFuncSetAttribute((const void *)k_tail<OP, NL, R>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            attr_set = true;
-        }
+        });
         k_tail<OP, NL, R><<<1, TAIL_THREADS, lds, C.st>>>(C.M, A);
     }
 
