@@ -182,8 +182,12 @@ __device__ __forceinline__ double2 hartley_pair(const double2 *Zl, int k, int n)
 // Geometry of a pass: block = line group g (B = 2 NP consecutive lines) of
 // plane or row q; line b's element k at base + b sb + k sn,
 // base = q qstride + g B sb.  XAXIS: lines along x (sn = 1, sb = n).
+// rows_first (z pass): consecutive blocks take consecutive rows q of one
+// line group, so the blocks in flight read rows that share address
+// translations (every z-line block touches all n planes): 4% on that pass.
 struct PassGeo {
     size_t qstride, sn, sb;
+    int rows_first;
 };
 
 template <int LOGN, int NP, bool XAXIS, bool GREEN>
@@ -196,7 +200,8 @@ __global__ __launch_bounds__(NP * Fft<LOGN>::NR) void k_hartley(const double *sr
     extern __shared__ double2 Z[];
     const int t = threadIdx.x;
     const int groups = n / B;
-    const int g = blockIdx.x % groups, q = blockIdx.x / groups;
+    const int g = geo.rows_first ? (int)(blockIdx.x / n) : (int)(blockIdx.x % groups);
+    const int q = geo.rows_first ? (int)(blockIdx.x % n) : (int)(blockIdx.x / groups);
     const size_t base = (size_t)q * geo.qstride + (size_t)g * B * geo.sb;
     // first stage from HBM.  Along x consecutive threads take consecutive
     // elements of a line; along y and z consecutive line pairs.
@@ -316,7 +321,7 @@ mg_status poisson_passes(const double *delta, double *phi, const double2 *w, dou
     constexpr int NPYZ = pairs_per_block(LOGN, MG_FFT_THREADS_YZ);
     constexpr int NPZ = pairs_per_block(LOGN, MG_FFT_THREADS_Z);
     const size_t nn = (size_t)n * n;
-    const PassGeo GX{nn, 1, (size_t)n}, GY{nn, (size_t)n, 1}, GZ{(size_t)n, nn, 1};
+    const PassGeo GX{nn, 1, (size_t)n, 0}, GY{nn, (size_t)n, 1, 0}, GZ{(size_t)n, nn, 1, 1};
     mg_status rc;
     if ((rc = launch_pass<LOGN, NPX, true, false>(delta, phi, GX, w, 0.0, stream)) != MG_OK) return rc;
     if ((rc = launch_pass<LOGN, NPYZ, false, false>(phi, phi, GY, w, 0.0, stream)) != MG_OK) return rc;
