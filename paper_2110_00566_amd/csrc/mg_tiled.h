@@ -377,49 +377,58 @@ __global__ __launch_bounds__(TPB) void k_resid_restrict_tiled(Mod M, LvlT<R> L, 
         __syncthreads();
         if (k + 2 <= k1) fetch(k + 2);
         if (k + 1 < k1) fetch_cells(k + 1);
-// the four children stay rolled: unrolled, the Kmouflage term needs 250+
-        // registers per lane (1-2 waves per SIMD); rolled it is 4% faster
-#pragma unroll 1
-        for (int b = 0; b < 2; ++b) {
-#pragma unroll 1
-            for (int c = 0; c < 2; ++c) {
-                const int row = 2 * ty + b;
-                const int p = (j0 + row + k + c) & 1;
-                const R *Am = (c ? s1[sm] : s0[sm]) + 1;
-                const R *A0 = (c ? s1[sz] : s0[sz]) + 1;
-                const R *Ap = (c ? s1[sp] : s0[sp]) + 1;
-                const R *Bm = (c ? s0[sm] : s1[sm]) + 1;
-                const R *B0 = (c ? s0[sz] : s1[sz]) + 1;
-                const R *Bp = (c ? s0[sp] : s1[sp]) + 1;
-                const int r = row + 1, q = tx + 1;
-                const double u = (double)A0[r * TXH + q];
-                const double f = (HASF ? (double)fc[2 * b + c] : 0.0) + fs;
-                double d;
-                if constexpr (sizeof(R) == 4 && OP == OP_DGP) {
-                    // FP32 storage: the Laplacian in double, the nDGP term in float
-                    const NbT<float> s = lds_nb<float, R>(Am, A0, Ap, B0, Bm, Bp, r, q, p);
-                    const double faces = ((double)s.xp + (double)s.xm) +
-                                         ((double)s.yp + (double)s.ym) +
-                                         ((double)s.zp + (double)s.zm);
-                    d = (faces - 6.0 * u) * inv_h2 -
-                        (double)model_term<OP, float>(M, L, s, (float)dc[2 * b + c], clamp) - f;
-                } else {
-                    const Nb s = lds_nb<double, R>(Am, A0, Ap, B0, Bm, Bp, r, q, p);
-                    const double faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
-                    d = (faces - 6.0 * u) * inv_h2 -
-                        tiled_term<OP, double>(M, L, s, (double)dc[2 * b + c], faces, u, clamp) -
-                        f;
-                }
-                sd += d;
-                su += u;
-                if (REDUCE) {
-                    acc1 += d;
-                    acc2 += d * d;
-                }
-                if (WG)
-                    *ptr(c ? g1 : g0, plane_off<float>(k, L.logn, L.lognh),
-                         cell_off<float>(j0 + row, m0 + tx, L.lognh)) = (float)(-d);
+        auto child = [&](int b, int c) {
+            const int row = 2 * ty + b;
+            const int p = (j0 + row + k + c) & 1;
+            const R *Am = (c ? s1[sm] : s0[sm]) + 1;
+            const R *A0 = (c ? s1[sz] : s0[sz]) + 1;
+            const R *Ap = (c ? s1[sp] : s0[sp]) + 1;
+            const R *Bm = (c ? s0[sm] : s1[sm]) + 1;
+            const R *B0 = (c ? s0[sz] : s1[sz]) + 1;
+            const R *Bp = (c ? s0[sp] : s1[sp]) + 1;
+            const int r = row + 1, q = tx + 1;
+            const double u = (double)A0[r * TXH + q];
+            const double f = (HASF ? (double)fc[2 * b + c] : 0.0) + fs;
+            double d;
+            if constexpr (sizeof(R) == 4 && OP == OP_DGP) {
+                // FP32 storage: the Laplacian in double, the nDGP term in float
+                const NbT<float> s = lds_nb<float, R>(Am, A0, Ap, B0, Bm, Bp, r, q, p);
+                const double faces = ((double)s.xp + (double)s.xm) +
+                                     ((double)s.yp + (double)s.ym) +
+                                     ((double)s.zp + (double)s.zm);
+                d = (faces - 6.0 * u) * inv_h2 -
+                    (double)model_term<OP, float>(M, L, s, (float)dc[2 * b + c], clamp) - f;
+            } else {
+                const Nb s = lds_nb<double, R>(Am, A0, Ap, B0, Bm, Bp, r, q, p);
+                const double faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
+                d = (faces - 6.0 * u) * inv_h2 -
+                    tiled_term<OP, double>(M, L, s, (double)dc[2 * b + c], faces, u, clamp) - f;
             }
+            sd += d;
+            su += u;
+            if (REDUCE) {
+                acc1 += d;
+                acc2 += d * d;
+            }
+            if (WG)
+                *ptr(c ? g1 : g0, plane_off<float>(k, L.logn, L.lognh),
+                     cell_off<float>(j0 + row, m0 + tx, L.lognh)) = (float)(-d);
+        };
+        if constexpr (sizeof(R) == 4 && OP != OP_KMO) {
+            // FP32 storage (70 registers rolled, 96 unrolled for nDGP): the
+            // four children unrolled
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) child(b, c);
+        } else {
+            // FP64 and Kmouflage: the four children stay rolled (unrolled,
+            // the Kmouflage term needs 200+ registers per lane; rolled the
+            // FP64 kernel is 4% faster)
+#pragma unroll 1
+            for (int b = 0; b < 2; ++b)
+#pragma unroll 1
+                for (int c = 0; c < 2; ++c) child(b, c);
         }
         if (k & 1) {
             const int K = k >> 1, I = m0 + tx, J = (j0 >> 1) + ty;
