@@ -372,12 +372,14 @@ __global__ __launch_bounds__(TPB) void k_resid_restrict_tiled(Mod M, LvlT<R> L, 
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             dc[q] = dn[q];
-            if (HASF) fc[q] = fn[q];
+            fc[q] = HASF ? fn[q] : R(0);
         }
         __syncthreads();
         if (k + 2 <= k1) fetch(k + 2);
         if (k + 1 < k1) fetch_cells(k + 1);
-        auto child = [&](int b, int c) {
+        // dv, fv: delta and f of child (b, c), passed by value so that the
+        // rolled loop indexes no local array (that would put dc, fc in scratch)
+        auto child = [&](int b, int c, R dv, R fv) {
             const int row = 2 * ty + b;
             const int p = (j0 + row + k + c) & 1;
             const R *Am = (c ? s1[sm] : s0[sm]) + 1;
@@ -388,7 +390,7 @@ __global__ __launch_bounds__(TPB) void k_resid_restrict_tiled(Mod M, LvlT<R> L, 
             const R *Bp = (c ? s0[sp] : s1[sp]) + 1;
             const int r = row + 1, q = tx + 1;
             const double u = (double)A0[r * TXH + q];
-            const double f = (HASF ? (double)fc[2 * b + c] : 0.0) + fs;
+            const double f = (HASF ? (double)fv : 0.0) + fs;
             double d;
             if constexpr (sizeof(R) == 4 && OP == OP_DGP) {
                 // FP32 storage: the Laplacian in double, the nDGP term in float
@@ -397,12 +399,12 @@ __global__ __launch_bounds__(TPB) void k_resid_restrict_tiled(Mod M, LvlT<R> L, 
                                      ((double)s.yp + (double)s.ym) +
                                      ((double)s.zp + (double)s.zm);
                 d = (faces - 6.0 * u) * inv_h2 -
-                    (double)model_term<OP, float>(M, L, s, (float)dc[2 * b + c], clamp) - f;
+                    (double)model_term<OP, float>(M, L, s, (float)dv, clamp) - f;
             } else {
                 const Nb s = lds_nb<double, R>(Am, A0, Ap, B0, Bm, Bp, r, q, p);
                 const double faces = (s.xp + s.xm) + (s.yp + s.ym) + (s.zp + s.zm);
                 d = (faces - 6.0 * u) * inv_h2 -
-                    tiled_term<OP, double>(M, L, s, (double)dc[2 * b + c], faces, u, clamp) - f;
+                    tiled_term<OP, double>(M, L, s, (double)dv, faces, u, clamp) - f;
             }
             sd += d;
             su += u;
@@ -414,21 +416,23 @@ __global__ __launch_bounds__(TPB) void k_resid_restrict_tiled(Mod M, LvlT<R> L, 
                 *ptr(c ? g1 : g0, plane_off<float>(k, L.logn, L.lognh),
                      cell_off<float>(j0 + row, m0 + tx, L.lognh)) = (float)(-d);
         };
-        if constexpr (sizeof(R) == 4 && OP != OP_KMO) {
-            // FP32 storage (70 registers rolled, 96 unrolled for nDGP): the
+        if constexpr (sizeof(R) == 4 && OP == OP_DGP) {
+            // FP32 nDGP (70 registers rolled, 96 unrolled, 3% faster): the
             // four children unrolled
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-#pragma unroll
-                for (int c = 0; c < 2; ++c) child(b, c);
+            child(0, 0, dc[0], fc[0]);
+            child(0, 1, dc[1], fc[1]);
+            child(1, 0, dc[2], fc[2]);
+            child(1, 1, dc[3], fc[3]);
         } else {
-            // FP64 and Kmouflage: the four children stay rolled (unrolled,
-            // the Kmouflage term needs 200+ registers per lane; rolled the
-            // FP64 kernel is 4% faster)
+            // the four children stay rolled (unrolled, the Kmouflage term
+            // needs 200+ registers per lane; rolled the FP64 kernel is 4%
+            // faster)
 #pragma unroll 1
-            for (int b = 0; b < 2; ++b)
-#pragma unroll 1
-                for (int c = 0; c < 2; ++c) child(b, c);
+            for (int q = 0; q < 4; ++q) {
+                const R dv = q == 0 ? dc[0] : q == 1 ? dc[1] : q == 2 ? dc[2] : dc[3];
+                const R fv = q == 0 ? fc[0] : q == 1 ? fc[1] : q == 2 ? fc[2] : fc[3];
+                child(q >> 1, q & 1, dv, fv);
+            }
         }
         if (k & 1) {
             const int K = k >> 1, I = m0 + tx, J = (j0 >> 1) + ty;
