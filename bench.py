@@ -326,7 +326,14 @@ SECTIONS = ("mixed", "cycle_types", "comparators", "other_solves", "vcycle_512",
             "big", "cpu")
 
 
+def note(what, t_start):
+    """One progress line on stderr per finished part (the JSON line comes last)."""
+    print("bench.py: %s done, %.1f s" % (what, time.perf_counter() - t_start), file=sys.stderr,
+          flush=True)
+
+
 def main():
+    t_start = time.perf_counter()
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
@@ -397,6 +404,7 @@ def main():
     dt = time.perf_counter() - t0
     prof = step(opts_prof)
     torch.cuda.synchronize()
+    note("FP64 steps", t_start)
 
     cycles = [s.cycles for s in stats]
     assert all(s.status == 0 and s.eps <= TOL for s in stats), [s.status for s in stats]
@@ -477,25 +485,34 @@ def main():
                     "max_rel_diff_phi_vs_fp64": err}
         del ws_mix
         torch.cuda.empty_cache()
+        note(key, t_start)
     if "cycle_types" in sections:
         out["cycle_types"] = cycle_types(mg, L, C, delta, ws, par, phi64)
+        note("cycle_types", t_start)
     if "comparators" in sections:
         out["comparators"] = comparators(mg, L, C, delta, ws, par, phi64)
+        note("comparators", t_start)
     if "other_solves" in sections:
         out["other_solves"] = other_solves(mg, delta, phi64)
+        note("other_solves", t_start)
     del ws
     torch.cuda.empty_cache()
     if "vcycle_512" in sections:
         out["vcycle_512"] = vcycle_time(mg, L, C, delta)
+        note("vcycle_512", t_start)
     if "pm_steps" in sections:
         out["pm_steps"] = pm_steps(mg, pos, dev)
+        note("pm_steps", t_start)
     if "big" in sections:
         pos1024 = torch.from_numpy(inputs.za_particles(512, 1024, 5)).to(dev)
         out["vcycle_1024"] = vcycle_1024(mg, L, C, pos1024)
+        note("vcycle_1024", t_start)
         out["pm_step_1024"] = pm_step_1024(mg, dev, pos1024)
+        note("pm_step_1024", t_start)
         del pos1024
     if "cpu" in sections:
         out["cpu_baseline"] = cpu_baseline(pos_np)
+        note("cpu_baseline", t_start)
     print(json.dumps(out), flush=True)
 
 

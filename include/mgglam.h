@@ -14,7 +14,8 @@
  *  - The caller owns every array and the workspace; the library never
  *    allocates, frees or keeps them.  Work is enqueued on the caller's
  *    stream.  Solver calls return after that stream has reached the end of
- *    the solve (the stopping test reads one residual per cycle).
+ *    the solve (the stopping test reads one residual per cycle), except
+ *    FP64 forward solves with mg_opts.no_sync = 1, which only enqueue.
  *  - Arguments are validated before the first GPU call; invalid ones give
  *    MG_ERR_ARG and mg_last_error() says which.  Positive status codes mean
  *    the outputs are valid (see the stats); negative codes leave outputs
@@ -103,6 +104,22 @@ typedef struct {
                          it; half the bytes of the caller's array).  phi and every
                          other array stay FP64.  The PM steps ignore it (their
                          density is their own FP64 delta_out). */
+    int no_sync;      /* 0: the call waits for the stream (residual read per cycle).
+                         1: enqueue only, for callers that capture the solve in a HIP
+                         graph or pipeline it behind other work: needs tol = 0,
+                         profile = 0 and MG_FP64 (mg_solve_dgp, _noalloc, _newton,
+                         _kmouflage, _poisson; the adjoint and the PM steps reject it).
+                         The call enqueues the same kernels as a tol = 0 solve of
+                         max_cycles cycles (initial residual, the cycles, final
+                         residual, zero-mean gauge, output) and returns
+                         MG_NOT_CONVERGED without waiting; it runs every cycle even if
+                         a residual reaches 0.  Nothing is read back: stats.cycles is
+                         max_cycles, eps0, eps and lambda are NaN, eps_hist is unset,
+                         n_clamped is -1, and non-finite or diverging residuals are
+                         not detected.  The launches record no hipMemsetAsync, the
+                         call allocates nothing and creates no HIP event (a solve of
+                         the same instantiation should have run once before a
+                         capture: the first tail launch sets a kernel attribute). */
 } mg_opts;
 
 #define MG_HIST 64

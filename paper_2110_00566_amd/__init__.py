@@ -51,7 +51,7 @@ class Opts(C.Structure):
     _fields_ = [("n", C.c_int), ("max_cycles", C.c_int), ("tol", C.c_double),
                 ("nu_pre", C.c_int), ("nu_post", C.c_int), ("nu_coarse", C.c_int),
                 ("precision", C.c_int), ("cycle", C.c_int), ("profile", C.c_int),
-                ("delta_fp32", C.c_int)]
+                ("delta_fp32", C.c_int), ("no_sync", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -229,9 +229,11 @@ def workspace(n: int, model: int = MODEL_DGP, adjoint: bool = False, device=None
 
 
 def make_opts(n, tol=1e-8, max_cycles=50, nu_pre=1, nu_post=1, nu_coarse=32, profile=False,
-              precision=MG_FP64, cycle=CYCLE_V, delta_fp32=False):
+              precision=MG_FP64, cycle=CYCLE_V, delta_fp32=False, no_sync=False):
+    """mg_opts.  no_sync: enqueue the solve without waiting (tol = 0, FP64;
+    the call can be captured in a HIP graph)."""
     return Opts(n, max_cycles, tol, nu_pre, nu_post, nu_coarse, precision, cycle, int(profile),
-                int(delta_fp32))
+                int(delta_fp32), int(no_sync))
 
 
 def dgp_params(a=1.0, omega_m=OMEGA_M, h0rc=1.0):

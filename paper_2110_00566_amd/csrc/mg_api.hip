@@ -104,6 +104,8 @@ struct Ctx {
     double kappa = 6.0;
     int adj_model = MODEL_DGP;   // model of the adjoint's Jacobian (tiled kernel dispatch)
     bool profile = false;
+    // enqueue only (mg_opts.no_sync): no scalar is read back, nothing waits
+    bool no_sync = false;
     std::vector<hipEvent_t> ev;
     int ev_used = 0;
     double pass_ms = 0.0;
@@ -463,6 +465,9 @@ mg_status check_opts(const mg_opts *o) {
         return fail(MG_ERR_ARG, "opts.cycle must be MG_CYCLE_V, MG_CYCLE_F or MG_CYCLE_W");
     if (o->delta_fp32 != 0 && o->delta_fp32 != 1)
         return fail(MG_ERR_ARG, "opts.delta_fp32 must be 0 (FP64 delta) or 1 (FP32 delta)");
+    if (o->no_sync != 0 && o->no_sync != 1) return fail(MG_ERR_ARG, "opts.no_sync must be 0 or 1");
+    if (o->no_sync && (o->tol != 0.0 || o->profile || o->precision != MG_FP64))
+        return fail(MG_ERR_ARG, "opts.no_sync = 1 needs tol = 0, profile = 0 and MG_FP64");
     return MG_OK;
 }
 
@@ -793,6 +798,19 @@ struct Solver {
     // residual evaluation (eps is then the last in-cycle residual).
     mg_status run(double tol, int max_cycles, double stall, mg_stats *st, int hist0,
                   PhaseResult &pr, double eps_in = -1.0, bool confirm_stall = true) {
+        if (C.no_sync) {
+            // enqueue only (tol = 0): the launches of the synchronous solve
+            // below for tol = 0 -- initial residual, max_cycles cycles, final
+            // residual -- in the same order, with no scalar read back
+            if (eps_in < 0.0) resid_restrict(0);
+            for (int c = 0; c < max_cycles; ++c) cycle(0, C.cycle);
+            if (max_cycles > 0) resid_restrict(0);
+            pr.status = MG_NOT_CONVERGED;
+            pr.cycles = max_cycles;
+            pr.eps0 = pr.eps = NAN;
+            st->lambda = NAN;
+            return MG_OK;
+        }
         double hs[S_NSCAL] = {};
         mg_status rc;
         double eps = eps_in;
@@ -905,6 +923,12 @@ mg_status finish(Ctx &C, mg_status status, mg_stats *st,
                  std::chrono::steady_clock::time_point t0) {
     unsigned long long ncl = 0;
     HIPCHK(hipGetLastError());
+    if (C.no_sync) {   // everything is enqueued; the clamp count is not read
+        st->n_clamped = -1;
+        st->status = status;
+        st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return status;
+    }
     HIPCHK(hipMemcpyAsync(&ncl, C.clamp, sizeof(ncl), hipMemcpyDeviceToHost, C.st));
     HIPCHK(hipStreamSynchronize(C.st));
     st->n_clamped = (long long)ncl;
@@ -1067,8 +1091,9 @@ mg_status forward_solve(const mg_opts *o, const Mod &M, const void *delta_p, dou
     C.nu2 = o->nu_post;
     C.nuc = o->nu_coarse;
     C.cycle = o->cycle;
+    C.no_sync = o->no_sync != 0;
     Profiler prof(C, o->profile != 0 && !noalloc, 2 * (o->nu_pre + o->nu_post) + 2);
-    if (!noalloc) arm_early_read(C);
+    if (!noalloc && !C.no_sync) arm_early_read(C);
     reset_scalars(C);
     if (o->precision == MG_FP32) return fp32_solve<OP>(o, C, delta, phi, st, t0);
     HLevel<double> &F = C.h64.lv[0];
@@ -1454,6 +1479,7 @@ mg_status mg_solve_adjoint(const mg_opts *opts, int model, const void *params,
     mg_status rc = common_checks(opts, delta, phi, ws, stats);
     if (rc != MG_OK) return rc;
     if (opts->precision != MG_FP64) return fail(MG_ERR_ARG, "the adjoint solve is FP64 only");
+    if (opts->no_sync) return fail(MG_ERR_ARG, "the adjoint solve waits for its stream: opts.no_sync must be 0");
     if (opts->cycle != MG_CYCLE_V) return fail(MG_ERR_ARG, "the adjoint solve uses V-cycles only");
     if (model == MG_MODEL_DGP_NEWTON) return fail(MG_ERR_ARG, "no adjoint for the Newton-GS comparator");
     if (!w || !grad_delta || !mu) return fail(MG_ERR_ARG, "w, grad_delta and mu must be device pointers");

@@ -480,6 +480,8 @@ mg_status mg_pm_step(const mg_pm_params *par, float *pos, float *mom, double *ph
     const int n = par->n_mesh;
     if (!pow2(n) || n < 8 || n > 2048 || par->mg.n != n)
         return fail(MG_ERR_ARG, "n_mesh must be a power of two in [8, 2048] equal to mg.n");
+    if (par->mg.no_sync)
+        return fail(MG_ERR_ARG, "the PM steps wait for their phases: mg.no_sync must be 0");
     if (par->n_part < 1 || par->n_part > 2048 || !(par->a > 0.0) || !std::isfinite(par->da) ||
         !(par->omega_m > 0.0) || !(par->omega_m < 1.0))
         return fail(MG_ERR_ARG, "invalid n_part, a, da or omega_m");
@@ -538,6 +540,8 @@ mg_status mg_pm_step_kmouflage(const mg_pm_kmo_params *par, float *pos, float *m
     const int n = par->n_mesh;
     if (!pow2(n) || n < 8 || n > 2048 || par->mg.n != n)
         return fail(MG_ERR_ARG, "n_mesh must be a power of two in [8, 2048] equal to mg.n");
+    if (par->mg.no_sync)
+        return fail(MG_ERR_ARG, "the PM steps wait for their phases: mg.no_sync must be 0");
     if (par->n_part < 1 || par->n_part > 2048 || !(par->a > 0.0) || !(par->da >= 0.0) ||
         !std::isfinite(par->da) || !(par->a + 0.5 * par->da <= 1.0) || !(par->box_mpch > 0.0) ||
         !std::isfinite(par->box_mpch))

@@ -108,6 +108,19 @@ int main() {
                            kneed, nullptr, &st) == MG_ERR_ARG);
     mg_poisson_params pp{NAN};
     CHECK(mg_solve_poisson(&o, &pp, fake, fake, ws_aligned, 1 << 30, nullptr, &st) == MG_ERR_ARG);
+    // enqueue-only solves: tol = 0, no profiling, FP64; not for the adjoint
+    mg_opts ons = o;
+    ons.no_sync = 1;   // with tol > 0
+    CHECK(mg_solve_dgp(&ons, &dp, fake, fake, ws_aligned, 1 << 30, nullptr, &st) == MG_ERR_ARG);
+    ons.tol = 0.0;
+    ons.precision = MG_MIXED;
+    CHECK(mg_solve_dgp(&ons, &dp, fake, fake, ws_aligned, 1 << 30, nullptr, &st) == MG_ERR_ARG);
+    ons.precision = MG_FP64;
+    ons.no_sync = 3;
+    CHECK(mg_solve_dgp(&ons, &dp, fake, fake, ws_aligned, 1 << 30, nullptr, &st) == MG_ERR_ARG);
+    ons.no_sync = 1;
+    CHECK(mg_solve_adjoint(&ons, MG_MODEL_DGP, &dp, fake, fake, fake, fake, fake, ws_aligned,
+                           kneed, nullptr, &st) == MG_ERR_ARG);
 
     // single operations
     CHECK(mg_op_residual(MG_MODEL_DGP, &dp, 6, 1.0, fake, fake, nullptr, 0.0, fake, ws_aligned,

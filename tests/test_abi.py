@@ -317,3 +317,31 @@ def test_delta_precision_flag_validated(L):
     assert L.mg_solve_dgp(C.byref(o), C.byref(mg.dgp_params()), d, d, d, 1 << 40, None,
                           C.byref(st)) == mg.MG_ERR_ARG
     assert b"delta_fp32" in L.mg_last_error()
+
+
+def test_no_sync_flag_validated(L):
+    # enqueue-only solves need tol = 0, profile = 0 and FP64; the adjoint and
+    # the PM steps wait for their stream and refuse the flag
+    d = C.c_void_p(0x1000)
+    st = mg.Stats()
+    par = mg.dgp_params()
+    for over in (dict(no_sync=2), dict(no_sync=1), dict(no_sync=1, tol=0.0, profile=1),
+                 dict(no_sync=1, tol=0.0, precision=mg.MG_MIXED),
+                 dict(no_sync=1, tol=0.0, precision=mg.MG_FP32)):
+        o = mg.make_opts(32)
+        for k, v in over.items():
+            setattr(o, k, v)
+        assert L.mg_solve_dgp(C.byref(o), C.byref(par), d, d, d, 1 << 40, None,
+                              C.byref(st)) == mg.MG_ERR_ARG, over
+        assert b"no_sync" in L.mg_last_error()
+    o = mg.make_opts(32, tol=0.0, no_sync=True)
+    assert L.mg_solve_adjoint(C.byref(o), mg.MODEL_DGP, C.byref(par), d, d, d, d, d, d, 1 << 40,
+                              None, C.byref(st)) == mg.MG_ERR_ARG
+    assert b"no_sync" in L.mg_last_error()
+    pm = mg.PmParams(32, 16, 0.3089, 1.0, 1.0, 0.01, o)
+    assert L.mg_pm_step(C.byref(pm), d, d, d, d, d, d, 1 << 40, None, C.byref(st)) == mg.MG_ERR_ARG
+    assert b"no_sync" in L.mg_last_error()
+    kp = mg.PmKmoParams(32, 16, 0.5, 0.01, 64.0, mg.kmo_bg_params(2, 1.0, 0.2), None, o)
+    assert L.mg_pm_step_kmouflage(C.byref(kp), d, d, d, d, d, d, 1 << 40, None,
+                                  C.byref(st)) == mg.MG_ERR_ARG
+    assert b"no_sync" in L.mg_last_error()
