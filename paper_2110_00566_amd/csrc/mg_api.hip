@@ -594,6 +594,17 @@ struct Solver {
         }
     }
 
+    // mu from a sample of the finest residual before a call's first full
+    // evaluation (k_mu_estimate); the adjoint's finest right-hand side is
+    // an array and needs none
+    void seed_mu() {
+        if constexpr (!ADJ) {
+            HLevel<R> &F = Hh.lv[0];
+            k_mu_estimate<OP, R><<<1, 64, 0, C.st>>>(C.M, view(F, false), coefs(F),
+                                                     C.scal + S_MU);
+        }
+    }
+
     void coarse_source(int lc) {
         HLevel<R> &Hc = Hh.lv[lc];
         LvlT<R> L = view(Hc, false);
@@ -802,7 +813,10 @@ struct Solver {
             // enqueue only (tol = 0): the launches of the synchronous solve
             // below for tol = 0 -- initial residual, max_cycles cycles, final
             // residual -- in the same order, with no scalar read back
-            if (eps_in < 0.0) resid_restrict(0);
+            if (eps_in < 0.0) {
+                seed_mu();
+                resid_restrict(0);
+            }
             for (int c = 0; c < max_cycles; ++c) cycle(0, C.cycle);
             if (max_cycles > 0) resid_restrict(0);
             pr.status = MG_NOT_CONVERGED;
@@ -815,6 +829,7 @@ struct Solver {
         mg_status rc;
         double eps = eps_in;
         if (eps_in < 0.0) {
+            seed_mu();
             resid_restrict(0);
             if ((rc = read_scal(hs)) != MG_OK) return rc;
             eps = std::sqrt(hs[S_EPS2]);

@@ -230,6 +230,30 @@ __global__ __launch_bounds__(TPB) void k_resid_restrict(Mod M, LvlT<R> L, Coefs 
     if (REDUCE) block_sum2(s1, s2, partials, blk);
 }
 
+// Starting value of the finest level's bordering scalar mu: the mean of
+// L(phi) - f over 64 cells spread over the mesh (one wave).  The finest
+// residual is reduced in one pass, eps^2 = <d^2> - <d>^2, which cancels when
+// |<d>| is many orders above eps.  A call's first residual evaluation would
+// otherwise see mu = 0 and <d> = the whole mean of L(phi); started from this
+// estimate, its <d> is of the order of the residual's spread, and its update
+// mu += <d> gives the mean over all cells as before.
+template <int OP, typename R>
+__global__ __launch_bounds__(64) void k_mu_estimate(Mod M, LvlT<R> L, Coefs Cf, double *mu) {
+    const int t = threadIdx.x;
+    const int c = t & 1;
+    const int m = (t * 5) & ((L.n >> 1) - 1);
+    const int j = (t * 7 + 1) & (L.n - 1);
+    const int k = (t * 11 + 2) & (L.n - 1);
+    double faces;
+    double term = cell_term<OP, double, R>(M, L, Cf, c, m, j, k, faces, nullptr);
+    const size_t idx = prow(j, k, L.logn, L.lognh) + m;
+    const double D = (faces - 6.0 * (double)(c ? L.u1 : L.u0)[idx]) / L.h2;
+    if constexpr (OP == OP_NEWTON) term = newton_term(M, term, D);
+    double d = D - term - rhs_at<double, R>(L, c, idx, nullptr, 0.0);
+    for (int off = 32; off > 0; off >>= 1) d += __shfl_down(d, off, 64);
+    if (t == 0) *mu = d * (1.0 / 64.0);
+}
+
 // FAS source on the coarse level: S = L^H(R u) - (R d - shift), written over
 // the restricted residual; the coarse unknown starts from R u.
 template <int OP, typename R>

@@ -392,8 +392,9 @@ __global__ __launch_bounds__(TPB) void k_resid_restrict_tiled(Mod M, LvlT<R> L, 
             const double u = (double)A0[r * TXH + q];
             const double f = (HASF ? (double)fv : 0.0) + fs;
             double d;
-            if constexpr (sizeof(R) == 4 && OP == OP_DGP) {
-                // FP32 storage: the Laplacian in double, the nDGP term in float
+            if constexpr (sizeof(R) == 4 && (OP == OP_DGP || OP == OP_KMO)) {
+                // FP32 storage: the Laplacian in double, the model term in
+                // float (nDGP) or from float stencil combinations (Kmouflage)
                 const NbT<float> s = lds_nb<float, R>(Am, A0, Ap, B0, Bm, Bp, r, q, p);
                 const double faces = ((double)s.xp + (double)s.xm) +
                                      ((double)s.yp + (double)s.ym) +

@@ -751,3 +751,30 @@ def test_zero_source_and_zero_cycles(n):
     phi, st = mg.solve_dgp(g(inputs.lognormal_delta(n, 9)), g(phi0), tol=1e-8, max_cycles=0)
     assert st["cycles"] == 0 and st["status"] == mg.MG_NOT_CONVERGED
     assert np.abs(c(phi) - (phi0 - phi0.mean())).max() <= 1e-14 * np.abs(phi0).max()
+
+
+@pytest.mark.parametrize("name,n", [("dgp", 64), ("dgp", 128), ("dgp_h05", 64)])
+def test_warm_start_residual_is_free_of_cancellation(name, n):
+    # a field within ~1e-11 of the solution, whose residual has a mean (the
+    # Lagrange multiplier) many orders larger: the first residual of the call
+    # must still equal the oracle's mean-projected RMS (the one-pass variance
+    # of the reduction would otherwise cancel), and a tol = 0 call from the
+    # converged field itself must run every cycle
+    gp, om = models(n)[name]
+    fn = mg.lib().mg_solve_dgp
+    delta = inputs.lognormal_delta(n, 17)
+    star, st = mg._solve(fn, gp, 0, g(delta), None, None, tol=1e-12, max_cycles=60)
+    assert st["status"] == 0
+    x = np.arange(n) * (2.0 * np.pi / n)
+    pert = 1e-9 * np.sin(x)[None, None, :] * np.cos(2.0 * x)[None, :, None]
+    phi0 = c(star) + pert
+    Lr = oracle.residual(om, phi0, delta)
+    eps_oracle = float(np.sqrt(np.mean((Lr - Lr.mean()) ** 2)))
+    _, st0 = mg._solve(fn, gp, 0, g(delta), g(phi0), None, tol=0.0, max_cycles=0)
+    print("\n%s %d^3: |lambda| %.3e, eps0 GPU %.6e, oracle %.6e"
+          % (name, n, abs(st["lam"]), st0["eps0"], eps_oracle))
+    assert abs(st["lam"]) > 1e6 * eps_oracle
+    assert st0["eps0"] == pytest.approx(eps_oracle, rel=1e-3)
+    _, st1 = mg._solve(fn, gp, 0, g(delta), star, None, tol=0.0, max_cycles=3)
+    assert st1["status"] == mg.MG_NOT_CONVERGED and st1["cycles"] == 3
+    assert 0.0 < st1["eps0"] < 1e-10
