@@ -558,8 +558,11 @@ __attribute__((amdgpu_waves_per_eu(OP == OP_KMO ? 3 : 1))) void k_prolong_pass_t
     constexpr int CH = TY / 2 + 2;       // coarse rows j0/2-1 .. j0/2+4
     constexpr int CPL = CW * CH;
     constexpr int CLOADS = (CPL + TPB - 1) / TPB;
+    // arithmetic type of the coarse correction: that of the storage (in FP32
+    // storage the correction, small beside phi, needs no FP64)
+    using CT = R;
     __shared__ R sA[3][TPLANE], sB[3][TPLANE];
-    __shared__ double sC[CPL];
+    __shared__ CT sC[CPL];
     const size_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int bx = (int)(blk % G.ntx);
     const int by = (int)((blk / G.ntx) % G.nty);
@@ -570,7 +573,7 @@ __attribute__((amdgpu_waves_per_eu(OP == OP_KMO ? 3 : 1))) void k_prolong_pass_t
     const R fs = (R)(fptr ? fscale * (*fptr) : 0.0);
 
     // coarse difference uc - rc of one coarse plane, via registers into sC
-    double cu[CLOADS], cr[CLOADS];
+    CT cu[CLOADS], cr[CLOADS];
     auto cfetch = [&](int Z) {
         const int Zw = Z & ncm1;
 #pragma unroll
@@ -583,8 +586,8 @@ __attribute__((amdgpu_waves_per_eu(OP == OP_KMO ? 3 : 1))) void k_prolong_pass_t
                 const size_t idx =
                     ((size_t)Zw << (2 * lnc - 1)) + ((size_t)Y << (lnc - 1)) + (X >> 1);
                 const bool odd = (X + Y + Zw) & 1;
-                cu[q] = (double)(odd ? uc1 : uc0)[idx];
-                cr[q] = (double)(odd ? rc1 : rc0)[idx];
+                cu[q] = (odd ? uc1 : uc0)[idx];
+                cr[q] = (odd ? rc1 : rc0)[idx];
             }
         }
     };
@@ -598,8 +601,8 @@ __attribute__((amdgpu_waves_per_eu(OP == OP_KMO ? 3 : 1))) void k_prolong_pass_t
     // x-y bilinear part of the coarse plane in sC at the thread's staged
     // positions, for fine x = 2m (index 0, coarse neighbour m-1) and
     // x = 2m+1 (index 1, coarse neighbour m+1)
-    double xlo[TLOADS][2], xhi[TLOADS][2], xnx[TLOADS][2];
-    auto interp = [&](double (&x)[TLOADS][2]) {
+    CT xlo[TLOADS][2], xhi[TLOADS][2], xnx[TLOADS][2];
+    auto interp = [&](CT (&x)[TLOADS][2]) {
 #pragma unroll
         for (int q = 0; q < TLOADS; ++q) {
             const int e = tid + q * TPB;
@@ -607,14 +610,14 @@ __attribute__((amdgpu_waves_per_eu(OP == OP_KMO ? 3 : 1))) void k_prolong_pass_t
                 const int r = e / TXH, cI = e - r * TXH;
                 const int lr = (r + 1) >> 1, lc = cI + 1;
                 const int ly = (r & 1) ? lr - 1 : lr + 1;   // fine row odd: coarse row above
-                const double c0 = sC[lr * CW + lc], cm = sC[lr * CW + lc - 1],
-                             cp = sC[lr * CW + lc + 1];
-                const double d0 = sC[ly * CW + lc], dm = sC[ly * CW + lc - 1],
-                             dp = sC[ly * CW + lc + 1];
-                x[q][0] = (9.0 / 16.0) * c0 + (3.0 / 16.0) * cm + (3.0 / 16.0) * d0 +
-                          (1.0 / 16.0) * dm;
-                x[q][1] = (9.0 / 16.0) * c0 + (3.0 / 16.0) * cp + (3.0 / 16.0) * d0 +
-                          (1.0 / 16.0) * dp;
+                const CT c0 = sC[lr * CW + lc], cm = sC[lr * CW + lc - 1],
+                         cp = sC[lr * CW + lc + 1];
+                const CT d0 = sC[ly * CW + lc], dm = sC[ly * CW + lc - 1],
+                         dp = sC[ly * CW + lc + 1];
+                x[q][0] = (CT)(9.0 / 16.0) * c0 + (CT)(3.0 / 16.0) * cm +
+                          (CT)(3.0 / 16.0) * d0 + (CT)(1.0 / 16.0) * dm;
+                x[q][1] = (CT)(9.0 / 16.0) * c0 + (CT)(3.0 / 16.0) * cp +
+                          (CT)(3.0 / 16.0) * d0 + (CT)(1.0 / 16.0) * dp;
             }
         }
     };
@@ -639,17 +642,17 @@ __attribute__((amdgpu_waves_per_eu(OP == OP_KMO ? 3 : 1))) void k_prolong_pass_t
     // corrected plane k into ring slot; the coarse pair (lo, hi) holds the
     // plane's own coarse plane (hi for even k, lo for odd k) and its neighbour
     auto stage = [&](int slot, int k, bool kodd) {
-        const double wl = kodd ? 0.75 : 0.25, wh = kodd ? 0.25 : 0.75;
+        const CT wl = kodd ? (CT)0.75 : (CT)0.25, wh = kodd ? (CT)0.25 : (CT)0.75;
 #pragma unroll
         for (int q = 0; q < TLOADS; ++q) {
             const int e = tid + q * TPB;
             if (e < TPLANE) {
                 const int r = e / TXH;
                 const bool p0 = (j0 - 1 + r + k) & 1;   // x parity of the colour-0 value
-                const double l0 = p0 ? xlo[q][1] : xlo[q][0], l1 = p0 ? xlo[q][0] : xlo[q][1];
-                const double h0 = p0 ? xhi[q][1] : xhi[q][0], h1 = p0 ? xhi[q][0] : xhi[q][1];
-                sA[slot][e] = (R)((double)ra[q] + (wl * l0 + wh * h0));
-                sB[slot][e] = (R)((double)rb[q] + (wl * l1 + wh * h1));
+                const CT l0 = p0 ? xlo[q][1] : xlo[q][0], l1 = p0 ? xlo[q][0] : xlo[q][1];
+                const CT h0 = p0 ? xhi[q][1] : xhi[q][0], h1 = p0 ? xhi[q][0] : xhi[q][1];
+                sA[slot][e] = ra[q] + (wl * l0 + wh * h0);
+                sB[slot][e] = rb[q] + (wl * l1 + wh * h1);
             }
         }
     };
