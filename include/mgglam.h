@@ -318,8 +318,9 @@ mg_status mg_fft_poisson(int n, double s, const double *delta, double *phi, void
 /* One nDGP particle-mesh step (Sec. 3.1): CIC density from the particles,
  * Newtonian potential (eq:GR_poisson_codeunit, by mg_fft_poisson; phi_newton
  * is overwritten), scalar field (warm start from
- * phi), total potential Phi_N + phi/2 (eq:poisson_nDGP), 3-point force
- * interpolated with CIC, kick dp/da = -(H0/adot) grad Phi at a, drift
+ * phi), total potential Phi_N + phi/2 (eq:poisson_nDGP), 3-point force on
+ * the mesh (computed in FP64, kept in FP32 in the workspace) interpolated
+ * with CIC, kick dp/da = -(H0/adot) grad Phi at a, drift
  * dx/da = (H0/adot) p / a^2 at a + da/2.  pos in [0, n_mesh) is wrapped.
  * phi_newton and delta_out are 16-byte aligned (MG_ERR_ARG otherwise). */
 typedef struct {

@@ -236,34 +236,74 @@ __global__ void k_zero_u64(unsigned long long *a, size_t n) {
     if (t < n) a[t] = 0ull;
 }
 
-// Total potential psi = Phi_N + cphi phi on the mesh (nDGP: cphi = 1/2;
-// Kmouflage: cphi = beta c~), formed once so that the particle kernel
-// gathers one field instead of two.
-__global__ __launch_bounds__(PTPB) void k_total_potential(const double *__restrict__ phin,
-                                                           const double *__restrict__ phi,
-                                                           double cphi, double *__restrict__ psi,
-                                                           size_t ncell) {
-    const size_t t = (size_t)blockIdx.x * PTPB + threadIdx.x;
-    if (t < ncell) psi[t] = phin[t] + cphi * phi[t];
+// Force on the mesh, g = -grad(psi) by 3-point differences of the total
+// potential psi = Phi_N + cphi phi (nDGP: cphi = 1/2; Kmouflage: cphi =
+// beta c~), in FP64 and stored once rounded to FP32 as (gx, gy, gz, 0): the
+// particle kernel then reads one 16-byte value per CIC cell instead of the
+// potential at the six neighbours of each of its eight cells.  A thread owns
+// one (x, y) column and marches fz planes of it, keeping psi of its own cell
+// at k - 1, k and k + 1 in registers; the x and y neighbours at plane k are
+// cells the adjacent threads loaded a step earlier and come from the caches.
+// A block takes PTPB consecutive columns (x fastest) of one z-chunk, and each
+// XCD a contiguous share of the blocks, so that the rows around a block's
+// columns are loaded through the same L2.
+__global__ __launch_bounds__(PTPB) void k_force(const double *__restrict__ phin,
+                                                 const double *__restrict__ phi, double cphi,
+                                                 float4 *__restrict__ force, int logn, int fz) {
+    const int nm1 = (1 << logn) - 1;
+    const size_t ncol = (size_t)1 << (2 * logn);
+    const size_t ncb = (ncol + PTPB - 1) / PTPB;   // column blocks per z-chunk
+    const size_t b = xcd_chunk(blockIdx.x, gridDim.x);
+    const size_t col = (b % ncb) * PTPB + threadIdx.x;
+    const int k0 = (int)(b / ncb) * fz;
+    if (col >= ncol) return;
+    const int i = (int)(col & nm1), j = (int)(col >> logn);
+    auto psi = [&](int a, int bb, int k) {
+        const size_t idx = ((size_t)(k & nm1) << (2 * logn)) + ((size_t)((j + bb) & nm1) << logn) +
+                           ((i + a) & nm1);
+        return phin[idx] + cphi * phi[idx];
+    };
+    double pm = psi(0, 0, k0 - 1), p0 = psi(0, 0, k0);
+    for (int k = k0; k < k0 + fz; ++k) {
+        const double pp = psi(0, 0, k + 1);
+        const double gx = -0.5 * (psi(1, 0, k) - psi(-1, 0, k));
+        const double gy = -0.5 * (psi(0, 1, k) - psi(0, -1, k));
+        const double gz = -0.5 * (pp - pm);
+        force[((size_t)k << (2 * logn)) + col] =
+            make_float4((float)gx, (float)gy, (float)gz, 0.0f);
+        pm = p0;
+        p0 = pp;
+    }
 }
 
-// g = -grad(psi) by 3-point differences at the 8 CIC cells, interpolated
-// with the CIC weights; p = damp p + g kick; x += p drift (periodic).
-// nDGP: damp = 1; Kmouflage: damp = 1 - beta (d phibar/da) da (the velocity
-// term of eq:force_Kmo2).  psi(i, j, k): the potential at corner + (i, j, k),
-// i, j, k in -1 .. 2.
-template <typename PSI>
-__device__ __forceinline__ void kick_particle(float *__restrict__ pos, float *__restrict__ mom,
-                                              size_t t, int n, const double f[3], PSI psi,
-                                              double damp, double kick, double drift) {
+// The mesh force interpolated with the CIC weights of the particle's eight
+// cells; p = damp p + g kick; x += p drift (periodic).  nDGP: damp = 1;
+// Kmouflage: damp = 1 - beta (d phibar/da) da (the velocity term of
+// eq:force_Kmo2).  One thread per particle, blocks in launch order.  (For
+// 512^3 particles on a 1024^3 mesh, gathering the potential at the 3-point
+// stencils of the eight cells -- 48 scattered loads per particle -- took
+// 20 ms, bound by the cache requests.)
+__global__ __launch_bounds__(PTPB) void k_kick_drift(float *__restrict__ pos,
+                                                      float *__restrict__ mom, size_t np, int logn,
+                                                      const float4 *__restrict__ force,
+                                                      double damp, double kick, double drift) {
+    const size_t t = (size_t)blockIdx.x * PTPB + threadIdx.x;
+    if (t >= np) return;
+    const int n = 1 << logn, nm1 = n - 1;
+    double f[3];
+    int i0[3];
+    cic_weights(pos + 3 * t, f, i0);
     double g[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int a = q & 1, b = (q >> 1) & 1, c = q >> 2;
         const double w = ((a ? f[0] : 1.0 - f[0]) * (b ? f[1] : 1.0 - f[1])) * (c ? f[2] : 1.0 - f[2]);
-        g[0] -= w * (psi(a + 1, b, c) - psi(a - 1, b, c)) * 0.5;
-        g[1] -= w * (psi(a, b + 1, c) - psi(a, b - 1, c)) * 0.5;
-        g[2] -= w * (psi(a, b, c + 1) - psi(a, b, c - 1)) * 0.5;
+        const size_t idx = ((size_t)((i0[2] + c) & nm1) << (2 * logn)) +
+                           ((size_t)((i0[1] + b) & nm1) << logn) + ((i0[0] + a) & nm1);
+        const float4 v = force[idx];
+        g[0] += w * (double)v.x;
+        g[1] += w * (double)v.y;
+        g[2] += w * (double)v.z;
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -275,30 +315,6 @@ __device__ __forceinline__ void kick_particle(float *__restrict__ pos, float *__
         mom[3 * t + a] = (float)pn;
         pos[3 * t + a] = xf;
     }
-}
-
-// One thread per particle, blocks in launch order.  (For 512^3 particles on
-// a 1024^3 mesh: a variant that staged the potential of a CIC tile in LDS and
-// walked the deposit's particle lists took about 21 against 20 ms; giving
-// each XCD a contiguous eighth of the blocks cut the HBM fetch from 127 to
-// 50 GB but took 22 ms.  The kick is bound by the cache requests of its 48
-// scattered loads per particle.)
-__global__ __launch_bounds__(PTPB) void k_kick_drift(float *__restrict__ pos,
-                                                      float *__restrict__ mom, size_t np, int logn,
-                                                      const double *__restrict__ psi_mesh,
-                                                      double damp, double kick, double drift) {
-    const size_t t = (size_t)blockIdx.x * PTPB + threadIdx.x;
-    if (t >= np) return;
-    const int n = 1 << logn, nm1 = n - 1;
-    double f[3];
-    int i0[3];
-    cic_weights(pos + 3 * t, f, i0);
-    auto psi = [&](int i, int j, int k) {
-        const size_t idx = ((size_t)((i0[2] + k) & nm1) << (2 * logn)) +
-                           ((size_t)((i0[1] + j) & nm1) << logn) + ((i0[0] + i) & nm1);
-        return psi_mesh[idx];
-    };
-    kick_particle(pos, mom, t, n, f, psi, damp, kick, drift);
 }
 
 unsigned nb(size_t threads) { return (unsigned)((threads + PTPB - 1) / PTPB); }
@@ -345,16 +361,19 @@ mg_status cic(int n_mesh, int n_part, const float *pos, T *delta, unsigned long 
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Total potential psi = Phi_N + cphi phi (written over the CIC workspace,
-// free again), then kick and drift of every particle.
+// Mesh force (FP32, 16 bytes per cell, written from the start of the step's
+// workspace: the CIC area and the solver workspace behind it are free once
+// both potentials are solved), then kick and drift of every particle.
 void potential_kick_drift(int n, int n_part, float *pos, float *mom, const double *phi_newton,
-                          const double *phi, double cphi, unsigned long long *counts,
-                          double damp, double kick, double drift, hipStream_t stream) {
-    const size_t ncell = (size_t)n * n * n;
+                          const double *phi, double cphi, void *ws, double damp, double kick,
+                          double drift, hipStream_t stream) {
     const size_t np = (size_t)n_part * n_part * n_part;
-    double *psi = reinterpret_cast<double *>(counts);
-    k_total_potential<<<nb(ncell), PTPB, 0, stream>>>(phi_newton, phi, cphi, psi, ncell);
-    k_kick_drift<<<nb(np), PTPB, 0, stream>>>(pos, mom, np, ilog2(n), psi, damp, kick, drift);
+    float4 *force = static_cast<float4 *>(ws);
+    const int fz = n < 32 ? n : 32;   // planes per block
+    const size_t ncb = ((size_t)n * n + PTPB - 1) / PTPB;
+    k_force<<<(unsigned)(ncb * (size_t)(n / fz)), PTPB, 0, stream>>>(phi_newton, phi, cphi, force,
+                                                                     ilog2(n), fz);
+    k_kick_drift<<<nb(np), PTPB, 0, stream>>>(pos, mom, np, ilog2(n), force, damp, kick, drift);
 }
 
 // GPU time of the phases of a PM step (CIC, Newtonian potential, scalar
