@@ -322,7 +322,8 @@ def solve_dgp(delta, phi0=None, a=1.0, omega_m=OMEGA_M, h0rc=1.0, ws=None, **kw)
     """nDGP field (eq:dgp_eom_code); returns (zero-mean phi, stats).
     Keywords: tol, max_cycles, nu_pre, nu_post, nu_coarse, profile,
     precision (MG_FP64, MG_MIXED, MG_FP32 or MG_MIXED_DC), cycle (CYCLE_V, CYCLE_F or
-    CYCLE_W)."""
+    CYCLE_W), no_sync (tol = 0, FP64: the call only enqueues the fixed cycles on the
+    current stream; the stats carry no residuals)."""
     return _solve(lib().mg_solve_dgp, dgp_params(a, omega_m, h0rc), MODEL_DGP, delta, phi0, ws, **kw)
 
 
