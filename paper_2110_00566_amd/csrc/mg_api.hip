@@ -283,16 +283,18 @@ bool tiled_level(int n) { return n >= 128; }
 // The tiled kernels implement the closed-form update only.
 constexpr bool tiled_op(int OP) { return OP != OP_ADJ; }
 
-// z-planes per block: the deepest chunk (4 .. 128 planes) that still gives a
-// launch at least 4096 blocks.  Deeper chunks re-read fewer z-halo planes;
+// z-planes per block: the deepest chunk (4 .. kzmax planes) that still gives
+// a launch at least 4096 blocks.  Deeper chunks re-read fewer z-halo planes;
 // at 1024^3 (128 planes, 8192 blocks per pass) the V-cycle is 1% faster than
-// with 64.
-TileGeom tile_geom(int n, int planes) {
+// with 64.  Kernels whose chunks count coarse planes (two fine planes each)
+// keep at most 64: the 1024^3 residual + restriction took 4.43 ms with 128
+// (4096 blocks) against 4.31 ms with 64.
+TileGeom tile_geom(int n, int planes, int kzmax = 128) {
     TileGeom G;
     G.ntx = (n / 2) / TX;
     G.nty = n / TY;
     const long per = (long)G.ntx * G.nty;
-    int kz = 128;
+    int kz = kzmax;
     while (kz > 4 && (long)planes * per / kz < 4096) kz >>= 1;
     while (planes % kz) kz >>= 1;
     G.kz = kz;
@@ -323,7 +325,7 @@ unsigned launch_resid_restrict(const Mod &M, const LvlT<R> &L, const Coefs &Cf, 
                                double fs, R *ru0, R *ru1, R *rd0, R *rd1, double *partials,
                                unsigned long long *clamp, hipStream_t st) {
     if (tiled_op(OP) && tiled_level(L.n)) {
-        const TileGeom G = tile_geom(L.n, L.n / 2);
+        const TileGeom G = tile_geom(L.n, L.n / 2, 64);
         const unsigned nb = tile_blocks(G, L.n / 2);
         if (L.f0)
             k_resid_restrict_tiled<fwd_op(OP), REDUCE, true, R><<<nb, TPB, 0, st>>>(
@@ -345,7 +347,7 @@ void launch_prolong(R *f0, R *f1, int logn, const R *uc0, const R *uc1, const R 
                     const R *rc1, hipStream_t st) {
     const int n = 1 << logn;
     if (tiled_level(n)) {
-        const TileGeom G = tile_geom(n, n / 2);
+        const TileGeom G = tile_geom(n, n / 2, 64);
         k_prolong_tiled<R><<<tile_blocks(G, n / 2), TPB, 0, st>>>(f0, f1, logn, uc0, uc1, rc0, rc1,
                                                                  G);
     } else {
@@ -388,7 +390,7 @@ template <int MODE, bool REDUCE>
 unsigned launch_adj_tiled(int model, const AdjLevel &A, int c, double *out, double *out2,
                           const double *fptr, double fscale, double *ru0, double *ru1,
                           double *rd0, double *rd1, double *partials, hipStream_t st) {
-    const TileGeom G = tile_geom(A.n, A.n);
+    const TileGeom G = tile_geom(A.n, A.n, 64);
     const unsigned nb = tile_blocks(G, A.n);
     switch (model) {
         case MODEL_KMO:
@@ -638,7 +640,7 @@ struct Solver {
         HLevel<R> &H = Hh.lv[l], &Hc = Hh.lv[l + 1];
         if (l == 0 && adj_tiled(0)) {
             // the colour sums of the corrected finest field
-            const TileGeom G = tile_geom(H.n, H.n / 2);
+            const TileGeom G = tile_geom(H.n, H.n / 2, 64);
             const unsigned nb = tile_blocks(G, H.n / 2);
             k_prolong_tiled<R, true><<<nb, TPB, 0, C.st>>>(H.u[0], H.u[1], H.logn, Hc.u[0],
                                                           Hc.u[1], Hc.ru[0], Hc.ru[1], G,
@@ -1012,7 +1014,7 @@ mg_status dc_finish(const mg_opts *o, Ctx &C, DeltaIn delta, double *phi, mg_sta
         k_zero_f32<<<nblocks(G.half), TPB, 0, C.st>>>(G.u[c], G.half);
     }
     Solver<OP, double> S64(C);
-    const TileGeom Gf = tile_geom(F.n, F.n), Gr = tile_geom(F.n, F.n / 2);
+    const TileGeom Gf = tile_geom(F.n, F.n), Gr = tile_geom(F.n, F.n / 2, 64);
     const unsigned nbf = tile_blocks(Gf, F.n), nbr = tile_blocks(Gr, F.n / 2);
     auto corr_pass = [&](int c) {
         k_corr_pass_tiled<MODEL><<<nbf, TPB, 0, C.st>>>(C.M, view(G, true), G.pb[0], G.pb[1], c,
