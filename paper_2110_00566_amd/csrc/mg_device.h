@@ -147,6 +147,19 @@ __device__ __forceinline__ T model_term(const Mod &M, const L_ &L, const NbT<T> 
     //     = [e_x^2 (2A_x-A_y-A_z) + ...]/(12 h^4) + (N_xy e_x e_y + ...)/(8 h^4),
     //   K = (src delta + b2 g^(n-2) Q) / (c~ (c0 + a1 g^(n-1))).
     const T ex = s.xp - s.xm, ey = s.yp - s.ym, ez = s.zp - s.zm;
+    if constexpr (sizeof(T) == 4) {
+        // FP32 storage: the whole term in FP32 (its relative error stays far
+        // below that of the FP32-stored field)
+        const float g = (ex * ex + ey * ey + ez * ez) * (float)L.c4h2;
+        const float q = (ex * ex * (2 * ax - ay - az) + ey * ey * (2 * ay - ax - az)
+                         + ez * ez * (2 * az - ax - ay)) * (float)L.c12h4
+                      + (s.nxy * ex * ey + s.nxz * ex * ez + s.nyz * ey * ez) * (float)L.c8h4;
+        float gn2 = 1.0f;
+        for (int t = 0; t < M.nk - 2; ++t) gn2 *= g;
+        const float sig1 = (float)M.c0 + (float)M.a1 * gn2 * g;
+        const float sig2 = (float)M.b2 * gn2 * q;
+        return ((float)M.src * delta + sig2) / ((float)M.ctil * sig1);
+    }
     const double g = (double)(ex * ex + ey * ey + ez * ez) * L.c4h2;
     const double q = (double)(ex * ex * (2 * ax - ay - az) + ey * ey * (2 * ay - ax - az)
                               + ez * ez * (2 * az - ax - ay)) * L.c12h4
